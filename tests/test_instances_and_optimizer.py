@@ -1,0 +1,78 @@
+"""Seeded input generator checks and the optimizer oracle's properties (CPU)."""
+import numpy as np
+import pytest
+
+from oracle.cost import cost_table, count_solutions_enum, level_histogram
+from oracle.evolve import psol_single_pair_hist
+from oracle.optimize import optimize_single_pair, single_pair_grid
+from paper_2402_02585_amd import instances as inst
+
+
+def test_generator_shape_and_rules():
+    rng = np.random.Generator(np.random.PCG64(0))
+    lits = inst.random_3sat(rng, 10, 42)
+    assert lits.shape == (42, 3) and lits.dtype == np.int32
+    var = lits >> 1
+    assert (var >= 0).all() and (var < 10).all()
+    assert all(len(set(v)) == 3 for v in var.tolist())
+    keys = {tuple(sorted(c)) for c in lits.tolist()}
+    assert len(keys) == 42
+
+
+def test_generator_is_deterministic():
+    a = inst.first_satisfiable(1, 10, 42)
+    b = inst.first_satisfiable(1, 10, 42)
+    np.testing.assert_array_equal(a.lits, b.lits)
+    assert a.draw == b.draw
+    c = inst.draw_at(1, 10, 42, a.draw)
+    np.testing.assert_array_equal(a.lits, c.lits)
+
+
+def test_drop_mode_can_shrink():
+    rng = np.random.Generator(np.random.PCG64(3))
+    lits = inst.random_3sat(rng, 3, 8, dup="drop")     # only 8 distinct clauses exist
+    assert lits.shape[0] <= 8
+
+
+def test_m_from_density():
+    assert inst.m_from_density(10, 4.2) == 42
+    assert inst.m_from_density(28, 4.2) == 118
+    assert inst.m_from_density(20, 4.25) == 85
+    assert inst.m_from_density(13, 4.5) == 59          # 58.5 rounds up
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_dpll_agrees_with_enumeration(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.integers(5, 12))
+    m = int(n * rng.choice([3.0, 4.2, 5.5, 7.0]))
+    lits = inst.random_3sat(rng, n, m)
+    assert inst.dpll_satisfiable(n, lits) == (count_solutions_enum(n, lits) > 0)
+
+
+def test_parse_paper_notation():
+    lits = inst.parse_paper_clauses("[-0, +2, +3], [+0, -2, 4]")
+    np.testing.assert_array_equal(lits, [[1, 4, 6], [0, 5, 8]])
+
+
+def test_batched_instances():
+    insts = inst.batched_scan_instances(3, 12, 8, 12)
+    assert len(insts) == 12
+    for it in insts:
+        assert 8 <= it.n <= 12 and it.d in (3.0, 4.2, 5.0)
+        assert it.m == inst.m_from_density(it.n, it.d)
+        assert level_histogram(cost_table(it.n, it.lits), it.m)[0] > 0
+
+
+def test_optimizer_refines_and_is_symmetric():
+    n, m, p = 10, 42, 4
+    it = inst.first_satisfiable(5, n, m)
+    hist = level_histogram(cost_table(n, it.lits), m)
+    gb = np.linspace(0, 2 * np.pi, 24, endpoint=False)
+    gg = np.linspace(0, np.pi, 12)
+    b, g, v_grid, v_ref = optimize_single_pair(hist, p, gb, gg, objective="psol")
+    assert v_ref <= v_grid + 1e-15
+    assert psol_single_pair_hist(hist, b, g, p) == pytest.approx(-v_ref, abs=1e-12)
+    grid = single_pair_grid(hist, p, gb, gg)
+    mirror = single_pair_grid(hist, p, -gb, -gg)
+    np.testing.assert_allclose(grid, mirror, atol=1e-13)
