@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Benchmark of the G-QAOA hot path on one MI355X.
+
+Headline workload: one random 3-SAT instance with n = 28 variables and
+m = 118 clauses (d ~ 4.2), complex64 state of 2^28 amplitudes (2 GiB) plus a
+uint8 cost table, p = 64 rounds with independent per-round angles drawn from
+a seed. One step = clause ingest + bit-sliced cost table + level histogram +
+64 statevector rounds (phase, Grover mixer, readouts) + the final readout
+pass. ``value`` is amplitude-rounds per second: 2^28 * 64 / step time.
+
+Also reported (extra keys of the same JSON line):
+  * ``roofline`` of the dominant kernel (the statevector round pass),
+  * ``cpu_baseline``: the CPU oracle timed on a bounded sample,
+  * ``batched``: the single-angle-pair scan over 4096 instances (n in 8..20,
+    d in {3, 4.2, 5}, 64 x 64 angle grid, p in {1, 4, 16, 64}) against the
+    plain one-instance-one-angle-pair path on the same GPU,
+  * ``cost_table``: clause evaluations per second of the cost-table kernel.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_VARS, M_CLAUSES, P_ROUNDS = 28, 118, 64
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("sv.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2402_02585_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the round kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "sv_round_c64_n28_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("source_sha") != kernel_source_sha():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline():
+    """The oracle's statevector evolution (complex128, numpy) on a bounded
+    sample: one seed-2 instance at n = 22, m = 92, p = 64 rounds."""
+    from oracle.cost import cost_table
+    from oracle.evolve import evolve_sv
+    from paper_2402_02585_amd import instances as inst
+
+    n, m, p = 22, 92, 64
+    it = inst.first_satisfiable(2, n, m)
+    beta, gamma = inst.uniform_angles(2, p)
+    cost = cost_table(n, it.lits)
+    t0 = time.perf_counter()
+    evolve_sv(n, cost, beta, gamma)
+    dt = time.perf_counter() - t0
+    return {"value": (2 ** n) * p / dt, "unit": "amplitude-rounds/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle statevector evolution, n={n} m={m} p={p}, complex128 numpy, one thread, "
+                      f"{dt:.1f} s"}
+
+
+def batched_leg(torch, g, inst, steps: int):
+    """Single-angle-pair scan of 4096 instances vs the plain per-call path."""
+    from paper_2402_02585_amd import instances as _inst  # noqa: F401
+
+    t0 = time.perf_counter()
+    insts = inst.batched_scan_instances(3, 4096, 8, 20)
+    log(f"generated 4096 satisfiable instances in {time.perf_counter() - t0:.1f} s")
+    ns = [it.n for it in insts]
+    ms = [it.m for it in insts]
+    stride = max(ms) + 1
+    hists_dev = g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=stride)
+    hists = hists_dev.cpu().numpy()
+    grid = np.linspace(0.0, math.pi, 64)
+    plist = [1, 4, 16, 64]
+    evals = len(insts) * 64 * 64 * len(plist)
+    out = g.gqaoa_scan_batched(ns, ms, hists, grid, grid, plist)       # autotunes, warms up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.gqaoa_scan_batched(ns, ms, hists, grid, grid, plist, out=out)
+    torch.cuda.synchronize()
+    t_scan = (time.perf_counter() - t0) / steps
+    # histogram step of the batched path (all 4096 instances)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=stride)
+    torch.cuda.synchronize()
+    t_hist = (time.perf_counter() - t0) / steps
+    psol = out[0].cpu().numpy()
+
+    # plain path: one instance and one angle pair per call, statevector and level space
+    rng = np.random.Generator(np.random.PCG64(33))
+    sample = rng.choice(len(insts), 32, replace=False)
+    cells = [(int(i), int(rng.integers(0, 64)), int(rng.integers(0, 64))) for i in sample for _ in range(2)]
+    costs = {int(i): g.gqaoa_cost_table(insts[i].n, insts[i].lits)[0] for i in sample}
+    max_dev = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, bi, gi in cells:
+        it = insts[i]
+        _, ps, _, _ = g.gqaoa_evolve(it.n, it.m, costs[i], np.full(64, grid[bi]), np.full(64, grid[gi]), dtype=g.C64)
+        max_dev = max(max_dev, max(abs(ps[p] - psol[i, q, gi, bi]) for q, p in enumerate(plist)))
+    t_sv = (time.perf_counter() - t0) / len(cells)
+    hdev = {int(i): hists_dev[i, :insts[i].m + 1].contiguous() for i in sample}
+    cells_h = [(int(i), int(rng.integers(0, 64)), int(rng.integers(0, 64))) for i in sample for _ in range(8)]
+    t0 = time.perf_counter()
+    for i, bi, gi in cells_h:
+        it = insts[i]
+        ps, _, _ = g.gqaoa_hist_evolve(it.n, it.m, hdev[i], np.full(64, grid[bi]), np.full(64, grid[gi]))
+        max_dev = max(max_dev, max(abs(ps[p] - psol[i, q, gi, bi]) for q, p in enumerate(plist)))
+    t_h = (time.perf_counter() - t0) / len(cells_h)
+    rate = evals / t_scan
+    plain_sv = len(plist) / t_sv
+    plain_h = len(plist) / t_h
+    return {
+        "metric": "instance-angle evals/s", "value": rate, "ms_per_scan": t_scan * 1e3,
+        "workload": "4096 satisfiable random 3-SAT, n~U{8..20}, d in {3.0,4.2,5.0}, beta,gamma=linspace(0,pi,64), "
+                    "p in {1,4,16,64}, float32",
+        "hist_batched_ms": t_hist * 1e3,
+        "plain_statevector": {"value": plain_sv, "calls_timed": len(cells), "kind": "gqaoa_evolve complex64 per "
+                              "(instance, angle pair), one call gives the 4 readouts"},
+        "plain_level_space": {"value": plain_h, "calls_timed": len(cells_h), "kind": "gqaoa_hist_evolve float64 per "
+                              "(instance, angle pair)"},
+        "speedup_vs_plain_statevector": rate / plain_sv,
+        "speedup_vs_plain_level_space": rate / plain_h,
+        "max_abs_psol_diff_vs_plain": max_dev,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the cpu_baseline leg")
+    ap.add_argument("--skip-batched", action="store_true", help="omit the batched-scan leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 2 GiB device copy (for counter calibration) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2402_02585_amd import gqaoa as g
+    from paper_2402_02585_amd import instances as inst
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        src = torch.empty(2 ** 28, dtype=torch.complex64, device="cuda")
+        src.zero_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x 2 GiB")
+        return
+
+    it = inst.first_satisfiable(2, N_VARS, M_CLAUSES)
+    beta, gamma = inst.uniform_angles(2, P_ROUNDS)
+    N = 1 << N_VARS
+    cost = torch.empty(N, dtype=torch.uint8, device="cuda")
+    psi = torch.empty(N, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(g.gqaoa_workspace_bytes(N_VARS, P_ROUNDS, g.C64), dtype=torch.uint8, device="cuda")
+
+    def step():
+        _, hist = g.gqaoa_cost_table(N_VARS, it.lits, cost=cost)
+        _, psol, _, _ = g.gqaoa_evolve(N_VARS, M_CLAUSES, cost, beta, gamma, dtype=g.C64, psi=psi, workspace=ws)
+        return hist, psol
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.gqaoa_profile_reset()
+    g.gqaoa_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hist, psol = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    g.gqaoa_profile_enable(False)
+    round_ms, round_cnt = g.gqaoa_profile_read("sv_round_c64")
+    ct_ms, ct_cnt = g.gqaoa_profile_read("cost_table")
+    ms_per_step = elapsed / args.steps * 1e3
+    value = N * P_ROUNDS / (elapsed / args.steps)
+    log(f"step {ms_per_step:.2f} ms; P_sol(64) = {psol[-1]:.6f}; #SAT = {int(hist[0].item())}")
+
+    # roofline of the round pass: algorithmic bytes = 16 B of state + 1 B of cost
+    # per amplitude, except round 1, which starts from |s> and reads no state
+    avg_round_ms = round_ms / max(round_cnt, 1)
+    bytes_per_step = N * (9 + (P_ROUNDS - 1) * 17)
+    bytes_per_launch = bytes_per_step / P_ROUNDS
+    achieved = bytes_per_launch / (avg_round_ms * 1e-3) / 1e9
+    traffic = read_traffic()
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "sv_forward_kernel<float,PHASE,WRITE,4,4>", "avg_launch_ms": avg_round_ms,
+                "launches": round_cnt, "algorithmic_bytes_per_launch": bytes_per_launch}
+    cost_table = {"avg_launch_ms": ct_ms / max(ct_cnt, 1),
+                  "clause_evals_per_s": M_CLAUSES * N / (ct_ms / max(ct_cnt, 1) * 1e-3)}
+
+    out = {
+        "metric": "amplitude-rounds/s (n=28,p=64) + batched instance-angle evals/s vs plain, same GPU",
+        "value": value, "unit": "amplitude-rounds/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "G-QAOA statevector, one random 3-SAT instance n=28 m=118 (seed 2, first satisfiable "
+                               "draw), complex64, p=64 independent per-round angles U[0,pi] (seed 2)",
+                   "n": N_VARS, "m": M_CLAUSES, "p": P_ROUNDS, "amplitudes": N, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cost_table": cost_table,
+    }
+    if not args.skip_batched:
+        out["batched"] = batched_leg(torch, g, inst, max(3, args.steps // 2))
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

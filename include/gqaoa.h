@@ -1,0 +1,223 @@
+/* gqaoa.h - C ABI of libgqaoa, an MI355X (gfx950) simulator of Grover-QAOA
+ * (G-QAOA) on random 3-SAT, following Zhang et al., "Grover-QAOA for 3-SAT:
+ * Quadratic Speedup, Fair-Sampling, and Parameter Clustering" (arXiv 2402.02585).
+ *
+ * Conventions for every entry point
+ *  - Pointers named *_dev are device memory (hipMalloc or a torch CUDA tensor),
+ *    owned by the caller. Pointers named *_host are host memory owned by the
+ *    caller. The library keeps no pointer after a call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *    is enqueued on it. Calls that fill *_host outputs synchronize `stream`
+ *    before returning; calls with device outputs only return after enqueueing.
+ *  - Arguments are validated before anything is enqueued: on GQAOA_EINVAL or
+ *    GQAOA_ERANGE nothing has been written. GQAOA_EHIP reports a failed HIP
+ *    call; gqaoa_last_error() then holds the HIP message.
+ *  - Clause encoding: a literal is the int32 2*var + neg (var in [0, n),
+ *    neg = 1 for a negated variable); a clause is 3 literals on 3 distinct
+ *    variables (App. B, Eq. (B2) with k_i = 3). lits_host holds 3*m int32.
+ *  - Assignment tau <-> index z with variable v at bit v of z. A literal is
+ *    false iff bit var of z equals neg (App. B: x is satisfied by tau(x) = 1,
+ *    its negation by tau(x) = 0).
+ *  - Complex amplitudes are interleaved (re, im): float2 for GQAOA_C64,
+ *    double2 for GQAOA_C128. Angles are always double.
+ *  - Per-round host outputs have p+1 entries: index 0 is the initial state,
+ *    index j the state after round j's mixer.
+ *  - The library is not thread-safe for concurrent calls sharing a
+ *    workspace; independent workspaces/streams may be used concurrently.
+ */
+#ifndef GQAOA_H
+#define GQAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GQAOA_OK = 0,
+    GQAOA_EINVAL = -1,      /* NULL pointer, malformed clause, unknown enum value */
+    GQAOA_ERANGE = -2,      /* n, m, p, level, batch size or grid out of range */
+    GQAOA_EWORKSPACE = -3,  /* ws_bytes smaller than the matching *_workspace_bytes */
+    GQAOA_EHIP = -4,        /* a HIP runtime call failed */
+    GQAOA_ENODEV = -5       /* no usable gfx950 device */
+};
+
+typedef enum { GQAOA_C64 = 0, GQAOA_C128 = 1 } gqaoa_dtype;
+
+/* Limits. GQAOA_MAX_M bounds m because costs are stored in one byte. */
+#define GQAOA_MIN_N 3
+#define GQAOA_MAX_N 34
+#define GQAOA_MAX_M 255
+
+/* Text of a status code (static storage). */
+const char *gqaoa_status_string(int status);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *gqaoa_last_error(void);
+/* ABI version, currently 1. */
+int gqaoa_abi_version(void);
+
+/* ---- cost table and level histogram ----------------------------------------
+ * Definition: Sec. II.A (the energy E_i of clause i following Eq. (1)) and
+ * App. B. C(z) = number of clauses that assignment z leaves unsatisfied = the
+ * diagonal of H_P. The level histogram N_k = #{z : C(z) = k} is the
+ * "classical pre-computation" of App. C ("Optimization").
+ * n in [3, 34], m in [1, 255]. cost_dev: uint8[2^n], written for every z.
+ * hist_dev: uint64[m+1] (N_0 = number of solutions), or NULL to skip it.
+ * Errors: EINVAL for NULL lits/cost or a clause with a repeated variable or a
+ * literal outside [0, 2n); ERANGE for n or m outside the limits. */
+int gqaoa_cost_table(int n, int m, const int32_t *lits_host, uint8_t *cost_dev,
+                     uint64_t *hist_dev, void *stream);
+
+/* Histograms only, for many instances in one launch (no cost table kept).
+ * Instance i has n_host[i] variables, m_host[i] clauses whose literals start
+ * at lits_host[3*off_i], off_i = sum of m_host[<i]. hists_dev is
+ * uint64[num_inst][hist_stride], hist_stride >= max m + 1; entries beyond m_i
+ * are zeroed. n_i in [3, 30], m_i in [1, 255], num_inst in [1, 2^20].
+ * Errors as gqaoa_cost_table, plus ERANGE for hist_stride. */
+int gqaoa_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                       const int32_t *lits_host, uint64_t *hists_dev, int hist_stride,
+                       void *stream);
+
+/* ---- statevector evolution, Eq. (3) ---------------------------------------
+ * For j = 1..p applies exp(-i gamma_j H_P) (phase exp(-i gamma_j C(z)) on z),
+ * then exp(-i beta_j H_M) with H_M = |s><s| a projector (Eq. (2)), i.e.
+ * psi <- psi + (exp(-i beta_j) - 1) |s><s|psi>. The single-angle-pair form,
+ * Eq. (5), is the special case of equal angles.
+ * psi_dev: on entry the initial state (ignored if init_uniform != 0, which
+ * starts from |+> = |s>); on exit the state after round p. p in [0, 100000].
+ * Readouts, each host array of p+1 doubles or NULL:
+ *   psol_host[j]   = sum over z with C(z) = target_level of |psi_z|^2
+ *                    (target_level 0: solutions; k_min: Max-SAT assignments),
+ *   energy_host[j] = <psi|H_P|psi>, the cost function of Eq. (4),
+ *   norm_host[j]   = <psi|psi>.
+ * cost_dev must hold C(z) for all z (from gqaoa_cost_table) with values <= m.
+ * ws_dev/ws_bytes: device scratch of gqaoa_workspace_bytes(n, p, dt, 0) bytes.
+ * Errors: EINVAL (NULL cost/psi/angles/ws, bad dtype), ERANGE (n, m, p,
+ * target_level outside [0, m]), EWORKSPACE. */
+size_t gqaoa_workspace_bytes(int n, int p, int dtype, int ckpt_every);
+int gqaoa_evolve(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host,
+                 const double *gamma_host, int dtype, int init_uniform, void *psi_dev,
+                 int target_level, double *psol_host, double *energy_host,
+                 double *norm_host, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Solution probability of a given state (the readout of Sec. III, P_sol):
+ * *out_host = sum over z with C(z) = target_level of |psi_z|^2.
+ * ws: gqaoa_workspace_bytes(n, 0, dtype, 0) bytes. */
+int gqaoa_solution_prob(int n, const uint8_t *cost_dev, const void *psi_dev, int dtype,
+                        int target_level, double *out_host, void *ws_dev, size_t ws_bytes,
+                        void *stream);
+
+/* ---- adjoint gradient of P_sol ----------------------------------------------
+ * P = <psi_p|Pi_t|psi_p> after p rounds of Eq. (3) from |s>, Pi_t the
+ * projector on level t = target_level, and its gradient with respect to all
+ * 2p angles (the full G-QAOA parameters optimized in App. C), by a reverse
+ * sweep: lambda_p = Pi_t psi_p; mu_k = lambda_k + (e^{+i beta_k} - 1)|s><s|lambda_k>;
+ * dP/dbeta_k = 2 Re(-i e^{-i beta_k} <lambda_k|s><s|phi_k>);
+ * dP/dgamma_k = 2 Im(sum_z conj(mu_z) C(z) phi_z); lambda_{k-1} = e^{+i gamma_k C} mu_k,
+ * with phi_k the state after round k's phase. Forward states are
+ * checkpointed every ckpt_every rounds and recomputed per segment
+ * (ckpt_every = 0 keeps every round's state).
+ * Batched form: num_inst instances with the same n, m_host[i] clauses,
+ * costs at cost_dev + i*2^n, angles at beta_host + i*p. Outputs psol_host[i],
+ * dbeta_host[i*p + k], dgamma_host[i*p + k].
+ * ws: gqaoa_grad_workspace_bytes(num_inst, n, p, dtype, ckpt_every) bytes.
+ * Errors: as gqaoa_evolve; ERANGE for p < 1, ckpt_every < 0 or num_inst < 1. */
+size_t gqaoa_grad_workspace_bytes(int num_inst, int n, int p, int dtype, int ckpt_every);
+int gqaoa_grad(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host,
+               const double *gamma_host, int dtype, int target_level, int ckpt_every,
+               double *psol_host, double *dbeta_host, double *dgamma_host, void *ws_dev,
+               size_t ws_bytes, void *stream);
+int gqaoa_grad_batched(int num_inst, int n, const int32_t *m_host, const uint8_t *cost_dev,
+                       int p, const double *beta_host, const double *gamma_host, int dtype,
+                       const int32_t *target_host, int ckpt_every, double *psol_host,
+                       double *dbeta_host, double *dgamma_host, void *ws_dev,
+                       size_t ws_bytes, void *stream);
+
+/* ---- level-space ("effective space") evolution ----------------------------
+ * App. C, "Optimization": from |s> every amplitude depends on z only through
+ * C(z), so the state is one amplitude b_k per occupied level k with weight
+ * w_k = N_k / 2^n, evolved as b_k <- e^{-i gamma_j k} b_k, then
+ * b_k <- b_k + (e^{-i beta_j} - 1) sum_l w_l b_l. Readouts P_sol = w_t |b_t|^2,
+ * E = sum_k k w_k |b_k|^2, norm = sum_k w_k |b_k|^2 (float64 on the device).
+ * hist_dev: uint64[m+1] (from gqaoa_cost_table); n gives 2^n = sum N_k.
+ * Outputs as gqaoa_evolve (p+1 entries each, NULL to skip). */
+int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const double *beta_host,
+                      const double *gamma_host, int target_level, double *psol_host,
+                      double *energy_host, double *norm_host, void *stream);
+
+/* ---- batched single-angle-pair scan, Eq. (5) -------------------------------
+ * For every instance i, beta_b (b < nb) and gamma_g (g < ng), runs the
+ * single-angle-pair protocol in the level space for p_list[num_p-1] rounds
+ * and records, after each p in p_list (ascending, >= 1),
+ *   psol_dev  [((i*num_p + q)*ng + g)*nb + b] = P_sol   (float),
+ *   energy_dev[same index]                    = E, Eq. (4) (float; NULL to skip).
+ * Instance i: hists_host + i*hist_stride holds N_k for k <= m_host[i],
+ * n_host[i] variables; target_host[i] its target level (NULL = 0 for all).
+ * betas_host[nb], gammas_host[ng] in radians. Arithmetic is float32.
+ * tile: NULL = autotuned (cached per device and shape class), else an int[2]
+ * {waves_per_block in {1,2,4}, blocks_per_cu in [1,32]}.
+ * ws: gqaoa_scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p) bytes.
+ * Errors: EINVAL (NULL pointers), ERANGE (num_inst, nb, ng in [1, 4096],
+ * num_p in [1, 16], p values in [1, 100000], more than 256 occupied levels). */
+size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p);
+int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                       const uint64_t *hists_host, int hist_stride, const int32_t *target_host,
+                       int nb, const double *betas_host, int ng, const double *gammas_host,
+                       int num_p, const int32_t *p_list_host, float *psol_dev,
+                       float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes,
+                       void *stream);
+
+/* ---- angle-predictor MLP (bfloat16 MFMA, float32 accumulation) -------------
+ * The paper suggests deriving angles from statistics of the density of
+ * states (Sec. V) and reports clustering of optimized pairs (Sec. III.B).
+ * Network 131 -> 256 -> GELU -> 256 -> GELU -> 2 (exact-erf GELU).
+ * params_dev: float32 master parameters packed as
+ *   W1[160][256] (rows 131..159 zero), b1[256], W2[256][256], b2[256],
+ *   W3[256][2], b3[2]  -> GQAOA_MLP_NPARAMS floats.
+ * x_dev: float32 features [batch][131] (rounded to bfloat16 on load).
+ * out_dev: float32 raw outputs [batch][2]; beta = 2 pi sigmoid(o0),
+ * gamma = pi sigmoid(o1).
+ * act_dev: activation cache of gqaoa_mlp_act_bytes(batch) bytes, written by
+ * forward and read by backward.
+ * gqaoa_mlp_backward takes dout_dev [batch][2] (dL/do, float32) and writes
+ * grads_dev (same packing as params, float32; overwritten, not accumulated).
+ * gqaoa_mlp_adam: Adam with bias correction on the float32 master copy;
+ * state_dev holds 2*GQAOA_MLP_NPARAMS floats (m then v), zero at step 1.
+ * batch in [1, 1<<20]. */
+#define GQAOA_MLP_NPARAMS (160 * 256 + 256 + 256 * 256 + 256 + 256 * 2 + 2)
+size_t gqaoa_mlp_act_bytes(int batch);
+int gqaoa_mlp_forward(const float *params_dev, int batch, const float *x_dev, float *out_dev,
+                      void *act_dev, void *stream);
+int gqaoa_mlp_backward(const float *params_dev, int batch, const void *act_dev,
+                       const float *dout_dev, float *grads_dev, void *stream);
+int gqaoa_mlp_adam(float *params_dev, const float *grads_dev, float *state_dev, int step,
+                   float lr, float beta1, float beta2, float eps, void *stream);
+/* Angle-regression loss L = mean_b ((beta_b - beta*_b)/(2 pi))^2 + ((gamma_b - gamma*_b)/pi)^2
+ * on the raw outputs out_dev [batch][2]; targets_dev [batch][2] = (beta*, gamma*).
+ * Writes dout_dev = dL/dout [batch][2] and *loss_dev (float, device). */
+int gqaoa_mlp_loss(int batch, const float *out_dev, const float *targets_dev, float *dout_dev,
+                   float *loss_dev, void *stream);
+/* Features of the network from device histograms: x_dev [batch][131] with
+ * x[k] = N_k / 2^n for k < 128 (0 beyond m), x[128] = n/24, x[129] = d/8 with
+ * d = m/n, x[130] = log2(p)/6. hists_dev [batch][hist_stride] (uint64);
+ * n_dev, m_dev, p_dev: int32 [batch] device arrays. */
+int gqaoa_mlp_features(int batch, const uint64_t *hists_dev, int hist_stride, const int32_t *n_dev,
+                       const int32_t *m_dev, const int32_t *p_dev, float *x_dev, void *stream);
+
+/* ---- instrumentation ---------------------------------------------------------
+ * When enabled, the library brackets each launch of its streaming round
+ * kernels with HIP events on the launch stream and accumulates their
+ * durations under a name: "sv_round_c64", "sv_round_c128" (forward round
+ * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table"
+ * and "scan". Durations are collected when the call that launched them
+ * synchronizes. gqaoa_profile_read returns GQAOA_EINVAL for an unknown name. */
+int gqaoa_profile_enable(int on);
+void gqaoa_profile_reset(void);
+int gqaoa_profile_read(const char *name, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GQAOA_H */

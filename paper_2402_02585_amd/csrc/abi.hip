@@ -1,0 +1,406 @@
+// C ABI of libgqaoa (include/gqaoa.h): argument validation, error reporting
+// and dispatch to the kernel launchers. Every check runs before the first HIP
+// call, so an invalid call returns without touching the device.
+#include "internal.h"
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+namespace gqaoa {
+
+// launchers (cost_table.hip, sv.hip, hist.hip, mlp.hip)
+int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist, hipStream_t st);
+int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits,
+                        uint64_t *hists, int hist_stride, hipStream_t st);
+size_t sv_workspace_bytes(int num_inst, int n, int p, int dtype, int ckpt_every, bool grad);
+int run_evolve(int n, int m, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
+               int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
+               hipStream_t st);
+int run_solution_prob(int n, const uint8_t *cost, const void *psi, int dtype, int target, double *out, void *ws,
+                      hipStream_t st);
+int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int p, const double *beta,
+             const double *gamma, int dtype, const int32_t *targets, int ckpt_every, double *psol, double *dbeta,
+             double *dgamma, void *ws, hipStream_t st);
+int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *beta, const double *gamma,
+                    int target, double *psol, double *energy, double *norm, hipStream_t st);
+size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p);
+int scan_max_levels();
+int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists, int hist_stride,
+             const int32_t *target_host, int nb, const double *betas, int ng, const double *gammas, int num_p,
+             const int32_t *p_list, float *psol, float *energy, const int32_t *tile, void *ws, hipStream_t st);
+size_t mlp_act_bytes(int batch);
+int run_mlp_forward(const float *prm, int batch, const float *x, float *out, void *act, hipStream_t st);
+int run_mlp_backward(const float *prm, int batch, const void *act, const float *dout, float *grads,
+                     hipStream_t st);
+int run_mlp_adam(float *prm, const float *grads, float *state, int step, float lr, float b1, float b2, float eps,
+                 hipStream_t st);
+int run_mlp_loss(int batch, const float *out, const float *tgt, float *dout, float *loss, hipStream_t st);
+int run_mlp_features(int batch, const uint64_t *hists, int hist_stride, const int32_t *n, const int32_t *m,
+                     const int32_t *p, float *x, hipStream_t st);
+
+// ---- errors ----------------------------------------------------------------------------
+static thread_local char g_err[512] = {0};
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+int fail(int status, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+// ---- instrumentation -----------------------------------------------------------------------
+struct ProfPending {
+    const char *name;
+    hipEvent_t e0, e1;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfPending> g_prof_pending;
+struct ProfTotal {
+    double ms = 0.0;
+    int64_t count = 0;
+};
+static const char *kProfNames[] = {"sv_round_c64", "sv_round_c128", "sv_reverse_c64", "sv_reverse_c128",
+                                   "cost_table", "scan"};
+static ProfTotal g_prof_tot[sizeof(kProfNames) / sizeof(kProfNames[0])];
+
+bool prof_on() { return g_prof_on; }
+
+ProfScope::ProfScope(const char *name, hipStream_t st) : name_(name), st_(st) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&e0_) != hipSuccess) { e0_ = nullptr; return; }
+    if (hipEventRecord(e0_, st_) != hipSuccess) { (void)hipEventDestroy(e0_); e0_ = nullptr; }
+}
+
+void ProfScope::end() {
+    if (!e0_) return;
+    hipEvent_t e1;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0_); e0_ = nullptr; return; }
+    (void)hipEventRecord(e1, st_);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_pending.push_back(ProfPending{name_, e0_, e1});
+    e0_ = nullptr;
+}
+
+void prof_collect() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &p : g_prof_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.e1) == hipSuccess && hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+            for (size_t i = 0; i < sizeof(kProfNames) / sizeof(kProfNames[0]); ++i)
+                if (!strcmp(kProfNames[i], p.name)) {
+                    g_prof_tot[i].ms += ms;
+                    g_prof_tot[i].count += 1;
+                }
+        }
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    g_prof_pending.clear();
+}
+
+// ---- device properties -------------------------------------------------------------------
+static std::mutex g_dev_mu;
+static std::vector<DeviceInfo> g_devs;
+
+int device_info(DeviceInfo *out) {
+    int dev = -1;
+    GQ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    for (auto &d : g_devs)
+        if (d.device == dev) {
+            *out = d;
+            return GQAOA_OK;
+        }
+    hipDeviceProp_t prop;
+    GQ_HIP(hipGetDeviceProperties(&prop, dev));
+    DeviceInfo d;
+    d.device = dev;
+    d.num_cus = prop.multiProcessorCount;
+    strncpy(d.arch, prop.gcnArchName, sizeof(d.arch) - 1);
+    if (strncmp(d.arch, "gfx950", 6) != 0)
+        return fail(GQAOA_ENODEV, "device %d is %s; this library is built for gfx950", dev, d.arch);
+    g_devs.push_back(d);
+    *out = d;
+    return GQAOA_OK;
+}
+
+// ---- validation helpers ------------------------------------------------------------------
+static int check_clauses(int n, int m, const int32_t *lits, int inst) {
+    for (int i = 0; i < m; ++i) {
+        int v[3];
+        for (int j = 0; j < 3; ++j) {
+            const int32_t lit = lits[3 * i + j];
+            if (lit < 0 || lit >= 2 * n)
+                return fail(GQAOA_EINVAL, "instance %d clause %d: literal %d outside [0, %d)", inst, i, lit, 2 * n);
+            v[j] = lit >> 1;
+        }
+        if (v[0] == v[1] || v[0] == v[2] || v[1] == v[2])
+            return fail(GQAOA_EINVAL, "instance %d clause %d repeats a variable", inst, i);
+    }
+    return GQAOA_OK;
+}
+
+static bool dtype_ok(int dt) { return dt == GQAOA_C64 || dt == GQAOA_C128; }
+constexpr int kMaxP = 100000;
+
+}  // namespace gqaoa
+
+using namespace gqaoa;
+
+extern "C" {
+
+const char *gqaoa_status_string(int status) {
+    switch (status) {
+        case GQAOA_OK: return "ok";
+        case GQAOA_EINVAL: return "invalid argument";
+        case GQAOA_ERANGE: return "argument out of range";
+        case GQAOA_EWORKSPACE: return "workspace too small";
+        case GQAOA_EHIP: return "HIP runtime error";
+        case GQAOA_ENODEV: return "no gfx950 device";
+        default: return "unknown status";
+    }
+}
+
+const char *gqaoa_last_error(void) { return g_err; }
+
+int gqaoa_abi_version(void) { return 1; }
+
+int gqaoa_cost_table(int n, int m, const int32_t *lits_host, uint8_t *cost_dev, uint64_t *hist_dev,
+                     void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (m < 1 || m > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "m=%d outside [1, 255]", m);
+    if (!lits_host || !cost_dev) return fail(GQAOA_EINVAL, "NULL lits_host or cost_dev");
+    int s = check_clauses(n, m, lits_host, 0);
+    if (s) return s;
+    return launch_cost_table(n, m, lits_host, cost_dev, hist_dev, (hipStream_t)stream);
+}
+
+int gqaoa_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits_host,
+                       uint64_t *hists_dev, int hist_stride, void *stream) {
+    clear_error();
+    if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d outside [1, 2^20]", num_inst);
+    if (!n_host || !m_host || !lits_host || !hists_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
+    size_t off = 0;
+    for (int i = 0; i < num_inst; ++i) {
+        if (n_host[i] < GQAOA_MIN_N || n_host[i] > 30) return fail(GQAOA_ERANGE, "instance %d: n=%d outside [3, 30]", i, n_host[i]);
+        if (m_host[i] < 1 || m_host[i] > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "instance %d: m=%d", i, m_host[i]);
+        if (m_host[i] + 1 > hist_stride) return fail(GQAOA_ERANGE, "instance %d: m+1=%d > hist_stride", i, m_host[i] + 1);
+        int s = check_clauses(n_host[i], m_host[i], lits_host + 3 * off, i);
+        if (s) return s;
+        off += (size_t)m_host[i];
+    }
+    return launch_hist_batched(num_inst, n_host, m_host, lits_host, hists_dev, hist_stride, (hipStream_t)stream);
+}
+
+size_t gqaoa_workspace_bytes(int n, int p, int dtype, int ckpt_every) {
+    (void)ckpt_every;
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N || p < 0 || p > kMaxP || !dtype_ok(dtype)) return 0;
+    return sv_workspace_bytes(1, n, p, dtype, 0, false);
+}
+
+int gqaoa_evolve(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host, const double *gamma_host,
+                 int dtype, int init_uniform, void *psi_dev, int target_level, double *psol_host,
+                 double *energy_host, double *norm_host, void *ws_dev, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (m < 1 || m > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "m=%d outside [1, 255]", m);
+    if (p < 0 || p > kMaxP) return fail(GQAOA_ERANGE, "p=%d outside [0, %d]", p, kMaxP);
+    if (target_level < 0 || target_level > m) return fail(GQAOA_ERANGE, "target_level=%d outside [0, m]", target_level);
+    if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
+    if (!cost_dev || !psi_dev || !ws_dev) return fail(GQAOA_EINVAL, "NULL cost_dev, psi_dev or ws_dev");
+    if (p > 0 && (!beta_host || !gamma_host)) return fail(GQAOA_EINVAL, "NULL angles");
+    const size_t need = sv_workspace_bytes(1, n, p, dtype, 0, false);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    return run_evolve(n, m, cost_dev, p, beta_host, gamma_host, dtype, init_uniform, psi_dev, target_level, psol_host,
+                      energy_host, norm_host, ws_dev, (hipStream_t)stream);
+}
+
+int gqaoa_solution_prob(int n, const uint8_t *cost_dev, const void *psi_dev, int dtype, int target_level,
+                        double *out_host, void *ws_dev, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (target_level < 0 || target_level > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "target_level=%d", target_level);
+    if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
+    if (!cost_dev || !psi_dev || !out_host || !ws_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    const size_t need = sv_workspace_bytes(1, n, 0, dtype, 0, false);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    return run_solution_prob(n, cost_dev, psi_dev, dtype, target_level, out_host, ws_dev, (hipStream_t)stream);
+}
+
+size_t gqaoa_grad_workspace_bytes(int num_inst, int n, int p, int dtype, int ckpt_every) {
+    if (num_inst < 1 || n < GQAOA_MIN_N || n > GQAOA_MAX_N || p < 1 || p > kMaxP || ckpt_every < 0 ||
+        !dtype_ok(dtype))
+        return 0;
+    return sv_workspace_bytes(num_inst, n, p, dtype, ckpt_every, true);
+}
+
+int gqaoa_grad_batched(int num_inst, int n, const int32_t *m_host, const uint8_t *cost_dev, int p,
+                       const double *beta_host, const double *gamma_host, int dtype, const int32_t *target_host,
+                       int ckpt_every, double *psol_host, double *dbeta_host, double *dgamma_host, void *ws_dev,
+                       size_t ws_bytes, void *stream) {
+    clear_error();
+    if (num_inst < 1 || num_inst > 65536) return fail(GQAOA_ERANGE, "num_inst=%d outside [1, 65536]", num_inst);
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (p < 1 || p > kMaxP) return fail(GQAOA_ERANGE, "p=%d outside [1, %d]", p, kMaxP);
+    if (ckpt_every < 0) return fail(GQAOA_ERANGE, "ckpt_every=%d", ckpt_every);
+    if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
+    if (!m_host || !cost_dev || !beta_host || !gamma_host || !ws_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    std::vector<int32_t> tg(num_inst, 0);
+    for (int i = 0; i < num_inst; ++i) {
+        if (m_host[i] < 1 || m_host[i] > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "instance %d: m=%d", i, m_host[i]);
+        if (target_host) tg[i] = target_host[i];
+        if (tg[i] < 0 || tg[i] > m_host[i]) return fail(GQAOA_ERANGE, "instance %d: target_level=%d", i, tg[i]);
+    }
+    const size_t need = sv_workspace_bytes(num_inst, n, p, dtype, ckpt_every, true);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    return run_grad(num_inst, n, m_host, cost_dev, p, beta_host, gamma_host, dtype, tg.data(), ckpt_every, psol_host,
+                    dbeta_host, dgamma_host, ws_dev, (hipStream_t)stream);
+}
+
+int gqaoa_grad(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host, const double *gamma_host,
+               int dtype, int target_level, int ckpt_every, double *psol_host, double *dbeta_host,
+               double *dgamma_host, void *ws_dev, size_t ws_bytes, void *stream) {
+    const int32_t mm = m, tt = target_level;
+    return gqaoa_grad_batched(1, n, &mm, cost_dev, p, beta_host, gamma_host, dtype, &tt, ckpt_every, psol_host,
+                              dbeta_host, dgamma_host, ws_dev, ws_bytes, stream);
+}
+
+int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const double *beta_host,
+                      const double *gamma_host, int target_level, double *psol_host, double *energy_host,
+                      double *norm_host, void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > 62) return fail(GQAOA_ERANGE, "n=%d outside [3, 62]", n);
+    if (m < 1 || m > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "m=%d outside [1, 255]", m);
+    if (p < 0 || p > kMaxP) return fail(GQAOA_ERANGE, "p=%d outside [0, %d]", p, kMaxP);
+    if (target_level < 0 || target_level > m) return fail(GQAOA_ERANGE, "target_level=%d", target_level);
+    if (!hist_dev) return fail(GQAOA_EINVAL, "NULL hist_dev");
+    if (p > 0 && (!beta_host || !gamma_host)) return fail(GQAOA_EINVAL, "NULL angles");
+    return run_hist_evolve(n, m, hist_dev, p, beta_host, gamma_host, target_level, psol_host, energy_host, norm_host,
+                           (hipStream_t)stream);
+}
+
+size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p) {
+    if (num_inst < 1 || hist_stride < 2 || nb < 1 || ng < 1 || num_p < 1) return 0;
+    return scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p);
+}
+
+int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
+                       int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
+                       const double *gammas_host, int num_p, const int32_t *p_list_host, float *psol_dev,
+                       float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d", num_inst);
+    if (nb < 1 || nb > 4096 || ng < 1 || ng > 4096) return fail(GQAOA_ERANGE, "grid %d x %d outside [1, 4096]^2", nb, ng);
+    if (num_p < 1 || num_p > 16) return fail(GQAOA_ERANGE, "num_p=%d outside [1, 16]", num_p);
+    if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
+    if (!n_host || !m_host || !hists_host || !betas_host || !gammas_host || !p_list_host || !psol_dev || !ws_dev)
+        return fail(GQAOA_EINVAL, "NULL argument");
+    for (int q = 0; q < num_p; ++q) {
+        if (p_list_host[q] < 1 || p_list_host[q] > kMaxP) return fail(GQAOA_ERANGE, "p_list[%d]=%d", q, p_list_host[q]);
+        if (q && p_list_host[q] <= p_list_host[q - 1]) return fail(GQAOA_EINVAL, "p_list is not ascending");
+    }
+    if (tile && (!(tile[0] == 1 || tile[0] == 2 || tile[0] == 4) || tile[1] < 1 || tile[1] > 32))
+        return fail(GQAOA_EINVAL, "tile {%d, %d}", tile[0], tile[1]);
+    const uint64_t items = (uint64_t)num_inst * ng * ((nb + 63) / 64);
+    if (items >= (1ull << 31)) return fail(GQAOA_ERANGE, "too many work items (%llu)", (unsigned long long)items);
+    for (int i = 0; i < num_inst; ++i) {
+        if (n_host[i] < GQAOA_MIN_N || n_host[i] > 62) return fail(GQAOA_ERANGE, "instance %d: n=%d", i, n_host[i]);
+        if (m_host[i] < 1 || m_host[i] > GQAOA_MAX_M || m_host[i] + 1 > hist_stride)
+            return fail(GQAOA_ERANGE, "instance %d: m=%d", i, m_host[i]);
+        const int t = target_host ? target_host[i] : 0;
+        if (t < 0 || t > m_host[i]) return fail(GQAOA_ERANGE, "instance %d: target_level=%d", i, t);
+        int K = 0;
+        for (int k = 0; k <= m_host[i]; ++k) K += hists_host[(size_t)i * hist_stride + k] != 0;
+        if (K > scan_max_levels()) return fail(GQAOA_ERANGE, "instance %d: %d occupied levels (max %d)", i, K, scan_max_levels());
+    }
+    const size_t need = scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    return run_scan(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng, gammas_host,
+                    num_p, p_list_host, psol_dev, energy_dev, tile, ws_dev, (hipStream_t)stream);
+}
+
+size_t gqaoa_mlp_act_bytes(int batch) {
+    if (batch < 1 || batch > (1 << 20)) return 0;
+    return mlp_act_bytes(batch);
+}
+
+int gqaoa_mlp_forward(const float *params_dev, int batch, const float *x_dev, float *out_dev, void *act_dev,
+                      void *stream) {
+    clear_error();
+    if (batch < 1 || batch > (1 << 20)) return fail(GQAOA_ERANGE, "batch=%d", batch);
+    if (!params_dev || !x_dev || !out_dev || !act_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    return run_mlp_forward(params_dev, batch, x_dev, out_dev, act_dev, (hipStream_t)stream);
+}
+
+int gqaoa_mlp_backward(const float *params_dev, int batch, const void *act_dev, const float *dout_dev,
+                       float *grads_dev, void *stream) {
+    clear_error();
+    if (batch < 1 || batch > (1 << 20)) return fail(GQAOA_ERANGE, "batch=%d", batch);
+    if (!params_dev || !act_dev || !dout_dev || !grads_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    return run_mlp_backward(params_dev, batch, act_dev, dout_dev, grads_dev, (hipStream_t)stream);
+}
+
+int gqaoa_mlp_adam(float *params_dev, const float *grads_dev, float *state_dev, int step, float lr, float beta1,
+                   float beta2, float eps, void *stream) {
+    clear_error();
+    if (step < 1) return fail(GQAOA_ERANGE, "step=%d (first step is 1)", step);
+    if (!params_dev || !grads_dev || !state_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+        return fail(GQAOA_ERANGE, "Adam hyper-parameters");
+    return run_mlp_adam(params_dev, grads_dev, state_dev, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+int gqaoa_mlp_loss(int batch, const float *out_dev, const float *targets_dev, float *dout_dev, float *loss_dev,
+                   void *stream) {
+    clear_error();
+    if (batch < 1 || batch > (1 << 20)) return fail(GQAOA_ERANGE, "batch=%d", batch);
+    if (!out_dev || !targets_dev || !dout_dev || !loss_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    return run_mlp_loss(batch, out_dev, targets_dev, dout_dev, loss_dev, (hipStream_t)stream);
+}
+
+int gqaoa_mlp_features(int batch, const uint64_t *hists_dev, int hist_stride, const int32_t *n_dev,
+                       const int32_t *m_dev, const int32_t *p_dev, float *x_dev, void *stream) {
+    clear_error();
+    if (batch < 1 || batch > (1 << 20)) return fail(GQAOA_ERANGE, "batch=%d", batch);
+    if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
+    if (!hists_dev || !n_dev || !m_dev || !p_dev || !x_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    return run_mlp_features(batch, hists_dev, hist_stride, n_dev, m_dev, p_dev, x_dev, (hipStream_t)stream);
+}
+
+int gqaoa_profile_enable(int on) {
+    g_prof_on = on != 0;
+    return GQAOA_OK;
+}
+
+void gqaoa_profile_reset(void) {
+    prof_collect();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &t : g_prof_tot) t = ProfTotal{};
+}
+
+int gqaoa_profile_read(const char *name, double *total_ms, int64_t *count) {
+    prof_collect();
+    if (!name) return fail(GQAOA_EINVAL, "NULL name");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (size_t i = 0; i < sizeof(kProfNames) / sizeof(kProfNames[0]); ++i)
+        if (!strcmp(kProfNames[i], name)) {
+            if (total_ms) *total_ms = g_prof_tot[i].ms;
+            if (count) *count = g_prof_tot[i].count;
+            return GQAOA_OK;
+        }
+    return fail(GQAOA_EINVAL, "unknown profile name %s", name);
+}
+
+}  // extern "C"

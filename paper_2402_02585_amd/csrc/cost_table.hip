@@ -1,0 +1,243 @@
+// Cost table C(z) and level histogram N_k by bit-sliced clause evaluation.
+//
+// C(z) is the number of clauses left unsatisfied by assignment z, i.e. the
+// diagonal of H_P (Sec. II.A, the clause energy that follows Eq. (1); App. B).
+// N_k = #{z : C(z) = k} is the per-level state count of App. C. The word
+// layout and clause records are described in cost_bits.h.
+//
+// Each lane evaluates one 32-assignment word per loop trip: per clause one
+// v_cndmask selects the low-literal pattern P when the clause is active for
+// this lane, then a carry-save adder tree folds 16 clauses at a time into
+// eight bit-planes; 8x8 bit transposes turn the planes into byte costs.
+// Clauses whose variables all sit in wave-uniform bits add a scalar count.
+// The histogram is tallied in LDS (one copy per wave) and written as per-block
+// rows, which a second kernel sums in a fixed order.
+#include "internal.h"
+#include "cost_bits.h"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+namespace gqaoa {
+
+constexpr int kCostThreads = 256;
+constexpr int kCostWaves = kCostThreads / kWave;
+
+// Costs of the 32 assignments of word w (bytes, p[r] byte q = C(32w + 4r + q)).
+__device__ __forceinline__ void eval_word(const ClauseRec *__restrict__ vec, int nvec,
+                                          const UniformRec *__restrict__ uni, int nuni,
+                                          uint64_t w, uint32_t (&out)[8]) {
+    const uint64_t zw = (w & ~63ull) << kLowBits;
+    // every active lane of the wave has the same high bits: make them scalar
+    const uint32_t zlo = __builtin_amdgcn_readfirstlane((uint32_t)zw);
+    const uint32_t zhi = __builtin_amdgcn_readfirstlane((uint32_t)(zw >> 32));
+    const uint64_t zwave = ((uint64_t)zhi << 32) | zlo;
+
+    uint32_t u = 0;
+    for (int i = 0; i < nuni; ++i) u += high_literals_false(zwave, uni[i].hivar, uni[i].hineg);
+
+    SlicedCounter cnt;
+    cnt.clear();
+    for (int g = 0; g < nvec; g += kGroup) {
+        uint32_t f[kGroup];
+#pragma unroll
+        for (int i = 0; i < kGroup; ++i) {
+            const ClauseRec r = vec[g + i];
+            const uint64_t L = high_literals_false(zwave, r.hivar, r.hineg) ? r.L : 0ull;
+            f[i] = __builtin_amdgcn_inverse_ballot_w64(L) ? r.P : 0u;
+        }
+        cnt.add16(f);
+    }
+    cnt.transpose_to_bytes();
+    const uint32_t ub = u * 0x01010101u;  // no byte overflows: every count <= m <= 255
+#pragma unroll
+    for (int r = 0; r < 8; ++r) out[r] = cnt.p[r] + ub;
+}
+
+__device__ __forceinline__ void tally(uint32_t *h, uint32_t v) {
+    atomicAdd(h + (v & 0xFFu), 1u);
+    atomicAdd(h + ((v >> 8) & 0xFFu), 1u);
+    atomicAdd(h + ((v >> 16) & 0xFFu), 1u);
+    atomicAdd(h + (v >> 24), 1u);
+}
+
+__global__ void __launch_bounds__(kCostThreads)
+cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec *__restrict__ uni,
+                  int nuni, int n, uint8_t *__restrict__ cost, uint32_t *__restrict__ block_hist,
+                  int hist_len) {
+    __shared__ uint32_t lhist[kCostWaves][256];
+    for (int i = threadIdx.x; i < kCostWaves * 256; i += kCostThreads) (&lhist[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t *h = lhist[threadIdx.x / kWave];
+    const uint64_t N = 1ull << n;
+    const uint64_t nwords = n >= kLowBits ? (N >> kLowBits) : 1;
+    const uint64_t stride = (uint64_t)gridDim.x * kCostThreads;
+    for (uint64_t w = (uint64_t)blockIdx.x * kCostThreads + threadIdx.x; w < nwords; w += stride) {
+        uint32_t t[8];
+        eval_word(vec, nvec, uni, nuni, w, t);
+        if (n >= kLowBits) {
+            typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+            u32x4 *dst = reinterpret_cast<u32x4 *>(cost + (w << kLowBits));
+            dst[0] = u32x4{t[0], t[1], t[2], t[3]};
+            dst[1] = u32x4{t[4], t[5], t[6], t[7]};
+#pragma unroll
+            for (int r = 0; r < 8; ++r) tally(h, t[r]);
+        } else {
+            for (uint32_t z = 0; z < (uint32_t)N; ++z) {
+                const uint32_t v = (t[z >> 2] >> (8 * (z & 3))) & 0xFFu;
+                cost[z] = (uint8_t)v;
+                atomicAdd(h + v, 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < hist_len; k += kCostThreads) {
+        uint32_t s = 0;
+        for (int wv = 0; wv < kCostWaves; ++wv) s += lhist[wv][k];
+        block_hist[(size_t)blockIdx.x * hist_len + k] = s;
+    }
+}
+
+// hist[k] = sum over blocks of block_hist[b][k], fixed order.
+__global__ void hist_reduce_kernel(const uint32_t *__restrict__ block_hist, int nblocks,
+                                   int hist_len, unsigned long long *__restrict__ hist) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= hist_len) return;
+    unsigned long long s = 0;
+    for (int b = 0; b < nblocks; ++b) s += block_hist[(size_t)b * hist_len + k];
+    hist[k] = s;
+}
+
+// ---- many instances, histograms only ---------------------------------------
+struct HistInst {
+    uint32_t vec_off, nvec, uni_off, nuni;
+    int32_t n, m;
+    uint32_t pad0, pad1;
+};
+struct HistUnit {
+    uint32_t inst, word0, nwords, pad;
+};
+
+__global__ void __launch_bounds__(kCostThreads)
+hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restrict__ units,
+                    const ClauseRec *__restrict__ vec, const UniformRec *__restrict__ uni,
+                    unsigned long long *__restrict__ hists, int hist_stride) {
+    __shared__ uint32_t lhist[kCostWaves][256];
+    for (int i = threadIdx.x; i < kCostWaves * 256; i += kCostThreads) (&lhist[0][0])[i] = 0;
+    __syncthreads();
+    const HistUnit unit = units[blockIdx.x];
+    const HistInst in = insts[unit.inst];
+    uint32_t *h = lhist[threadIdx.x / kWave];
+    const uint32_t nbits = in.n >= kLowBits ? 32u : (1u << in.n);
+    for (uint32_t i = threadIdx.x; i < unit.nwords; i += kCostThreads) {
+        const uint64_t w = (uint64_t)unit.word0 + i;
+        uint32_t t[8];
+        eval_word(vec + in.vec_off, in.nvec, uni + in.uni_off, in.nuni, w, t);
+        if (nbits == 32u) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) tally(h, t[r]);
+        } else {
+            for (uint32_t z = 0; z < nbits; ++z) atomicAdd(h + ((t[z >> 2] >> (8 * (z & 3))) & 0xFFu), 1u);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k <= in.m; k += kCostThreads) {
+        uint32_t s = 0;
+        for (int wv = 0; wv < kCostWaves; ++wv) s += lhist[wv][k];
+        if (s) atomicAdd(hists + (size_t)unit.inst * hist_stride + k, (unsigned long long)s);
+    }
+}
+
+// ---- host launchers (arguments already validated) ---------------------------
+int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist,
+                      hipStream_t stream) {
+    DeviceInfo dev;
+    int st = device_info(&dev);
+    if (st) return st;
+    std::vector<ClauseRec> vec;
+    std::vector<UniformRec> uni;
+    pack_clauses(m, lits, vec, uni);
+    const uint64_t nwords = n >= kLowBits ? (1ull << (n - kLowBits)) : 1;
+    const uint64_t want = (nwords + kCostThreads - 1) / kCostThreads;
+    const int nblocks = (int)std::min<uint64_t>(want, (uint64_t)dev.num_cus * 8);
+    const int hist_len = m + 1;
+    const size_t rec_bytes = sizeof(ClauseRec) * vec.size() + sizeof(UniformRec) * (uni.size() + 1);
+    const size_t bh_bytes = sizeof(uint32_t) * (size_t)nblocks * hist_len;
+    void *scratch = nullptr;
+    GQ_HIP(hipMallocAsync(&scratch, rec_bytes + bh_bytes + 256, stream));
+    ClauseRec *d_vec = reinterpret_cast<ClauseRec *>(scratch);
+    UniformRec *d_uni = reinterpret_cast<UniformRec *>(d_vec + vec.size());
+    uint32_t *d_bh = reinterpret_cast<uint32_t *>(
+        (reinterpret_cast<uintptr_t>(d_uni + uni.size() + 1) + 255) & ~uintptr_t(255));
+    std::vector<char> staging(rec_bytes);
+    memcpy(staging.data(), vec.data(), sizeof(ClauseRec) * vec.size());
+    if (!uni.empty()) memcpy(staging.data() + sizeof(ClauseRec) * vec.size(), uni.data(), sizeof(UniformRec) * uni.size());
+    GQ_HIP(hipMemcpyAsync(scratch, staging.data(), rec_bytes, hipMemcpyHostToDevice, stream));
+    GQ_HIP(hipStreamSynchronize(stream));  // staging is host pageable memory owned here
+    ProfScope ps("cost_table", stream);
+    hipLaunchKernelGGL(cost_table_kernel, dim3(nblocks), dim3(kCostThreads), 0, stream, d_vec,
+                       (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len);
+    ps.end();
+    GQ_LAUNCH_CHECK();
+    if (hist) {
+        hipLaunchKernelGGL(hist_reduce_kernel, dim3(1), dim3(256), 0, stream, d_bh, nblocks, hist_len,
+                           reinterpret_cast<unsigned long long *>(hist));
+        GQ_LAUNCH_CHECK();
+    }
+    GQ_HIP(hipFreeAsync(scratch, stream));
+    return GQAOA_OK;
+}
+
+int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                        const int32_t *lits, uint64_t *hists, int hist_stride, hipStream_t stream) {
+    std::vector<ClauseRec> vec_all, vec;
+    std::vector<UniformRec> uni_all, uni;
+    std::vector<HistInst> insts(num_inst);
+    std::vector<HistUnit> units;
+    constexpr uint32_t kUnitWords = kCostThreads * 4;
+    size_t off = 0;
+    for (int i = 0; i < num_inst; ++i) {
+        pack_clauses(m_host[i], lits + 3 * off, vec, uni);
+        off += (size_t)m_host[i];
+        insts[i] = HistInst{(uint32_t)vec_all.size(), (uint32_t)vec.size(), (uint32_t)uni_all.size(),
+                            (uint32_t)uni.size(), n_host[i], m_host[i], 0u, 0u};
+        vec_all.insert(vec_all.end(), vec.begin(), vec.end());
+        uni_all.insert(uni_all.end(), uni.begin(), uni.end());
+        const uint64_t nwords = n_host[i] >= kLowBits ? (1ull << (n_host[i] - kLowBits)) : 1;
+        for (uint64_t w0 = 0; w0 < nwords; w0 += kUnitWords)
+            units.push_back(HistUnit{(uint32_t)i, (uint32_t)w0,
+                                     (uint32_t)std::min<uint64_t>(kUnitWords, nwords - w0), 0u});
+    }
+    if (vec_all.empty()) vec_all.push_back(ClauseRec{0u, 0u, 0ull, 0ull, 0ull});
+    if (uni_all.empty()) uni_all.push_back(UniformRec{0ull, 0ull});
+    const size_t b_inst = sizeof(HistInst) * insts.size();
+    const size_t b_unit = sizeof(HistUnit) * units.size();
+    const size_t b_vec = sizeof(ClauseRec) * vec_all.size();
+    const size_t b_uni = sizeof(UniformRec) * uni_all.size();
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t total = al(b_inst) + al(b_unit) + al(b_vec) + al(b_uni);
+    std::vector<char> staging(total, 0);
+    size_t o_inst = 0, o_unit = al(b_inst), o_vec = o_unit + al(b_unit), o_uni = o_vec + al(b_vec);
+    memcpy(staging.data() + o_inst, insts.data(), b_inst);
+    memcpy(staging.data() + o_unit, units.data(), b_unit);
+    memcpy(staging.data() + o_vec, vec_all.data(), b_vec);
+    memcpy(staging.data() + o_uni, uni_all.data(), b_uni);
+    void *scratch = nullptr;
+    GQ_HIP(hipMallocAsync(&scratch, total, stream));
+    char *base = reinterpret_cast<char *>(scratch);
+    GQ_HIP(hipMemcpyAsync(scratch, staging.data(), total, hipMemcpyHostToDevice, stream));
+    GQ_HIP(hipStreamSynchronize(stream));
+    GQ_HIP(hipMemsetAsync(hists, 0, sizeof(uint64_t) * (size_t)num_inst * hist_stride, stream));
+    hipLaunchKernelGGL(hist_batched_kernel, dim3((unsigned)units.size()), dim3(kCostThreads), 0,
+                       stream, reinterpret_cast<const HistInst *>(base + o_inst),
+                       reinterpret_cast<const HistUnit *>(base + o_unit),
+                       reinterpret_cast<const ClauseRec *>(base + o_vec),
+                       reinterpret_cast<const UniformRec *>(base + o_uni),
+                       reinterpret_cast<unsigned long long *>(hists), hist_stride);
+    GQ_LAUNCH_CHECK();
+    GQ_HIP(hipFreeAsync(scratch, stream));
+    return GQAOA_OK;
+}
+
+}  // namespace gqaoa

@@ -1,0 +1,96 @@
+// Internal helpers shared by the libgqaoa translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/gqaoa.h"
+
+namespace gqaoa {
+
+// ---- status / error reporting ------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+int fail(int status, const char *fmt, ...);
+
+#define GQ_HIP(call)                                                             \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess)                                                    \
+            return ::gqaoa::fail(GQAOA_EHIP, "%s failed: %s (%s:%d)", #call,      \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);     \
+    } while (0)
+
+#define GQ_LAUNCH_CHECK()                                                        \
+    do {                                                                         \
+        hipError_t e_ = hipGetLastError();                                       \
+        if (e_ != hipSuccess)                                                    \
+            return ::gqaoa::fail(GQAOA_EHIP, "kernel launch failed: %s (%s:%d)",  \
+                                 hipGetErrorString(e_), __FILE__, __LINE__);     \
+    } while (0)
+
+// Optional event timing of selected launches (see gqaoa_profile_enable).
+bool prof_on();
+struct ProfScope {
+    // records a start event on construction and an end event on end()
+    ProfScope(const char *name, hipStream_t st);
+    void end();
+    const char *name_;
+    hipStream_t st_;
+    hipEvent_t e0_ = nullptr;
+};
+void prof_collect();  // after a stream synchronize: fold finished pairs into totals
+
+// Device properties the launch shapes depend on (cached per device).
+struct DeviceInfo {
+    int device = -1;
+    int num_cus = 0;
+    char arch[64] = {0};
+};
+int device_info(DeviceInfo *out);
+
+// ---- device-side helpers -----------------------------------------------------
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Fixed-order reduction of R doubles across a block of kThreads threads.
+// Every thread passes its R values; thread 0 receives the block sums.
+template <int R, int kThreads>
+__device__ __forceinline__ void block_sum(double (&v)[R], double *lds /* R*kThreads/64 */) {
+    constexpr int kWaves = kThreads / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = wave_sum(v[r]);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[wave * R + r] = v[r];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double s = 0.0;
+            for (int w = 0; w < kWaves; ++w) s += lds[w * R + r];
+            v[r] = s;
+        }
+    }
+}
+
+}  // namespace gqaoa

@@ -1,0 +1,903 @@
+// Statevector G-QAOA rounds (Eq. (3)) and their adjoint, streamed from HBM.
+//
+// One round is exp(-i gamma_j H_P) followed by the Grover mixer
+// exp(-i beta_j |s><s|) = I + (e^{-i beta_j} - 1)|s><s| (Eq. (2)). The mixer
+// adds the same scalar to every amplitude, delta_j = (e^{-i beta_j}-1) S_j / 2^n
+// with S_j = sum_z phi_z, so it is applied lazily: pass j reads psi (holding
+// phi_{j-1}) and the device scalar delta_{j-1}, forms psi' = phi_{j-1} + delta_{j-1}
+// (the true state after round j-1), reads out P_sol / E (Eq. (4)) / norm of
+// psi', multiplies by the phase LUT entry e^{-i gamma_j C(z)} and stores
+// phi_j. One pass = one read and one write of psi plus one byte of cost per
+// amplitude. Block partial sums are reduced in a fixed order by a one-block
+// finalize kernel per instance, which also forms delta_j on the device, so no
+// value crosses to the host between rounds.
+//
+// The reverse sweep of the adjoint gradient uses the same streaming shape:
+// pass k reads lambda_k, phi_k and C, forms mu_k = lambda_k + eps_k
+// (eps_k = (e^{+i beta_k}-1) sum lambda_k / 2^n), accumulates
+// G_k = sum conj(mu) C phi (dP/dgamma_k = 2 Im G_k), and writes
+// lambda_{k-1} = e^{+i gamma_k C} mu_k together with its sum.
+//
+// All kernels take an instance index in blockIdx.y so that many equally
+// sized instances stream in one launch.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+namespace gqaoa {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kSvThreads = 256;
+constexpr int kFwdR = 7;   // S.re, S.im, psol, energy, norm, T.re, T.im (T = sum over target level)
+constexpr int kRevR = 4;   // L.re, L.im (sum of lambda_{k-1}), G.re, G.im
+
+template <typename T>
+struct Cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {  // conj(a) * b
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+
+// ---- vectorized amplitude and cost I/O ---------------------------------------
+template <typename T, int AMP>
+struct AmpIO;
+
+template <int AMP>
+struct AmpIO<float, AMP> {
+    static_assert(AMP >= 2 && AMP % 2 == 0, "complex64 chunks hold pairs of amplitudes");
+    static __device__ __forceinline__ void load(const void *p, Cx<float> (&a)[AMP]) {
+        const f32x4 *q = reinterpret_cast<const f32x4 *>(p);
+#pragma unroll
+        for (int i = 0; i < AMP / 2; ++i) {
+            const f32x4 v = __builtin_nontemporal_load(q + i);
+            a[2 * i] = {v.x, v.y};
+            a[2 * i + 1] = {v.z, v.w};
+        }
+    }
+    static __device__ __forceinline__ void store(void *p, const Cx<float> (&a)[AMP]) {
+        f32x4 *q = reinterpret_cast<f32x4 *>(p);
+#pragma unroll
+        for (int i = 0; i < AMP / 2; ++i)
+            __builtin_nontemporal_store(f32x4{a[2 * i].re, a[2 * i].im, a[2 * i + 1].re, a[2 * i + 1].im}, q + i);
+    }
+};
+
+template <int AMP>
+struct AmpIO<double, AMP> {
+    static __device__ __forceinline__ void load(const void *p, Cx<double> (&a)[AMP]) {
+        const f64x2 *q = reinterpret_cast<const f64x2 *>(p);
+#pragma unroll
+        for (int i = 0; i < AMP; ++i) {
+            const f64x2 v = __builtin_nontemporal_load(q + i);
+            a[i] = {v.x, v.y};
+        }
+    }
+    static __device__ __forceinline__ void store(void *p, const Cx<double> (&a)[AMP]) {
+        f64x2 *q = reinterpret_cast<f64x2 *>(p);
+#pragma unroll
+        for (int i = 0; i < AMP; ++i) __builtin_nontemporal_store(f64x2{a[i].re, a[i].im}, q + i);
+    }
+};
+
+template <int AMP>
+__device__ __forceinline__ void load_costs(const uint8_t *p, uint32_t (&c)[AMP]) {
+    if constexpr (AMP == 1) {
+        c[0] = p[0];
+    } else if constexpr (AMP == 2) {
+        const uint32_t v = *reinterpret_cast<const uint16_t *>(p);
+        c[0] = v & 0xFFu;
+        c[1] = v >> 8;
+    } else if constexpr (AMP == 4) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = (v >> (8 * i)) & 0xFFu;
+    } else if constexpr (AMP == 8) {
+        const uint64_t v = *reinterpret_cast<const uint64_t *>(p);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c[i] = (uint32_t)(v >> (8 * i)) & 0xFFu;
+    } else {
+        static_assert(AMP == 16, "unsupported chunk");
+        const u32x4 v = *reinterpret_cast<const u32x4 *>(p);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) c[i] = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+    }
+}
+
+// Accumulator type for per-tile partial sums (float tiles are short).
+template <typename T>
+struct Acc;
+template <>
+struct Acc<float> {
+    using t = float;
+};
+template <>
+struct Acc<double> {
+    using t = double;
+};
+
+// ---- forward pass ---------------------------------------------------------------
+struct FwdArgs {
+    const uint8_t *cost;     // [inst][N]
+    const void *psi_in;      // [inst][N] complex T (ignored if init_uniform)
+    void *psi_out;           // [inst][N] complex T (may equal psi_in)
+    uint64_t N;
+    const void *lut;         // [inst][lut_stride] complex T, e^{-i gamma C}; null: no phase
+    int lut_stride;
+    int lut_len;
+    const double *delta;     // [inst][delta_stride] complex double added before the phase; null: none
+    int delta_stride;
+    int init_uniform;
+    double init_amp;
+    const int32_t *target;   // [inst]
+    double *partials;        // [inst][gridDim.x][kFwdR]
+};
+
+template <typename T, bool PHASE, bool WRITE, int AMP, int UNROLL>
+__global__ void __launch_bounds__(kSvThreads) sv_forward_kernel(FwdArgs a) {
+    __shared__ Cx<T> lut_s[256];
+    __shared__ double red_s[kFwdR * kSvThreads / kWave];
+    const int inst = blockIdx.y;
+    const uint64_t ioff = (uint64_t)inst * a.N;
+    if constexpr (PHASE) {
+        const Cx<T> *lut = reinterpret_cast<const Cx<T> *>(a.lut) + (size_t)inst * a.lut_stride;
+        for (int i = threadIdx.x; i < a.lut_len; i += kSvThreads) lut_s[i] = lut[i];
+        __syncthreads();
+    }
+    const uint32_t target = (uint32_t)a.target[inst];
+    Cx<T> dl{T(0), T(0)};
+    if (a.delta) {
+        const double *d = a.delta + (size_t)inst * a.delta_stride;
+        dl = {T(d[0]), T(d[1])};
+    }
+    const uint8_t *cost = a.cost + ioff;
+    const Cx<T> *src = reinterpret_cast<const Cx<T> *>(a.psi_in) + ioff;
+    Cx<T> *dst = reinterpret_cast<Cx<T> *>(a.psi_out) + ioff;
+    const T amp0 = T(a.init_amp);
+
+    double accSr = 0, accSi = 0, accP = 0, accE = 0, accN = 0, accTr = 0, accTi = 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave = ((uint64_t)blockIdx.x * kSvThreads + threadIdx.x) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kSvThreads / kWave;
+    constexpr uint64_t kTile = (uint64_t)kWave * AMP * UNROLL;
+    for (uint64_t base = wave * kTile; base < a.N; base += nwaves * kTile) {
+        uint32_t c[UNROLL][AMP];
+        Cx<T> v[UNROLL][AMP];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
+            if (idx < a.N) {
+                load_costs<AMP>(cost + idx, c[u]);
+                if (!a.init_uniform) AmpIO<T, AMP>::load(src + idx, v[u]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < AMP; ++i) c[u][i] = 0xFFFFu;  // never a target level
+            }
+        }
+        typename Acc<T>::t sSr = 0, sSi = 0, sP = 0, sE = 0, sN = 0, sTr = 0, sTi = 0;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
+            const bool ok = idx < a.N;
+#pragma unroll
+            for (int i = 0; i < AMP; ++i) {
+                Cx<T> x = a.init_uniform ? Cx<T>{amp0, T(0)} : v[u][i];
+                x.re += dl.re;
+                x.im += dl.im;
+                const T pr = ok ? x.re * x.re + x.im * x.im : T(0);
+                sN += pr;
+                sE += T(c[u][i]) * pr;
+                const bool hit = c[u][i] == target;
+                sP += hit ? pr : T(0);
+                sTr += hit ? x.re : T(0);
+                sTi += hit ? x.im : T(0);
+                if constexpr (PHASE) {
+                    x = cmul(lut_s[ok ? c[u][i] : 0], x);
+                    sSr += ok ? x.re : T(0);
+                    sSi += ok ? x.im : T(0);
+                }
+                v[u][i] = x;
+            }
+        }
+        accSr += sSr; accSi += sSi; accP += sP; accE += sE; accN += sN; accTr += sTr; accTi += sTi;
+        if constexpr (WRITE) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
+                if (idx < a.N) AmpIO<T, AMP>::store(dst + idx, v[u]);
+            }
+        }
+    }
+    double r[kFwdR] = {accSr, accSi, accP, accE, accN, accTr, accTi};
+    block_sum<kFwdR, kSvThreads>(r, red_s);
+    if (threadIdx.x == 0) {
+        double *out = a.partials + ((size_t)inst * gridDim.x + blockIdx.x) * kFwdR;
+#pragma unroll
+        for (int k = 0; k < kFwdR; ++k) out[k] = r[k];
+    }
+}
+
+// ---- reverse (adjoint) pass -------------------------------------------------------
+struct RevArgs {
+    const uint8_t *cost;
+    const void *phi;        // phi_k, [inst][N]
+    const void *lam_in;     // lambda_k, [inst][N]; null on the first reverse step
+    void *lam_out;          // lambda_{k-1}, may equal lam_in
+    uint64_t N;
+    const void *lut;        // forward LUT of round k (the pass uses its conjugate)
+    int lut_stride;
+    int lut_len;
+    const double *eps;      // [inst][eps_stride] complex: eps_k
+    int eps_stride;
+    const double *delta_p;  // [inst][delta_stride] complex delta_p (first step only)
+    int delta_stride;
+    const int32_t *target;
+    double *partials;       // [inst][gridDim.x][kRevR]
+};
+
+template <typename T, bool FIRST, bool WRITE, int AMP, int UNROLL>
+__global__ void __launch_bounds__(kSvThreads) sv_reverse_kernel(RevArgs a) {
+    __shared__ Cx<T> lut_s[256];
+    __shared__ double red_s[kRevR * kSvThreads / kWave];
+    const int inst = blockIdx.y;
+    const uint64_t ioff = (uint64_t)inst * a.N;
+    {
+        const Cx<T> *lut = reinterpret_cast<const Cx<T> *>(a.lut) + (size_t)inst * a.lut_stride;
+        for (int i = threadIdx.x; i < a.lut_len; i += kSvThreads) lut_s[i] = lut[i];
+        __syncthreads();
+    }
+    const uint32_t target = (uint32_t)a.target[inst];
+    const double *e = a.eps + (size_t)inst * a.eps_stride;
+    const Cx<T> eps{T(e[0]), T(e[1])};
+    Cx<T> dp{T(0), T(0)};
+    if constexpr (FIRST) {
+        const double *d = a.delta_p + (size_t)inst * a.delta_stride;
+        dp = {T(d[0]), T(d[1])};
+    }
+    const uint8_t *cost = a.cost + ioff;
+    const Cx<T> *phi = reinterpret_cast<const Cx<T> *>(a.phi) + ioff;
+    const Cx<T> *lin = reinterpret_cast<const Cx<T> *>(a.lam_in) + ioff;
+    Cx<T> *lout = reinterpret_cast<Cx<T> *>(a.lam_out) + ioff;
+
+    double accLr = 0, accLi = 0, accGr = 0, accGi = 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave = ((uint64_t)blockIdx.x * kSvThreads + threadIdx.x) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kSvThreads / kWave;
+    constexpr uint64_t kTile = (uint64_t)kWave * AMP * UNROLL;
+    for (uint64_t base = wave * kTile; base < a.N; base += nwaves * kTile) {
+        uint32_t c[UNROLL][AMP];
+        Cx<T> f[UNROLL][AMP], l[UNROLL][AMP];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
+            if (idx < a.N) {
+                load_costs<AMP>(cost + idx, c[u]);
+                AmpIO<T, AMP>::load(phi + idx, f[u]);
+                if constexpr (!FIRST) AmpIO<T, AMP>::load(lin + idx, l[u]);
+            }
+        }
+        typename Acc<T>::t sLr = 0, sLi = 0, sGr = 0, sGi = 0;
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
+            if (idx < a.N) {
+#pragma unroll
+                for (int i = 0; i < AMP; ++i) {
+                    Cx<T> lam;
+                    if constexpr (FIRST) {
+                        const bool hit = c[u][i] == target;
+                        lam = {hit ? f[u][i].re + dp.re : T(0), hit ? f[u][i].im + dp.im : T(0)};
+                    } else {
+                        lam = l[u][i];
+                    }
+                    const Cx<T> mu{lam.re + eps.re, lam.im + eps.im};
+                    const Cx<T> g = cmulc(mu, f[u][i]);
+                    const T cc = T(c[u][i]);
+                    sGr += cc * g.re;
+                    sGi += cc * g.im;
+                    const Cx<T> nl = cmulc(lut_s[c[u][i]], mu);  // e^{+i gamma C} mu
+                    sLr += nl.re;
+                    sLi += nl.im;
+                    l[u][i] = nl;
+                }
+            }
+        }
+        accLr += sLr; accLi += sLi; accGr += sGr; accGi += sGi;
+        if constexpr (WRITE) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
+                if (idx < a.N) AmpIO<T, AMP>::store(lout + idx, l[u]);
+            }
+        }
+    }
+    double r[kRevR] = {accLr, accLi, accGr, accGi};
+    block_sum<kRevR, kSvThreads>(r, red_s);
+    if (threadIdx.x == 0) {
+        double *out = a.partials + ((size_t)inst * gridDim.x + blockIdx.x) * kRevR;
+#pragma unroll
+        for (int k = 0; k < kRevR; ++k) out[k] = r[k];
+    }
+}
+
+// ---- finalizers (one block per instance, fixed-order sums) ------------------------
+template <int R>
+__device__ __forceinline__ void reduce_partials(const double *p, int nblocks, double (&r)[R],
+                                                double *lds) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) r[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kSvThreads)
+#pragma unroll
+        for (int k = 0; k < R; ++k) r[k] += p[(size_t)b * R + k];
+    block_sum<R, kSvThreads>(r, lds);
+}
+
+struct FinArgs {
+    const double *partials;  // [inst][nblocks][kFwdR]
+    int nblocks;
+    double inv_N;
+    // per instance (strided by the *_stride fields, all in doubles)
+    const double *mixf;      // e^{-i beta_j} - 1 for this round; null in the last pass
+    int mixf_stride;
+    double *delta_out;       // delta_j
+    double *S_out;           // S_j
+    double *readout_out;     // psol, E, norm of the state before this pass's phase
+    double *T_out;           // sum over the target level (last pass only)
+    int stride;              // stride for delta_out/S_out/T_out per instance
+    int readout_stride;
+    // adjoint set-up after the last forward pass: eps_p and dbeta_p
+    const double *mixb;      // e^{+i beta_p} - 1, null: skip
+    const double *ebeta;     // e^{-i beta_p}
+    const double *S_p;       // S_p
+    double *eps_out;
+    double *dbeta_out;
+    int mix_stride;          // doubles per instance in mixb / ebeta (2p)
+    int grad_stride;         // doubles per instance in dbeta (p)
+};
+
+__global__ void __launch_bounds__(kSvThreads) sv_finalize_kernel(FinArgs a) {
+    __shared__ double lds[kFwdR * kSvThreads / kWave];
+    const int inst = blockIdx.x;
+    double r[kFwdR];
+    reduce_partials<kFwdR>(a.partials + (size_t)inst * a.nblocks * kFwdR, a.nblocks, r, lds);
+    if (threadIdx.x != 0) return;
+    if (a.readout_out) {
+        double *ro = a.readout_out + (size_t)inst * a.readout_stride;
+        ro[0] = r[2];
+        ro[1] = r[3];
+        ro[2] = r[4];
+    }
+    if (a.mixf) {
+        const double *mf = a.mixf + (size_t)inst * a.mixf_stride;
+        const double sr = r[0] * a.inv_N, si = r[1] * a.inv_N;
+        double *d = a.delta_out + (size_t)inst * a.stride;
+        d[0] = mf[0] * sr - mf[1] * si;
+        d[1] = mf[0] * si + mf[1] * sr;
+        if (a.S_out) {
+            double *s = a.S_out + (size_t)inst * a.stride;
+            s[0] = r[0];
+            s[1] = r[1];
+        }
+    }
+    if (a.T_out) {
+        double *t = a.T_out + (size_t)inst * a.stride;
+        t[0] = r[5];
+        t[1] = r[6];
+    }
+    if (a.mixb) {
+        // eps_p = (e^{+i beta_p}-1) sum(lambda_p)/N, sum(lambda_p) = T
+        const double *mb = a.mixb + (size_t)inst * a.mix_stride;
+        const double tr = r[5], ti = r[6];
+        double *e = a.eps_out + (size_t)inst * 2;
+        e[0] = (mb[0] * tr - mb[1] * ti) * a.inv_N;
+        e[1] = (mb[0] * ti + mb[1] * tr) * a.inv_N;
+        // dbeta_p = 2 Re(-i e^{-i beta_p} conj(T) S_p) / N
+        const double *eb = a.ebeta + (size_t)inst * a.mix_stride;
+        const double *sp = a.S_p + (size_t)inst * a.stride;
+        const double xr = tr * sp[0] + ti * sp[1], xi = tr * sp[1] - ti * sp[0];  // conj(T) S
+        const double yr = eb[0] * xr - eb[1] * xi, yi = eb[0] * xi + eb[1] * xr;  // e^{-i b} x
+        a.dbeta_out[(size_t)inst * a.grad_stride] = 2.0 * yi * a.inv_N;          // Re(-i y) = Im y
+    }
+}
+
+struct RevFinArgs {
+    const double *partials;  // [inst][nblocks][kRevR]
+    int nblocks;
+    double inv_N;
+    double *dgamma_k;        // [inst * grad_stride]
+    // for k > 1: eps_{k-1} and dbeta_{k-1}
+    const double *mixb_km1;  // e^{+i beta_{k-1}} - 1
+    const double *ebeta_km1; // e^{-i beta_{k-1}}
+    const double *S_km1;     // S_{k-1}
+    int S_stride;
+    double *eps_out;
+    double *dbeta_km1;
+    int grad_stride;
+};
+
+__global__ void __launch_bounds__(kSvThreads) sv_rev_finalize_kernel(RevFinArgs a) {
+    __shared__ double lds[kRevR * kSvThreads / kWave];
+    const int inst = blockIdx.x;
+    double r[kRevR];
+    reduce_partials<kRevR>(a.partials + (size_t)inst * a.nblocks * kRevR, a.nblocks, r, lds);
+    if (threadIdx.x != 0) return;
+    a.dgamma_k[(size_t)inst * a.grad_stride] = 2.0 * r[3];
+    if (a.mixb_km1) {
+        const double *mb = a.mixb_km1 + (size_t)inst * a.grad_stride * 2;
+        const double lr = r[0], li = r[1];
+        double *e = a.eps_out + (size_t)inst * 2;
+        e[0] = (mb[0] * lr - mb[1] * li) * a.inv_N;
+        e[1] = (mb[0] * li + mb[1] * lr) * a.inv_N;
+        const double *eb = a.ebeta_km1 + (size_t)inst * a.grad_stride * 2;
+        const double *sp = a.S_km1 + (size_t)inst * a.S_stride;
+        const double xr = lr * sp[0] + li * sp[1], xi = lr * sp[1] - li * sp[0];
+        const double yi = eb[0] * xi + eb[1] * xr;
+        a.dbeta_km1[(size_t)inst * a.grad_stride] = 2.0 * yi * a.inv_N;
+    }
+}
+
+// ---- launch shapes ------------------------------------------------------------------
+struct PassShape {
+    int amp, unroll, blocks_x;
+};
+
+constexpr int kMaxPassBlocks = 4096;  // partial-sum rows per launch (all instances)
+
+static PassShape pass_shape(uint64_t N, int num_inst, int dtype, const DeviceInfo &dev) {
+    PassShape s;
+    if (dtype == GQAOA_C64) {
+        s.amp = 4;
+        s.unroll = 4;
+        if (N < (uint64_t)kWave * 16) { s.amp = 2; s.unroll = 1; }
+    } else {
+        s.amp = 2;
+        s.unroll = 4;
+        if (N < (uint64_t)kWave * 8) { s.amp = 1; s.unroll = 1; }
+    }
+    const uint64_t per_block = (uint64_t)kSvThreads * s.amp * s.unroll;
+    const uint64_t want = (N + per_block - 1) / per_block;
+    const uint64_t cap = std::max<uint64_t>(1, (uint64_t)std::min(kMaxPassBlocks, dev.num_cus * 8) / num_inst);
+    s.blocks_x = (int)std::max<uint64_t>(1, std::min(want, cap));
+    return s;
+}
+
+template <typename T, bool PHASE, bool WRITE>
+static void launch_fwd_t(const PassShape &s, int num_inst, const FwdArgs &a, hipStream_t st) {
+    const dim3 grid(s.blocks_x, num_inst), block(kSvThreads);
+    if constexpr (sizeof(T) == 4) {
+        if (s.amp == 4) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 4, 4>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 1>), grid, block, 0, st, a);
+    } else {
+        if (s.amp == 2) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 4>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 1>), grid, block, 0, st, a);
+    }
+}
+
+static void launch_fwd(int dtype, bool phase, bool write, const PassShape &s, int num_inst,
+                       const FwdArgs &a, hipStream_t st) {
+    if (dtype == GQAOA_C64) {
+        if (phase) launch_fwd_t<float, true, true>(s, num_inst, a, st);
+        else if (write) launch_fwd_t<float, false, true>(s, num_inst, a, st);
+        else launch_fwd_t<float, false, false>(s, num_inst, a, st);
+    } else {
+        if (phase) launch_fwd_t<double, true, true>(s, num_inst, a, st);
+        else if (write) launch_fwd_t<double, false, true>(s, num_inst, a, st);
+        else launch_fwd_t<double, false, false>(s, num_inst, a, st);
+    }
+}
+
+template <typename T, bool FIRST, bool WRITE>
+static void launch_rev_t(const PassShape &s, int num_inst, const RevArgs &a, hipStream_t st) {
+    const dim3 grid(s.blocks_x, num_inst), block(kSvThreads);
+    if constexpr (sizeof(T) == 4) {
+        if (s.amp == 4) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 4, 4>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 1>), grid, block, 0, st, a);
+    } else {
+        if (s.amp == 2) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 4>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 1>), grid, block, 0, st, a);
+    }
+}
+
+static void launch_rev(int dtype, bool first, bool write, const PassShape &s, int num_inst,
+                       const RevArgs &a, hipStream_t st) {
+    if (dtype == GQAOA_C64) {
+        if (first) {
+            if (write) launch_rev_t<float, true, true>(s, num_inst, a, st);
+            else launch_rev_t<float, true, false>(s, num_inst, a, st);
+        } else {
+            if (write) launch_rev_t<float, false, true>(s, num_inst, a, st);
+            else launch_rev_t<float, false, false>(s, num_inst, a, st);
+        }
+    } else {
+        if (first) {
+            if (write) launch_rev_t<double, true, true>(s, num_inst, a, st);
+            else launch_rev_t<double, true, false>(s, num_inst, a, st);
+        } else {
+            if (write) launch_rev_t<double, false, true>(s, num_inst, a, st);
+            else launch_rev_t<double, false, false>(s, num_inst, a, st);
+        }
+    }
+}
+
+// ---- workspace layout ---------------------------------------------------------------
+// Small tables first (per instance), then the state slots used by the adjoint.
+struct SvLayout {
+    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, target, partials;
+    size_t slots, slot_bytes, nslots, total;
+};
+
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static SvLayout sv_layout(int num_inst, int n, int p, int dtype, int ckpt_every, bool grad) {
+    SvLayout L{};
+    const size_t cs = dtype == GQAOA_C64 ? 8 : 16;
+    const size_t I = (size_t)num_inst;
+    const size_t P = (size_t)std::max(p, 1);
+    size_t o = 0;
+    L.lut = o;      o += al256(I * P * 256 * cs);
+    L.mixf = o;     o += al256(I * P * 16);
+    L.mixb = o;     o += al256(I * P * 16);
+    L.ebeta = o;    o += al256(I * P * 16);
+    L.delta = o;    o += al256(I * (P + 1) * 16);
+    L.S = o;        o += al256(I * (P + 1) * 16);
+    L.readout = o;  o += al256(I * (P + 1) * 24);
+    L.T = o;        o += al256(I * 16);
+    L.eps = o;      o += al256(I * 16);
+    L.dbeta = o;    o += al256(I * P * 8);
+    L.dgamma = o;   o += al256(I * P * 8);
+    L.target = o;   o += al256(I * 4);
+    L.partials = o; o += al256(std::max<size_t>(kMaxPassBlocks, I) * kFwdR * 8);
+    L.slots = o;
+    L.slot_bytes = al256(I * ((size_t)1 << n) * cs);
+    L.nslots = 0;
+    if (grad) {
+        const int c = (ckpt_every <= 0 || ckpt_every >= p) ? p : ckpt_every;
+        const int nseg = (p + c - 1) / c;
+        L.nslots = (size_t)(nseg - 1) /*checkpoints*/ + (size_t)c /*segment*/ +
+                   (nseg > 1 ? 1 : 0) /*working*/ + 1 /*lambda*/;
+    }
+    L.total = o + L.nslots * L.slot_bytes;
+    return L;
+}
+
+size_t sv_workspace_bytes(int num_inst, int n, int p, int dtype, int ckpt_every, bool grad) {
+    return sv_layout(num_inst, n, p, dtype, ckpt_every, grad).total;
+}
+
+// Host tables: phase LUTs e^{-i gamma_j k} (k = 0..m, gamma_j k reduced mod 2 pi in
+// double, rounded once to the state's precision), mixer factors per round.
+static void build_tables(int num_inst, const int32_t *m_of, int p, const double *beta,
+                         const double *gamma, int dtype, std::vector<char> &lut,
+                         std::vector<double> &mixf, std::vector<double> &mixb,
+                         std::vector<double> &ebeta) {
+    const size_t cs = dtype == GQAOA_C64 ? 8 : 16;
+    lut.assign((size_t)num_inst * p * 256 * cs, 0);
+    mixf.assign((size_t)num_inst * p * 2, 0.0);
+    mixb.assign((size_t)num_inst * p * 2, 0.0);
+    ebeta.assign((size_t)num_inst * p * 2, 0.0);
+    const double two_pi = 2.0 * M_PI;
+    for (int i = 0; i < num_inst; ++i) {
+        for (int j = 0; j < p; ++j) {
+            const double g = gamma[(size_t)i * p + j], b = beta[(size_t)i * p + j];
+            for (int k = 0; k <= m_of[i]; ++k) {
+                const double ang = std::fmod(g * (double)k, two_pi);
+                const double re = std::cos(ang), im = -std::sin(ang);
+                const size_t e = ((size_t)i * p + j) * 256 + k;
+                if (dtype == GQAOA_C64) {
+                    float *f = reinterpret_cast<float *>(lut.data()) + 2 * e;
+                    f[0] = (float)re;
+                    f[1] = (float)im;
+                } else {
+                    double *d = reinterpret_cast<double *>(lut.data()) + 2 * e;
+                    d[0] = re;
+                    d[1] = im;
+                }
+            }
+            const size_t q = ((size_t)i * p + j) * 2;
+            mixf[q] = std::cos(b) - 1.0;
+            mixf[q + 1] = -std::sin(b);
+            mixb[q] = std::cos(b) - 1.0;
+            mixb[q + 1] = std::sin(b);
+            ebeta[q] = std::cos(b);
+            ebeta[q + 1] = -std::sin(b);
+        }
+    }
+}
+
+static int upload(void *dst, const void *src, size_t bytes, hipStream_t st) {
+    if (!bytes) return GQAOA_OK;
+    GQ_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    return GQAOA_OK;
+}
+
+// ---- forward evolution (used by evolve and by the adjoint) -----------------------------
+struct FwdPlan {
+    int dtype, num_inst, n, p;
+    uint64_t N;
+    char *ws;
+    SvLayout L;
+    PassShape shape;
+    const uint8_t *cost;
+};
+
+static FwdArgs base_fwd_args(const FwdPlan &P) {
+    FwdArgs a{};
+    a.cost = P.cost;
+    a.N = P.N;
+    a.lut_stride = P.p * 256;
+    a.lut_len = 256;
+    a.delta_stride = 2 * (P.p + 1);
+    a.init_amp = 1.0 / std::sqrt((double)P.N);
+    a.target = reinterpret_cast<const int32_t *>(P.ws + P.L.target);
+    a.partials = reinterpret_cast<double *>(P.ws + P.L.partials);
+    return a;
+}
+
+static FinArgs base_fin_args(const FwdPlan &P) {
+    FinArgs f{};
+    f.partials = reinterpret_cast<double *>(P.ws + P.L.partials);
+    f.nblocks = P.shape.blocks_x;
+    f.inv_N = 1.0 / (double)P.N;
+    f.mixf_stride = 2 * P.p;
+    f.stride = 2 * (P.p + 1);
+    f.readout_stride = 3 * (P.p + 1);
+    f.mix_stride = 2 * P.p;
+    f.grad_stride = P.p;
+    return f;
+}
+
+// One forward round j (1-based): psi_in holds phi_{j-1} (or |s> if j == 1 and
+// uniform), psi_out receives phi_j. With finalize, writes delta_j, S_j and the
+// readout of round j-1.
+static int forward_round(const FwdPlan &P, int j, const void *psi_in, void *psi_out, bool uniform,
+                         bool finalize, hipStream_t st) {
+    const size_t cs = P.dtype == GQAOA_C64 ? 8 : 16;
+    FwdArgs a = base_fwd_args(P);
+    a.psi_in = psi_in;
+    a.psi_out = psi_out;
+    a.lut = P.ws + P.L.lut + (size_t)(j - 1) * 256 * cs;
+    a.delta = j > 1 ? reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * (j - 1) : nullptr;
+    a.init_uniform = uniform ? 1 : 0;
+    ProfScope ps(P.dtype == GQAOA_C64 ? "sv_round_c64" : "sv_round_c128", st);
+    launch_fwd(P.dtype, true, true, P.shape, P.num_inst, a, st);
+    ps.end();
+    GQ_LAUNCH_CHECK();
+    if (finalize) {
+        FinArgs f = base_fin_args(P);
+        f.mixf = reinterpret_cast<double *>(P.ws + P.L.mixf) + 2 * (j - 1);
+        f.delta_out = reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * j;
+        f.S_out = reinterpret_cast<double *>(P.ws + P.L.S) + 2 * j;
+        f.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * (j - 1);
+        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, f);
+        GQ_LAUNCH_CHECK();
+    }
+    return GQAOA_OK;
+}
+
+// Final pass: psi_out = phi_p + delta_p (if write), readout of round p.
+static int final_pass(const FwdPlan &P, const void *psi_in, void *psi_out, bool uniform, bool write,
+                      hipStream_t st) {
+    FwdArgs a = base_fwd_args(P);
+    a.psi_in = psi_in;
+    a.psi_out = psi_out;
+    a.lut = nullptr;
+    a.delta = P.p > 0 ? reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * P.p : nullptr;
+    a.init_uniform = uniform ? 1 : 0;
+    launch_fwd(P.dtype, false, write, P.shape, P.num_inst, a, st);
+    GQ_LAUNCH_CHECK();
+    FinArgs f = base_fin_args(P);
+    f.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * P.p;
+    hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, f);
+    GQ_LAUNCH_CHECK();
+    return GQAOA_OK;
+}
+
+static int prepare_plan(FwdPlan &P, int num_inst, int n, const int32_t *m_of, const uint8_t *cost,
+                        int p, const double *beta, const double *gamma, int dtype,
+                        const int32_t *targets, void *ws, int ckpt_every, bool grad,
+                        hipStream_t st, std::vector<char> &keep_lut, std::vector<double> &keep_f,
+                        std::vector<double> &keep_b, std::vector<double> &keep_e,
+                        std::vector<int32_t> &keep_t) {
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    P.dtype = dtype;
+    P.num_inst = num_inst;
+    P.n = n;
+    P.p = p;
+    P.N = 1ull << n;
+    P.ws = reinterpret_cast<char *>(ws);
+    P.L = sv_layout(num_inst, n, p, dtype, ckpt_every, grad);
+    P.shape = pass_shape(P.N, num_inst, dtype, dev);
+    P.cost = cost;
+    if (p > 0) {
+        build_tables(num_inst, m_of, p, beta, gamma, dtype, keep_lut, keep_f, keep_b, keep_e);
+        // the LUT block is laid out [inst][p][256]; the kernels index it with lut_stride p*256
+        if ((s = upload(P.ws + P.L.lut, keep_lut.data(), keep_lut.size(), st))) return s;
+        if ((s = upload(P.ws + P.L.mixf, keep_f.data(), keep_f.size() * 8, st))) return s;
+        if ((s = upload(P.ws + P.L.mixb, keep_b.data(), keep_b.size() * 8, st))) return s;
+        if ((s = upload(P.ws + P.L.ebeta, keep_e.data(), keep_e.size() * 8, st))) return s;
+    }
+    keep_t.assign(targets, targets + num_inst);
+    if ((s = upload(P.ws + P.L.target, keep_t.data(), keep_t.size() * 4, st))) return s;
+    GQ_HIP(hipMemsetAsync(P.ws + P.L.delta, 0, (size_t)num_inst * (p + 1) * 16, st));
+    return GQAOA_OK;
+}
+
+// ---- entry points (validated by the ABI layer) ---------------------------------------------
+int run_evolve(int n, int m, const uint8_t *cost, int p, const double *beta, const double *gamma,
+               int dtype, int init_uniform, void *psi, int target, double *psol, double *energy,
+               double *norm, void *ws, hipStream_t st) {
+    FwdPlan P;
+    std::vector<char> lut;
+    std::vector<double> f, b, e;
+    std::vector<int32_t> t;
+    int32_t m_of[1] = {m};
+    int32_t tg[1] = {target};
+    int s = prepare_plan(P, 1, n, m_of, cost, p, beta, gamma, dtype, tg, ws, 0, false, st, lut, f, b, e, t);
+    if (s) return s;
+    for (int j = 1; j <= p; ++j)
+        if ((s = forward_round(P, j, psi, psi, init_uniform && j == 1, true, st))) return s;
+    const bool write = p > 0 || init_uniform;
+    if ((s = final_pass(P, psi, psi, init_uniform && p == 0, write, st))) return s;
+    std::vector<double> ro((size_t)(p + 1) * 3);
+    GQ_HIP(hipMemcpyAsync(ro.data(), P.ws + P.L.readout, ro.size() * 8, hipMemcpyDeviceToHost, st));
+    GQ_HIP(hipStreamSynchronize(st));
+    if (prof_on()) prof_collect();
+    for (int j = 0; j <= p; ++j) {
+        if (psol) psol[j] = ro[3 * j];
+        if (energy) energy[j] = ro[3 * j + 1];
+        if (norm) norm[j] = ro[3 * j + 2];
+    }
+    return GQAOA_OK;
+}
+
+int run_solution_prob(int n, const uint8_t *cost, const void *psi, int dtype, int target,
+                      double *out, void *ws, hipStream_t st) {
+    FwdPlan P;
+    std::vector<char> lut;
+    std::vector<double> f, b, e;
+    std::vector<int32_t> t;
+    int32_t m_of[1] = {255};
+    int32_t tg[1] = {target};
+    int s = prepare_plan(P, 1, n, m_of, cost, 0, nullptr, nullptr, dtype, tg, ws, 0, false, st, lut, f, b, e, t);
+    if (s) return s;
+    if ((s = final_pass(P, psi, const_cast<void *>(psi), false, false, st))) return s;
+    double ro[3];
+    GQ_HIP(hipMemcpyAsync(ro, P.ws + P.L.readout, 24, hipMemcpyDeviceToHost, st));
+    GQ_HIP(hipStreamSynchronize(st));
+    *out = ro[0];
+    return GQAOA_OK;
+}
+
+int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int p,
+             const double *beta, const double *gamma, int dtype, const int32_t *targets,
+             int ckpt_every, double *psol, double *dbeta, double *dgamma, void *ws, hipStream_t st) {
+    FwdPlan P;
+    std::vector<char> lut;
+    std::vector<double> f, b, e;
+    std::vector<int32_t> t;
+    int s = prepare_plan(P, num_inst, n, m_of, cost, p, beta, gamma, dtype, targets, ws, ckpt_every,
+                         true, st, lut, f, b, e, t);
+    if (s) return s;
+    const int c = (ckpt_every <= 0 || ckpt_every >= p) ? p : ckpt_every;
+    const int nseg = (p + c - 1) / c;
+    auto slot = [&](size_t k) { return (void *)(P.ws + P.L.slots + k * P.L.slot_bytes); };
+    // slots: [0, nseg-1) checkpoints phi_{s c} for s = 1..nseg-1; then c segment
+    // slots; then the working slot (if nseg > 1); then lambda.
+    const size_t seg0 = (size_t)(nseg - 1);
+    const size_t work = seg0 + (size_t)c;
+    const size_t lam = work + (nseg > 1 ? 1 : 0);
+    const int k0_last = (nseg - 1) * c;
+    auto seg_slot = [&](int k, int k0) { return slot(seg0 + (size_t)(k - k0 - 1)); };
+
+    // forward sweep
+    const void *prev = nullptr;
+    for (int k = 1; k <= p; ++k) {
+        void *out;
+        if (k > k0_last) out = seg_slot(k, k0_last);
+        else if (k % c == 0) out = slot((size_t)(k / c - 1));
+        else out = slot(work);
+        if ((s = forward_round(P, k, k == 1 ? out : prev, out, k == 1, true, st))) return s;
+        prev = out;
+    }
+    // readout of round p and adjoint set-up (eps_p, dbeta_p); the target sum T
+    // is taken from the final state's level-t amplitudes.
+    {
+        FwdArgs a = base_fwd_args(P);
+        a.psi_in = prev;
+        a.psi_out = nullptr;
+        a.lut = nullptr;
+        a.delta = reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * p;
+        launch_fwd(P.dtype, false, false, P.shape, P.num_inst, a, st);
+        GQ_LAUNCH_CHECK();
+        FinArgs fa = base_fin_args(P);
+        fa.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * p;
+        fa.mixb = reinterpret_cast<double *>(P.ws + P.L.mixb) + 2 * (p - 1);
+        fa.ebeta = reinterpret_cast<double *>(P.ws + P.L.ebeta) + 2 * (p - 1);
+        fa.S_p = reinterpret_cast<double *>(P.ws + P.L.S) + 2 * p;
+        fa.stride = 2 * (p + 1);
+        fa.eps_out = reinterpret_cast<double *>(P.ws + P.L.eps);
+        fa.dbeta_out = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (p - 1);
+        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, fa);
+        GQ_LAUNCH_CHECK();
+    }
+    // reverse sweep, segment by segment
+    const size_t cs = dtype == GQAOA_C64 ? 8 : 16;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int k0 = sg * c, k1 = std::min(p, k0 + c);
+        if (sg != nseg - 1) {  // recompute phi_{k0+1..k1} from the checkpoint
+            for (int k = k0 + 1; k <= k1; ++k) {
+                const void *in = k == k0 + 1 ? (k0 == 0 ? seg_slot(k, k0) : slot((size_t)(k0 / c - 1)))
+                                             : seg_slot(k - 1, k0);
+                if ((s = forward_round(P, k, in, seg_slot(k, k0), k == 1, false, st))) return s;
+            }
+        }
+        for (int k = k1; k >= k0 + 1; --k) {
+            RevArgs r{};
+            r.cost = P.cost;
+            r.phi = seg_slot(k, k0);
+            r.lam_in = k == p ? nullptr : slot(lam);
+            r.lam_out = slot(lam);
+            r.N = P.N;
+            r.lut = P.ws + P.L.lut + (size_t)(k - 1) * 256 * cs;
+            r.lut_stride = p * 256;
+            r.lut_len = 256;
+            r.eps = reinterpret_cast<double *>(P.ws + P.L.eps);
+            r.eps_stride = 2;
+            r.delta_p = reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * p;
+            r.delta_stride = 2 * (p + 1);
+            r.target = reinterpret_cast<const int32_t *>(P.ws + P.L.target);
+            r.partials = reinterpret_cast<double *>(P.ws + P.L.partials);
+            ProfScope ps(dtype == GQAOA_C64 ? "sv_reverse_c64" : "sv_reverse_c128", st);
+            launch_rev(dtype, k == p, k > 1, P.shape, P.num_inst, r, st);
+            ps.end();
+            GQ_LAUNCH_CHECK();
+            RevFinArgs rf{};
+            rf.partials = r.partials;
+            rf.nblocks = P.shape.blocks_x;
+            rf.inv_N = 1.0 / (double)P.N;
+            rf.dgamma_k = reinterpret_cast<double *>(P.ws + P.L.dgamma) + (k - 1);
+            rf.grad_stride = p;
+            if (k > 1) {
+                rf.mixb_km1 = reinterpret_cast<double *>(P.ws + P.L.mixb) + 2 * (k - 2);
+                rf.ebeta_km1 = reinterpret_cast<double *>(P.ws + P.L.ebeta) + 2 * (k - 2);
+                rf.S_km1 = reinterpret_cast<double *>(P.ws + P.L.S) + 2 * (k - 1);
+                rf.S_stride = 2 * (p + 1);
+                rf.eps_out = reinterpret_cast<double *>(P.ws + P.L.eps);
+                rf.dbeta_km1 = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (k - 2);
+            }
+            hipLaunchKernelGGL(sv_rev_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, rf);
+            GQ_LAUNCH_CHECK();
+        }
+    }
+    std::vector<double> ro((size_t)num_inst * (p + 1) * 3), db((size_t)num_inst * p), dg((size_t)num_inst * p);
+    GQ_HIP(hipMemcpyAsync(ro.data(), P.ws + P.L.readout, ro.size() * 8, hipMemcpyDeviceToHost, st));
+    GQ_HIP(hipMemcpyAsync(db.data(), P.ws + P.L.dbeta, db.size() * 8, hipMemcpyDeviceToHost, st));
+    GQ_HIP(hipMemcpyAsync(dg.data(), P.ws + P.L.dgamma, dg.size() * 8, hipMemcpyDeviceToHost, st));
+    GQ_HIP(hipStreamSynchronize(st));
+    if (prof_on()) prof_collect();
+    for (int i = 0; i < num_inst; ++i) {
+        if (psol) psol[i] = ro[((size_t)i * (p + 1) + p) * 3];
+        for (int k = 0; k < p; ++k) {
+            if (dbeta) dbeta[(size_t)i * p + k] = db[(size_t)i * p + k];
+            if (dgamma) dgamma[(size_t)i * p + k] = dg[(size_t)i * p + k];
+        }
+    }
+    return GQAOA_OK;
+}
+
+}  // namespace gqaoa

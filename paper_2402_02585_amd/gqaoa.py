@@ -1,0 +1,329 @@
+"""Python binding of libgqaoa (the C ABI in include/gqaoa.h).
+
+Argument marshalling only: every function forwards to the entry point of the
+same name, passing torch device pointers and the current HIP stream. Device
+buffers are torch tensors on ``cuda`` (ROCm); host arrays are numpy. There is
+no CPU fallback: the functions raise ``GQAOAError`` when the library or a
+gfx950 device is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgqaoa.so")
+
+C64, C128 = 0, 1
+MLP_NPARAMS = 160 * 256 + 256 + 256 * 256 + 256 + 256 * 2 + 2
+MLP_OFFSETS = {"W1": (0, (160, 256)), "b1": (40960, (256,)), "W2": (41216, (256, 256)),
+               "b2": (106752, (256,)), "W3": (107008, (256, 2)), "b3": (107520, (2,))}
+
+_lib = None
+_c = ctypes
+_vp, _i32, _sz, _f32 = _c.c_void_p, _c.c_int, _c.c_size_t, _c.c_float
+
+_SIGS = {
+    "gqaoa_status_string": ([_i32], _c.c_char_p),
+    "gqaoa_last_error": ([], _c.c_char_p),
+    "gqaoa_abi_version": ([], _i32),
+    "gqaoa_cost_table": ([_i32, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_hist_batched": ([_i32, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
+    "gqaoa_workspace_bytes": ([_i32, _i32, _i32, _i32], _sz),
+    "gqaoa_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_solution_prob": ([_i32, _vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_grad_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32], _sz),
+    "gqaoa_grad": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_grad_batched": ([_i32, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_hist_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_scan_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32], _sz),
+    "gqaoa_scan_batched": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_mlp_act_bytes": ([_i32], _sz),
+    "gqaoa_mlp_forward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_mlp_backward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_mlp_adam": ([_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
+    "gqaoa_mlp_loss": ([_i32, _vp, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_mlp_features": ([_i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_profile_enable": ([_i32], _i32),
+    "gqaoa_profile_reset": ([], None),
+    "gqaoa_profile_read": ([_c.c_char_p, _vp, _vp], _i32),
+}
+
+
+class GQAOAError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        super().__init__(f"{what} (status {status}){': ' + detail if detail else ''}")
+        self.status = status
+
+
+def load_library():
+    """Load libgqaoa.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GQAOAError(-5, "libgqaoa.so is not built", LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        lib = load_library()
+        raise GQAOAError(status, lib.gqaoa_status_string(status).decode(), lib.gqaoa_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise GQAOAError(-5, "no GPU visible to torch; libgqaoa has no CPU path")
+    return torch
+
+
+def _stream(torch, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (C64, "c64", "complex64"):
+        return C64
+    if dtype in (C128, "c128", "complex128"):
+        return C128
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def _lits(lits) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(lits, dtype=np.int32).reshape(-1))
+
+
+# ---- cost table -----------------------------------------------------------------------
+def gqaoa_cost_table(n: int, lits, with_hist: bool = True, cost=None, stream=None):
+    """Returns (cost uint8[2^n], hist int64[m+1] or None) as device tensors."""
+    torch = _torch()
+    lib = load_library()
+    flat = _lits(lits)
+    m = flat.size // 3
+    if cost is None:
+        cost = torch.empty(1 << n, dtype=torch.uint8, device="cuda")
+    hist = torch.empty(m + 1, dtype=torch.int64, device="cuda") if with_hist else None
+    _check(lib.gqaoa_cost_table(n, m, _np_ptr(flat), _ptr(cost), _ptr(hist), _stream(torch, stream)))
+    return cost, hist
+
+
+def gqaoa_hist_batched(ns, ms, lits_list, hist_stride: int | None = None, stream=None):
+    """Level histograms of many instances: int64 device tensor [I, hist_stride]."""
+    torch = _torch()
+    lib = load_library()
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    flat = np.ascontiguousarray(np.concatenate([_lits(l) for l in lits_list]))
+    stride = int(hist_stride or (int(ms.max()) + 1))
+    hists = torch.empty((len(ns), stride), dtype=torch.int64, device="cuda")
+    _check(lib.gqaoa_hist_batched(len(ns), _np_ptr(ns), _np_ptr(ms), _np_ptr(flat), _ptr(hists), stride,
+                                  _stream(torch, stream)))
+    return hists
+
+
+# ---- statevector ----------------------------------------------------------------------
+def gqaoa_workspace_bytes(n: int, p: int, dtype=C64, ckpt_every: int = 0) -> int:
+    return int(load_library().gqaoa_workspace_bytes(n, p, _dtype_code(dtype), ckpt_every))
+
+
+def _workspace(torch, nbytes: int):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+def gqaoa_evolve(n: int, m: int, cost, betas, gammas, dtype=C64, psi=None, init_uniform: bool = True,
+                 target_level: int = 0, workspace=None, stream=None):
+    """Eq. (3) on the device. Returns (psi, psol[p+1], energy[p+1], norm[p+1])."""
+    torch = _torch()
+    lib = load_library()
+    dt = _dtype_code(dtype)
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    p = b.size
+    if psi is None:
+        psi = torch.empty(1 << n, dtype=torch.complex64 if dt == C64 else torch.complex128, device="cuda")
+    need = lib.gqaoa_workspace_bytes(n, p, dt, 0)
+    ws = workspace if workspace is not None else _workspace(torch, need)
+    psol, energy, norm = np.empty(p + 1), np.empty(p + 1), np.empty(p + 1)
+    _check(lib.gqaoa_evolve(n, m, _ptr(cost), p, _np_ptr(b), _np_ptr(g), dt, int(bool(init_uniform)), _ptr(psi),
+                            target_level, _np_ptr(psol), _np_ptr(energy), _np_ptr(norm), _ptr(ws),
+                            ws.numel(), _stream(torch, stream)))
+    return psi, psol, energy, norm
+
+
+def gqaoa_solution_prob(n: int, cost, psi, dtype=C64, target_level: int = 0, workspace=None, stream=None) -> float:
+    torch = _torch()
+    lib = load_library()
+    dt = _dtype_code(dtype)
+    ws = workspace if workspace is not None else _workspace(torch, lib.gqaoa_workspace_bytes(n, 0, dt, 0))
+    out = np.zeros(1)
+    _check(lib.gqaoa_solution_prob(n, _ptr(cost), _ptr(psi), dt, target_level, _np_ptr(out), _ptr(ws), ws.numel(),
+                                   _stream(torch, stream)))
+    return float(out[0])
+
+
+def gqaoa_grad_workspace_bytes(num_inst: int, n: int, p: int, dtype=C128, ckpt_every: int = 0) -> int:
+    return int(load_library().gqaoa_grad_workspace_bytes(num_inst, n, p, _dtype_code(dtype), ckpt_every))
+
+
+def gqaoa_grad(n: int, m: int, cost, betas, gammas, dtype=C128, target_level: int = 0, ckpt_every: int = 0,
+               workspace=None, stream=None):
+    """Returns (P, dP/dbeta[p], dP/dgamma[p]) by the adjoint sweep."""
+    P, db, dg = gqaoa_grad_batched(n, [m], cost, np.asarray(betas)[None, :], np.asarray(gammas)[None, :], dtype,
+                                   [target_level], ckpt_every, workspace, stream)
+    return float(P[0]), db[0], dg[0]
+
+
+def gqaoa_grad_batched(n: int, ms, costs, betas, gammas, dtype=C128, targets=None, ckpt_every: int = 0,
+                       workspace=None, stream=None):
+    """Batched adjoint: costs uint8 [I, 2^n] (contiguous), betas/gammas [I, p].
+    Returns (P[I], dbeta[I, p], dgamma[I, p])."""
+    torch = _torch()
+    lib = load_library()
+    dt = _dtype_code(dtype)
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    I, p = b.shape
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    need = lib.gqaoa_grad_workspace_bytes(I, n, p, dt, ckpt_every)
+    ws = workspace if workspace is not None else _workspace(torch, need)
+    P, db, dg = np.empty(I), np.empty((I, p)), np.empty((I, p))
+    _check(lib.gqaoa_grad_batched(I, n, _np_ptr(ms), _ptr(costs), p, _np_ptr(b), _np_ptr(g), dt, _np_ptr(tg),
+                                  ckpt_every, _np_ptr(P), _np_ptr(db), _np_ptr(dg), _ptr(ws), ws.numel(),
+                                  _stream(torch, stream)))
+    return P, db, dg
+
+
+# ---- level space ------------------------------------------------------------------------
+def gqaoa_hist_evolve(n: int, m: int, hist, betas, gammas, target_level: int = 0, stream=None):
+    """Level-space evolution of one instance (float64). Returns (psol, energy, norm), each [p+1]."""
+    torch = _torch()
+    lib = load_library()
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    p = b.size
+    psol, energy, norm = np.empty(p + 1), np.empty(p + 1), np.empty(p + 1)
+    _check(lib.gqaoa_hist_evolve(n, m, _ptr(hist), p, _np_ptr(b), _np_ptr(g), target_level, _np_ptr(psol),
+                                 _np_ptr(energy), _np_ptr(norm), _stream(torch, stream)))
+    return psol, energy, norm
+
+
+def gqaoa_scan_workspace_bytes(num_inst: int, hist_stride: int, nb: int, ng: int, num_p: int) -> int:
+    return int(load_library().gqaoa_scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p))
+
+
+def gqaoa_scan_batched(ns, ms, hists, betas, gammas, p_list, targets=None, tile=None, with_energy: bool = True,
+                       out=None, workspace=None, stream=None):
+    """Single-angle-pair scan. hists: host int64/uint64 [I, stride].
+    Returns (psol, energy) float32 device tensors [I, num_p, ng, nb]."""
+    torch = _torch()
+    lib = load_library()
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    h = np.ascontiguousarray(np.asarray(hists).astype(np.uint64))
+    I, stride = h.shape
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    pl = np.ascontiguousarray(np.asarray(p_list, dtype=np.int32))
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    tl = None if tile is None else np.ascontiguousarray(np.asarray(tile, dtype=np.int32))
+    shape = (I, pl.size, g.size, b.size)
+    if out is None:
+        psol = torch.empty(shape, dtype=torch.float32, device="cuda")
+        energy = torch.empty(shape, dtype=torch.float32, device="cuda") if with_energy else None
+    else:
+        psol, energy = out
+    need = lib.gqaoa_scan_workspace_bytes(I, stride, b.size, g.size, pl.size)
+    ws = workspace if workspace is not None else _workspace(torch, need)
+    _check(lib.gqaoa_scan_batched(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), b.size, _np_ptr(b),
+                                  g.size, _np_ptr(g), pl.size, _np_ptr(pl), _ptr(psol), _ptr(energy), _np_ptr(tl),
+                                  _ptr(ws), ws.numel(), _stream(torch, stream)))
+    return psol, energy
+
+
+# ---- MLP ---------------------------------------------------------------------------------
+def gqaoa_mlp_act_bytes(batch: int) -> int:
+    return int(load_library().gqaoa_mlp_act_bytes(batch))
+
+
+def gqaoa_mlp_forward(params, x, out=None, act=None, stream=None):
+    """params float32 [MLP_NPARAMS], x float32 [B, 131] -> (out [B, 2], act cache)."""
+    torch = _torch()
+    lib = load_library()
+    B = x.shape[0]
+    out = out if out is not None else torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    act = act if act is not None else _workspace(torch, lib.gqaoa_mlp_act_bytes(B))
+    _check(lib.gqaoa_mlp_forward(_ptr(params), B, _ptr(x), _ptr(out), _ptr(act), _stream(torch, stream)))
+    return out, act
+
+
+def gqaoa_mlp_backward(params, act, dout, grads=None, stream=None):
+    torch = _torch()
+    lib = load_library()
+    B = dout.shape[0]
+    grads = grads if grads is not None else torch.empty(MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    _check(lib.gqaoa_mlp_backward(_ptr(params), B, _ptr(act), _ptr(dout), _ptr(grads), _stream(torch, stream)))
+    return grads
+
+
+def gqaoa_mlp_adam(params, grads, state, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    torch = _torch()
+    lib = load_library()
+    _check(lib.gqaoa_mlp_adam(_ptr(params), _ptr(grads), _ptr(state), step, lr, beta1, beta2, eps,
+                              _stream(torch, stream)))
+
+
+def gqaoa_mlp_loss(out, targets, dout=None, loss=None, stream=None):
+    torch = _torch()
+    lib = load_library()
+    B = out.shape[0]
+    dout = dout if dout is not None else torch.empty_like(out)
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib.gqaoa_mlp_loss(B, _ptr(out), _ptr(targets), _ptr(dout), _ptr(loss), _stream(torch, stream)))
+    return dout, loss
+
+
+def gqaoa_mlp_features(hists, ns, ms, ps, x=None, stream=None):
+    """hists int64 device [B, stride]; ns, ms, ps int32 device [B] -> x float32 [B, 131]."""
+    torch = _torch()
+    lib = load_library()
+    B, stride = hists.shape
+    x = x if x is not None else torch.empty((B, 131), dtype=torch.float32, device="cuda")
+    _check(lib.gqaoa_mlp_features(B, _ptr(hists), stride, _ptr(ns), _ptr(ms), _ptr(ps), _ptr(x),
+                                  _stream(torch, stream)))
+    return x
+
+
+# ---- instrumentation ------------------------------------------------------------------------
+def gqaoa_profile_enable(on: bool = True):
+    _check(load_library().gqaoa_profile_enable(int(bool(on))))
+
+
+def gqaoa_profile_reset():
+    load_library().gqaoa_profile_reset()
+
+
+def gqaoa_profile_read(name: str):
+    """(total_ms, count) of the launches recorded under ``name``."""
+    ms = np.zeros(1)
+    cnt = np.zeros(1, dtype=np.int64)
+    _check(load_library().gqaoa_profile_read(name.encode(), _np_ptr(ms), _np_ptr(cnt)))
+    return float(ms[0]), int(cnt[0])

@@ -1,0 +1,37 @@
+"""Helpers shared by the GPU parity tests (inputs come from the seeded
+generators; expected values only from the oracle)."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2402_02585_amd import instances as inst
+
+
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch
+
+
+def rand_lits(n, m, seed):
+    return inst.random_3sat(np.random.Generator(np.random.PCG64(seed)), n, m)
+
+
+def rand_state(n, seed, dtype=np.complex128):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+    return (v / np.linalg.norm(v)).astype(dtype)
+
+
+@functools.lru_cache(maxsize=None)
+def c2_instance():
+    """Seed-2 stream, n = 28, m = 118 (d ~ 4.2): first satisfiable draw."""
+    return inst.first_satisfiable(2, 28, 118)
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()

@@ -1,0 +1,129 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every entry
+point that include/gqaoa.h declares, and rejects invalid arguments before any
+device call (no compute call runs here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2402_02585_amd import gqaoa as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gqaoa.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(g.LIB_PATH), reason="libgqaoa.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gqaoa_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = ctypes.CDLL(g.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(g._SIGS), "binding and header disagree"
+
+
+def test_status_strings_and_version():
+    lib = g.load_library()
+    assert lib.gqaoa_abi_version() == 1
+    assert lib.gqaoa_status_string(0) == b"ok"
+    assert lib.gqaoa_status_string(-3) == b"workspace too small"
+
+
+def _lits(rows):
+    return np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1))
+
+
+def test_cost_table_rejects_bad_clauses():
+    lib = g.load_library()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    bad_repeat = _lits([[0, 2, 1]])              # variable 0 twice
+    assert lib.gqaoa_cost_table(5, 1, g._np_ptr(bad_repeat), dummy, None, None) == -1
+    assert b"repeats" in lib.gqaoa_last_error()
+    bad_range = _lits([[0, 2, 10]])              # literal 10 = var 5 >= n
+    assert lib.gqaoa_cost_table(5, 1, g._np_ptr(bad_range), dummy, None, None) == -1
+    ok = _lits([[0, 2, 4]])
+    assert lib.gqaoa_cost_table(2, 1, g._np_ptr(ok), dummy, None, None) == -2   # n < 3
+    assert lib.gqaoa_cost_table(35, 1, g._np_ptr(ok), dummy, None, None) == -2  # n > 34
+    assert lib.gqaoa_cost_table(5, 0, g._np_ptr(ok), dummy, None, None) == -2   # m < 1
+    assert lib.gqaoa_cost_table(5, 1, None, dummy, None, None) == -1
+    assert lib.gqaoa_cost_table(5, 1, g._np_ptr(ok), None, None, None) == -1
+
+
+def test_evolve_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    b = np.zeros(3)
+    bp = g._np_ptr(b)
+    need = lib.gqaoa_workspace_bytes(10, 3, 0, 0)
+    assert need > 0
+    assert lib.gqaoa_workspace_bytes(10, 3, 7, 0) == 0
+    args = dict(n=10, m=42, cost=d, p=3, beta=bp, gamma=bp, dt=0, uni=1, psi=d, t=0, ws=d, wsb=need)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return lib.gqaoa_evolve(a["n"], a["m"], a["cost"], a["p"], a["beta"], a["gamma"], a["dt"], a["uni"],
+                                a["psi"], a["t"], None, None, None, a["ws"], a["wsb"], None)
+
+    assert call(n=2) == -2
+    assert call(n=35) == -2
+    assert call(m=256) == -2
+    assert call(p=-1) == -2
+    assert call(t=43) == -2
+    assert call(dt=3) == -1
+    assert call(cost=None) == -1
+    assert call(psi=None) == -1
+    assert call(beta=None) == -1
+    assert call(wsb=need - 1) == -3
+
+
+def test_grad_and_scan_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    b = np.zeros(4)
+    m = np.array([42], dtype=np.int32)
+    t = np.array([43], dtype=np.int32)
+    need = lib.gqaoa_grad_workspace_bytes(1, 10, 4, 1, 2)
+    assert need > lib.gqaoa_grad_workspace_bytes(1, 10, 4, 1, 0) - 1 or need > 0
+    assert lib.gqaoa_grad_batched(1, 10, g._np_ptr(m), d, 0, g._np_ptr(b), g._np_ptr(b), 1, None, 0, None, None,
+                                  None, d, need, None) == -2      # p < 1
+    assert lib.gqaoa_grad_batched(1, 10, g._np_ptr(m), d, 4, g._np_ptr(b), g._np_ptr(b), 1, g._np_ptr(t), 0, None,
+                                  None, None, d, need, None) == -2  # target > m
+    ns = np.array([10], dtype=np.int32)
+    hist = np.zeros((1, 43), dtype=np.uint64)
+    hist[0, :5] = 1
+    pl = np.array([4, 2], dtype=np.int32)                      # not ascending
+    ws = lib.gqaoa_scan_workspace_bytes(1, 43, 4, 4, 2)
+    assert lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 43, None, 4, g._np_ptr(b), 4,
+                                  g._np_ptr(b), 2, g._np_ptr(pl), d, None, None, d, ws, None) == -1
+    pl = np.array([2, 4], dtype=np.int32)
+    tile = np.array([3, 4], dtype=np.int32)                    # 3 waves per block is not offered
+    assert lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 43, None, 4, g._np_ptr(b), 4,
+                                  g._np_ptr(b), 2, g._np_ptr(pl), d, None, g._np_ptr(tile), d, ws, None) == -1
+    assert lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 43, None, 4, g._np_ptr(b), 4,
+                                  g._np_ptr(b), 2, g._np_ptr(pl), d, None, None, d, ws - 1, None) == -3
+
+
+def test_mlp_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    assert lib.gqaoa_mlp_forward(d, 0, d, d, d, None) == -2
+    assert lib.gqaoa_mlp_adam(d, d, d, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -2
+    assert lib.gqaoa_mlp_adam(d, d, d, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -2
+    assert lib.gqaoa_mlp_act_bytes(256) > 256 * 256 * 4
+
+
+def test_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(g.GQAOAError):
+        g.gqaoa_cost_table(5, [[0, 2, 4]])

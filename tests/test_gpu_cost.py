@@ -1,0 +1,64 @@
+"""GPU parity: cost table and level histograms are bit-exact with the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import c2_instance, log, need_gpu, rand_lits
+from oracle import brute
+from oracle.cost import cost_table, level_histogram
+from paper_2402_02585_amd import gqaoa as g
+from paper_2402_02585_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(3, 1, 1), (3, 8, 2), (4, 9, 3), (5, 20, 4), (6, 25, 5), (8, 34, 6), (10, 42, 7), (11, 46, 8),
+         (12, 80, 9), (13, 55, 10), (14, 59, 11), (16, 255, 12), (17, 71, 13), (18, 76, 14), (20, 84, 15),
+         (20, 200, 16)]
+
+
+@pytest.mark.parametrize("n,m,seed", CASES)
+def test_cost_table_bit_exact(n, m, seed):
+    need_gpu()
+    log(f"cost table n={n} m={m} seed={seed}")
+    lits = rand_lits(n, m, seed)
+    cost, hist = g.gqaoa_cost_table(n, lits)
+    ref = cost_table(n, lits)
+    np.testing.assert_array_equal(cost.cpu().numpy(), ref.astype(np.uint8))
+    np.testing.assert_array_equal(hist.cpu().numpy(), level_histogram(ref, m))
+
+
+def test_cost_table_deterministic_and_two_level():
+    need_gpu()
+    lits = inst.two_level_instance(15, keep_pattern=6)
+    c1, h1 = g.gqaoa_cost_table(15, lits)
+    c2, h2 = g.gqaoa_cost_table(15, lits)
+    assert bool((c1 == c2).all()) and bool((h1 == h2).all())
+    assert h1.cpu().tolist()[:2] == [2 ** 12, 2 ** 15 - 2 ** 12]
+
+
+def test_hist_batched_matches_oracle():
+    need_gpu()
+    insts = inst.batched_scan_instances(3, 24, 3, 14, sat_only=False)
+    ns = [it.n for it in insts]
+    ms = [it.m for it in insts]
+    hists = g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=80).cpu().numpy()
+    for i, it in enumerate(insts):
+        ref = level_histogram(cost_table(it.n, it.lits), it.m)
+        np.testing.assert_array_equal(hists[i, :it.m + 1], ref)
+        assert not hists[i, it.m + 1:].any()
+
+
+def test_full_size_n28_histogram_and_sampled_costs():
+    """n = 28, m = 118: histogram against the oracle's brute-force count over
+    all 2^28 assignments, and sampled windows of the cost table."""
+    torch = need_gpu()
+    it = c2_instance()
+    log(f"n=28 m=118 draw={it.draw}")
+    cost, hist = g.gqaoa_cost_table(28, it.lits)
+    ref_hist = brute.level_histogram_brute(28, it.lits)
+    np.testing.assert_array_equal(hist.cpu().numpy(), ref_hist)
+    rng = np.random.Generator(np.random.PCG64(28))
+    for z0 in [0, 2 ** 28 - 4096] + [int(x) for x in rng.integers(0, 2 ** 28 - 4096, 6)]:
+        got = cost[z0:z0 + 4096].cpu().numpy()
+        np.testing.assert_array_equal(got, brute.cost_range_brute(28, it.lits, z0, 4096))
+    del cost
+    torch.cuda.empty_cache()

@@ -1,0 +1,100 @@
+"""GPU parity: level-space evolution and the adjoint gradient."""
+import numpy as np
+import pytest
+
+from gpu_common import log, need_gpu, rand_lits
+from oracle.cost import cost_table, level_histogram, min_level
+from oracle.evolve import evolve_hist, evolve_sv
+from oracle.grad import grad_hist, grad_sv
+from paper_2402_02585_amd import gqaoa as g
+from paper_2402_02585_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,m,p,seed,same", [(10, 42, 20, 1, False), (14, 59, 64, 2, True), (18, 255, 30, 3, False),
+                                             (20, 84, 64, 4, True), (6, 26, 1, 5, False), (8, 34, 0, 6, False)])
+def test_hist_evolve_float64(n, m, p, seed, same):
+    need_gpu()
+    lits = rand_lits(n, m, seed)
+    cost, hist = g.gqaoa_cost_table(n, lits)
+    if same:
+        b, gm = inst.uniform_angles(seed, 1)
+        beta, gamma = np.full(p, b[0]), np.full(p, gm[0])
+    else:
+        beta, gamma = inst.uniform_angles(seed, p)
+    ref_hist = level_histogram(cost_table(n, lits), m)
+    psol, energy, norm = g.gqaoa_hist_evolve(n, m, hist, beta, gamma)
+    _, rp, re, rn = evolve_hist(ref_hist, beta, gamma)
+    assert np.abs(psol - rp).max() < 1e-12
+    assert np.abs(energy - re).max() / m < 1e-12
+    assert np.abs(norm - rn).max() < 1e-12
+
+
+@pytest.mark.parametrize("dt,ckpt", [(g.C128, 0), (g.C128, 1), (g.C128, 3), (g.C128, 7), (g.C128, 50), (g.C64, 2)])
+def test_grad_single_vs_oracle(dt, ckpt):
+    need_gpu()
+    n, m, p = 11, 47, 7
+    lits = rand_lits(n, m, 9)
+    ref_cost = cost_table(n, lits)
+    beta, gamma = inst.uniform_angles(19, p)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    P, db, dg = g.gqaoa_grad(n, m, cost, beta, gamma, dtype=dt, ckpt_every=ckpt)
+    rP, rdb, rdg = grad_sv(n, ref_cost, beta, gamma)
+    tol = 1e-12 if dt == g.C128 else 2e-5
+    assert abs(P - rP) < tol
+    assert np.abs(db - rdb).max() < tol, np.abs(db - rdb).max()
+    assert np.abs(dg - rdg).max() < tol * m, np.abs(dg - rdg).max()
+
+
+def test_grad_max_sat_target_and_central_fd():
+    need_gpu()
+    n, m, p = 10, 70, 6
+    lits = rand_lits(n, m, 21)
+    ref_cost = cost_table(n, lits)
+    t = min_level(level_histogram(ref_cost, m))
+    beta, gamma = inst.uniform_angles(21, p)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    P, db, dg = g.gqaoa_grad(n, m, cost, beta, gamma, dtype=g.C128, target_level=t, ckpt_every=2)
+    h = 1e-4
+    for k in range(p):
+        for arr, d in ((beta, db), (gamma, dg)):
+            ap, am = arr.copy(), arr.copy()
+            ap[k] += h
+            am[k] -= h
+            if arr is beta:
+                fd = (evolve_sv(n, ref_cost, ap, gamma, target=t)[1][-1] - evolve_sv(n, ref_cost, am, gamma, target=t)[1][-1]) / (2 * h)
+            else:
+                fd = (evolve_sv(n, ref_cost, beta, ap, target=t)[1][-1] - evolve_sv(n, ref_cost, beta, am, target=t)[1][-1]) / (2 * h)
+            assert d[k] == pytest.approx(fd, abs=1e-6)
+
+
+def test_grad_batched_adjoint_config_sample():
+    """Adjoint workload shape: n = 20, m = 85, p = 32, checkpoints every 8 rounds
+    (a batch of 6 of the seeded instances); every instance against the
+    oracle's level-space sweep, one against the statevector sweep."""
+    torch = need_gpu()
+    n, m, p, I = 20, 85, 32, 6
+    insts = []
+    rng_seed = 4
+    for k, lits in inst.sat_stream(rng_seed, n, m):
+        if inst.dpll_satisfiable(n, lits):
+            insts.append(lits)
+        if len(insts) == I:
+            break
+    costs = torch.empty((I, 2 ** n), dtype=torch.uint8, device="cuda")
+    for i, lits in enumerate(insts):
+        g.gqaoa_cost_table(n, lits, with_hist=False, cost=costs[i])
+    betas = np.stack([inst.uniform_angles(100 + i, p)[0] for i in range(I)])
+    gammas = np.stack([inst.uniform_angles(100 + i, p)[1] for i in range(I)])
+    log("grad batched n=20 p=32")
+    P, db, dg = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, dtype=g.C128, ckpt_every=8)
+    for i, lits in enumerate(insts):
+        ref_cost = cost_table(n, lits)
+        rP, rdb, rdg = grad_hist(level_histogram(ref_cost, m), betas[i], gammas[i])
+        assert abs(P[i] - rP) < 1e-12
+        assert np.abs(db[i] - rdb).max() < 1e-11
+        assert np.abs(dg[i] - rdg).max() < 1e-10
+        if i == 0:
+            sP, sdb, sdg = grad_sv(n, ref_cost, betas[i], gammas[i])
+            assert np.abs(db[i] - sdb).max() < 1e-11 and np.abs(dg[i] - sdg).max() < 1e-10

@@ -1,0 +1,101 @@
+"""GPU parity: the bfloat16 MFMA angle MLP against the float64 oracle that
+emulates the same bfloat16 storage points.
+
+Bar: raw outputs within 1e-2 relative (plus 1e-3 absolute); parameter
+gradients with cosine similarity >= 0.999 and relative norm error <= 2e-2
+per tensor; Adam and the loss within float32 rounding of the oracle.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import need_gpu
+from oracle import mlp as ref
+from paper_2402_02585_amd import gqaoa as g
+
+pytestmark = pytest.mark.gpu
+
+
+def _pack(params):
+    flat = np.zeros(g.MLP_NPARAMS, dtype=np.float32)
+    for k, (off, shape) in g.MLP_OFFSETS.items():
+        src = params[k]
+        if k == "W1":
+            full = np.zeros(shape)
+            full[:src.shape[0]] = src
+            src = full
+        flat[off:off + int(np.prod(shape))] = np.asarray(src, dtype=np.float32).ravel()
+    return flat
+
+
+def _unpack(flat, key):
+    off, shape = g.MLP_OFFSETS[key]
+    v = flat[off:off + int(np.prod(shape))].reshape(shape)
+    return v[:131] if key == "W1" else v
+
+
+def _params32(seed):
+    p = ref.init_params(seed)
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+@pytest.mark.parametrize("B", [1, 37, 256, 1000])
+def test_forward_backward_vs_oracle(B):
+    torch = need_gpu()
+    params = _params32(B)
+    rng = np.random.Generator(np.random.PCG64(B))
+    x = (np.abs(rng.normal(size=(B, 131))) * 0.2).astype(np.float32).astype(np.float64)
+    tgt = np.stack([rng.uniform(0, 2 * np.pi, B), rng.uniform(0, np.pi, B)], axis=1).astype(np.float32)
+    prm = torch.tensor(_pack(params), device="cuda")
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    out, act = g.gqaoa_mlp_forward(prm, xd)
+    o_ref, cache = ref.forward(params, x)
+    o = out.cpu().numpy()
+    assert np.all(np.abs(o - o_ref) <= 1e-2 * np.abs(o_ref) + 1e-3), np.abs(o - o_ref).max()
+    # loss and its gradient on the device's own outputs
+    dout, loss = g.gqaoa_mlp_loss(out, torch.tensor(tgt, device="cuda"))
+    l_ref, d_ref = ref.loss_and_dout(o.astype(np.float64), tgt[:, 0].astype(np.float64), tgt[:, 1].astype(np.float64))
+    assert float(loss.item()) == pytest.approx(l_ref, rel=1e-5)
+    np.testing.assert_allclose(dout.cpu().numpy(), d_ref, rtol=1e-4, atol=1e-9)
+    grads = g.gqaoa_mlp_backward(prm, act, dout).cpu().numpy()
+    g_ref = ref.backward(params, cache, dout.cpu().numpy().astype(np.float64))
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        a, b = _unpack(grads, k).ravel().astype(np.float64), g_ref[k].ravel()
+        if np.linalg.norm(b) == 0:
+            assert np.linalg.norm(a) == 0
+            continue
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        assert cos > 0.999, (k, cos)
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 2e-2, k
+    assert not _unpack(grads, "W1")[131:].any() if _unpack(grads, "W1").shape[0] > 131 else True
+
+
+def test_adam_matches_oracle():
+    torch = need_gpu()
+    rng = np.random.Generator(np.random.PCG64(3))
+    p0 = rng.normal(size=g.MLP_NPARAMS).astype(np.float32)
+    p0[:40960].reshape(160, 256)[131:] = 0
+    grads = [rng.normal(size=g.MLP_NPARAMS).astype(np.float32) for _ in range(3)]
+    prm = torch.tensor(p0, device="cuda")
+    state = torch.zeros(2 * g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    rp = {"w": p0.astype(np.float64)}
+    st = {}
+    for step, gr in enumerate(grads, start=1):
+        g.gqaoa_mlp_adam(prm, torch.tensor(gr, device="cuda"), state, step, lr=1e-2)
+        gg = gr.astype(np.float64).copy()
+        gg[:40960].reshape(160, 256)[131:] = 0
+        ref.adam_step(rp, {"w": gg}, st, lr=1e-2)
+    out = prm.cpu().numpy()
+    np.testing.assert_allclose(out, rp["w"], rtol=1e-5, atol=1e-6)
+
+
+def test_features_match_oracle():
+    torch = need_gpu()
+    hist = np.array([[3, 5, 0, 8, 0], [1, 2, 3, 4, 6]], dtype=np.int64)
+    ns = np.array([4, 4], dtype=np.int32)
+    ms = np.array([4, 3], dtype=np.int32)
+    ps = np.array([16, 1], dtype=np.int32)
+    x = g.gqaoa_mlp_features(torch.tensor(hist, device="cuda"), torch.tensor(ns, device="cuda"),
+                             torch.tensor(ms, device="cuda"), torch.tensor(ps, device="cuda")).cpu().numpy()
+    for i in range(2):
+        xr = ref.features(hist[i, :ms[i] + 1], int(ns[i]), ms[i] / ns[i], int(ps[i]))
+        np.testing.assert_allclose(x[i], xr, rtol=1e-6, atol=1e-7)
