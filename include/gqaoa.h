@@ -155,19 +155,25 @@ int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const doubl
  *   energy_dev[same index]                    = E, Eq. (4) (float; NULL to skip).
  * Instance i: hists_host + i*hist_stride holds N_k for k <= m_host[i],
  * n_host[i] variables; target_host[i] its target level (NULL = 0 for all).
- * betas_host[nb], gammas_host[ng] in radians. Arithmetic is float32.
+ * Angles in radians: with per_instance_grid = 0 every instance uses
+ * betas_host[nb] and gammas_host[ng]; with 1 instance i uses
+ * betas_host[i*nb .. i*nb+nb) and gammas_host[i*ng .. i*ng+ng). Arithmetic is
+ * float32.
  * tile: NULL = autotuned (cached per device and shape class), else an int[2]
  * {waves_per_block in {1,2,4}, blocks_per_cu in [1,32]}.
- * ws: gqaoa_scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p) bytes.
- * Errors: EINVAL (NULL pointers), ERANGE (num_inst, nb, ng in [1, 4096],
- * num_p in [1, 16], p values in [1, 100000], more than 256 occupied levels). */
-size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p);
+ * ws: gqaoa_scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p,
+ * per_instance_grid) bytes.
+ * Errors: EINVAL (NULL pointers), ERANGE (num_inst in [1, 2^20], nb, ng in
+ * [1, 4096], num_p in [1, 16], p values in [1, 100000], more than 128
+ * occupied levels in an instance). */
+size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p,
+                                  int per_instance_grid);
 int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
                        const uint64_t *hists_host, int hist_stride, const int32_t *target_host,
                        int nb, const double *betas_host, int ng, const double *gammas_host,
-                       int num_p, const int32_t *p_list_host, float *psol_dev,
-                       float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes,
-                       void *stream);
+                       int per_instance_grid, int num_p, const int32_t *p_list_host,
+                       float *psol_dev, float *energy_dev, const int32_t *tile, void *ws_dev,
+                       size_t ws_bytes, void *stream);
 
 /* ---- angle-predictor MLP (bfloat16 MFMA, float32 accumulation) -------------
  * The paper suggests deriving angles from statistics of the density of

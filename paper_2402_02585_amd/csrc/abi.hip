@@ -24,11 +24,12 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
              double *dgamma, void *ws, hipStream_t st);
 int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *beta, const double *gamma,
                     int target, double *psol, double *energy, double *norm, hipStream_t st);
-size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p);
+size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p, int per_inst);
 int scan_max_levels();
 int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists, int hist_stride,
-             const int32_t *target_host, int nb, const double *betas, int ng, const double *gammas, int num_p,
-             const int32_t *p_list, float *psol, float *energy, const int32_t *tile, void *ws, hipStream_t st);
+             const int32_t *target_host, int nb, const double *betas, int ng, const double *gammas, int per_inst,
+             int num_p, const int32_t *p_list, float *psol, float *energy, const int32_t *tile, void *ws,
+             hipStream_t st);
 size_t mlp_act_bytes(int batch);
 int run_mlp_forward(const float *prm, int batch, const float *x, float *out, void *act, hipStream_t st);
 int run_mlp_backward(const float *prm, int batch, const void *act, const float *dout, float *grads,
@@ -291,14 +292,15 @@ int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const doubl
                            (hipStream_t)stream);
 }
 
-size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p) {
+size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p, int per_instance_grid) {
     if (num_inst < 1 || hist_stride < 2 || nb < 1 || ng < 1 || num_p < 1) return 0;
-    return scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p);
+    return scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p, per_instance_grid ? 1 : 0);
 }
 
 int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
                        int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
-                       const double *gammas_host, int num_p, const int32_t *p_list_host, float *psol_dev,
+                       const double *gammas_host, int per_instance_grid, int num_p, const int32_t *p_list_host,
+                       float *psol_dev,
                        float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream) {
     clear_error();
     if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d", num_inst);
@@ -325,10 +327,11 @@ int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_hos
         for (int k = 0; k <= m_host[i]; ++k) K += hists_host[(size_t)i * hist_stride + k] != 0;
         if (K > scan_max_levels()) return fail(GQAOA_ERANGE, "instance %d: %d occupied levels (max %d)", i, K, scan_max_levels());
     }
-    const size_t need = scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p);
+    const int pig = per_instance_grid ? 1 : 0;
+    const size_t need = scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p, pig);
     if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     return run_scan(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng, gammas_host,
-                    num_p, p_list_host, psol_dev, energy_dev, tile, ws_dev, (hipStream_t)stream);
+                    pig, num_p, p_list_host, psol_dev, energy_dev, tile, ws_dev, (hipStream_t)stream);
 }
 
 size_t gqaoa_mlp_act_bytes(int batch) {

@@ -179,6 +179,7 @@ struct ScanArgs {
     unsigned int *counter;
     unsigned int total_items;
     int nb, ng, ntiles, num_p;
+    int per_inst;          // angle grids are per instance
     int p_list[kScanMaxP];
 };
 
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
         const unsigned rest = item / (unsigned)a.ntiles;
         const int g = (int)(rest % (unsigned)a.ng);
         const ScanSlot sl = a.slots[rest / (unsigned)a.ng];
-        const double gam = a.gammas[g];
+        const double gam = a.gammas[(a.per_inst ? (size_t)sl.inst * a.ng : 0) + g];
         for (int k = lane; k < KMAX; k += 64) {
             float4 e = {1.f, 0.f, 0.f, 0.f};
             if (k < sl.K) {
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
         const int b = tile * 64 + lane;
         const bool active = b < a.nb;
         double sb, cb;
-        sincos(a.betas[active ? b : 0], &sb, &cb);
+        sincos(a.betas[(a.per_inst ? (size_t)sl.inst * a.nb : 0) + (active ? b : 0)], &sb, &cb);
         const float mr = (float)(cb - 1.0), mi = (float)(-sb);
         float br[KMAX], bi[KMAX];
 #pragma unroll
@@ -394,17 +395,18 @@ static int tune_bucket(int bucket, const DeviceInfo &dev, const ScanArgs &a, uns
     return GQAOA_OK;
 }
 
-size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p) {
+size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p, int per_inst) {
     (void)num_p;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t lv = (size_t)num_inst * std::min(hist_stride, kScanMaxK + 128);
-    return al(sizeof(ScanSlot) * (size_t)num_inst) + al(4 * lv) + al(4 * lv) + al(8 * (size_t)nb) +
-           al(8 * (size_t)ng) + al(4 * kNumBuckets) + 256;
+    const size_t lv = (size_t)num_inst * std::min(hist_stride, kScanMaxK);
+    const size_t ga = per_inst ? (size_t)num_inst : 1;
+    return al(sizeof(ScanSlot) * (size_t)num_inst) + al(4 * lv) + al(4 * lv) + al(8 * (size_t)nb * ga) +
+           al(8 * (size_t)ng * ga) + al(4 * kNumBuckets) + 256;
 }
 
 int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
              int hist_stride, const int32_t *target_host, int nb, const double *betas, int ng,
-             const double *gammas, int num_p, const int32_t *p_list, float *psol, float *energy,
+             const double *gammas, int per_inst, int num_p, const int32_t *p_list, float *psol, float *energy,
              const int32_t *tile, void *ws, hipStream_t st) {
     DeviceInfo dev;
     int s = device_info(&dev);
@@ -454,16 +456,17 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
     p += al(4 * std::max<size_t>(1, lev_all.size()));
     float *d_w = reinterpret_cast<float *>(p);
     p += al(4 * std::max<size_t>(1, w_all.size()));
+    const size_t ga = per_inst ? (size_t)num_inst : 1;
     double *d_b = reinterpret_cast<double *>(p);
-    p += al(8 * (size_t)nb);
+    p += al(8 * (size_t)nb * ga);
     double *d_g = reinterpret_cast<double *>(p);
-    p += al(8 * (size_t)ng);
+    p += al(8 * (size_t)ng * ga);
     unsigned int *d_cnt = reinterpret_cast<unsigned int *>(p);
     GQ_HIP(hipMemcpyAsync(d_slots, slots.data(), sizeof(ScanSlot) * slots.size(), hipMemcpyHostToDevice, st));
     GQ_HIP(hipMemcpyAsync(d_lev, lev_all.data(), 4 * lev_all.size(), hipMemcpyHostToDevice, st));
     GQ_HIP(hipMemcpyAsync(d_w, w_all.data(), 4 * w_all.size(), hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemcpyAsync(d_b, betas, 8 * (size_t)nb, hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemcpyAsync(d_g, gammas, 8 * (size_t)ng, hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(d_b, betas, 8 * (size_t)nb * ga, hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(d_g, gammas, 8 * (size_t)ng * ga, hipMemcpyHostToDevice, st));
 
     ScanArgs a{};
     a.lev = d_lev;
@@ -476,6 +479,7 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
     a.ng = ng;
     a.ntiles = (nb + 63) / 64;
     a.num_p = num_p;
+    a.per_inst = per_inst;
     for (int q = 0; q < num_p; ++q) a.p_list[q] = p_list[q];
     for (int bk = 0; bk < kNumBuckets; ++bk) {
         const int nslots = bucket_first[bk + 1] - bucket_first[bk];

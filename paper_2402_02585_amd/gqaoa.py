@@ -38,8 +38,9 @@ _SIGS = {
     "gqaoa_grad": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_grad_batched": ([_i32, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_hist_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp], _i32),
-    "gqaoa_scan_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32], _sz),
-    "gqaoa_scan_batched": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_scan_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32, _i32], _sz),
+    "gqaoa_scan_batched": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                            _sz, _vp], _i32),
     "gqaoa_mlp_act_bytes": ([_i32], _sz),
     "gqaoa_mlp_forward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_mlp_backward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
@@ -226,14 +227,17 @@ def gqaoa_hist_evolve(n: int, m: int, hist, betas, gammas, target_level: int = 0
     return psol, energy, norm
 
 
-def gqaoa_scan_workspace_bytes(num_inst: int, hist_stride: int, nb: int, ng: int, num_p: int) -> int:
-    return int(load_library().gqaoa_scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p))
+def gqaoa_scan_workspace_bytes(num_inst: int, hist_stride: int, nb: int, ng: int, num_p: int,
+                               per_instance_grid: bool = False) -> int:
+    return int(load_library().gqaoa_scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p,
+                                                         int(bool(per_instance_grid))))
 
 
 def gqaoa_scan_batched(ns, ms, hists, betas, gammas, p_list, targets=None, tile=None, with_energy: bool = True,
                        out=None, workspace=None, stream=None):
-    """Single-angle-pair scan. hists: host int64/uint64 [I, stride].
-    Returns (psol, energy) float32 device tensors [I, num_p, ng, nb]."""
+    """Single-angle-pair scan. hists: host int64/uint64 [I, stride]. betas, gammas:
+    1-D (one grid shared by all instances) or 2-D [I, nb] / [I, ng] (a grid per
+    instance). Returns (psol, energy) float32 device tensors [I, num_p, ng, nb]."""
     torch = _torch()
     lib = load_library()
     ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
@@ -242,20 +246,24 @@ def gqaoa_scan_batched(ns, ms, hists, betas, gammas, p_list, targets=None, tile=
     I, stride = h.shape
     b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
     g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    per_inst = b.ndim == 2
+    if per_inst != (g.ndim == 2) or (per_inst and (b.shape[0] != I or g.shape[0] != I)):
+        raise ValueError("betas and gammas must both be 1-D, or both [num_inst, *]")
+    nb, ng = b.shape[-1], g.shape[-1]
     pl = np.ascontiguousarray(np.asarray(p_list, dtype=np.int32))
     tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
     tl = None if tile is None else np.ascontiguousarray(np.asarray(tile, dtype=np.int32))
-    shape = (I, pl.size, g.size, b.size)
+    shape = (I, pl.size, ng, nb)
     if out is None:
         psol = torch.empty(shape, dtype=torch.float32, device="cuda")
         energy = torch.empty(shape, dtype=torch.float32, device="cuda") if with_energy else None
     else:
         psol, energy = out
-    need = lib.gqaoa_scan_workspace_bytes(I, stride, b.size, g.size, pl.size)
+    need = lib.gqaoa_scan_workspace_bytes(I, stride, nb, ng, pl.size, int(per_inst))
     ws = workspace if workspace is not None else _workspace(torch, need)
-    _check(lib.gqaoa_scan_batched(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), b.size, _np_ptr(b),
-                                  g.size, _np_ptr(g), pl.size, _np_ptr(pl), _ptr(psol), _ptr(energy), _np_ptr(tl),
-                                  _ptr(ws), ws.numel(), _stream(torch, stream)))
+    _check(lib.gqaoa_scan_batched(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), nb, _np_ptr(b),
+                                  ng, _np_ptr(g), int(per_inst), pl.size, _np_ptr(pl), _ptr(psol), _ptr(energy),
+                                  _np_ptr(tl), _ptr(ws), ws.numel(), _stream(torch, stream)))
     return psol, energy
 
 

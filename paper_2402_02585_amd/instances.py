@@ -62,6 +62,9 @@ def random_3sat(rng: np.random.Generator, n: int, m: int, dup: str = "redraw") -
         raise ValueError("a 3-SAT clause needs n >= 3 variables")
     if dup not in ("redraw", "drop"):
         raise ValueError("dup must be 'redraw' or 'drop'")
+    distinct = 8 * (n * (n - 1) * (n - 2) // 6)   # 3-variable sets times sign patterns
+    if dup == "redraw" and m > distinct:
+        raise ValueError(f"only {distinct} distinct 3-literal clauses exist over {n} variables, asked for {m}")
     seen: set = set()
     out = []
     while len(out) < m:

@@ -1,0 +1,128 @@
+"""Learned single-angle-pair G-QAOA angles.
+
+The paper observes that optimized single-pair angles cluster, more tightly as
+the clause count grows (Sec. III.B), and suggests determining angles from
+statistics of the density of states (Sec. V). ``AngleMLP`` maps an
+instance's normalized level histogram and (n, d = m/n, p) to one (beta,
+gamma) pair with the device MLP (bfloat16 MFMA forward/backward, float32
+Adam); labels come from ``optim.batched_single_pair``. All arithmetic runs in
+libgqaoa kernels; this module only orders the calls.
+
+Reference points for judging the network:
+  * ``cluster_median``: one fixed pair per p (the median of the training
+    labels), i.e. what parameter clustering alone gives;
+  * the plain and batched optimizers of ``optim``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import gqaoa as g
+from . import optim
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class AngleMLP:
+    def __init__(self, seed: int = 0):
+        torch = _torch()
+        rng = np.random.Generator(np.random.PCG64(seed))
+        flat = np.zeros(g.MLP_NPARAMS, dtype=np.float32)
+        for key, fan_in in (("W1", 131), ("W2", 256), ("W3", 256)):
+            off, shape = g.MLP_OFFSETS[key]
+            bound = 1.0 / math.sqrt(fan_in)
+            w = np.zeros(shape, dtype=np.float32)
+            w[:fan_in] = rng.uniform(-bound, bound, size=(fan_in, shape[1]))
+            flat[off:off + w.size] = w.ravel()
+        self.params = torch.tensor(flat, device="cuda")
+        self.state = torch.zeros(2 * g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        self.grads = torch.empty(g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        self.step = 0
+
+    def outputs(self, x):
+        out, _ = g.gqaoa_mlp_forward(self.params, x)
+        return out
+
+    def angles(self, x):
+        """(beta, gamma) numpy arrays: beta = 2 pi sigmoid(o0), gamma = pi sigmoid(o1)."""
+        o = self.outputs(x).cpu().numpy().astype(np.float64)
+        s = 1.0 / (1.0 + np.exp(-o))
+        return 2 * math.pi * s[:, 0], math.pi * s[:, 1]
+
+    def train(self, X, Y, steps: int = 2000, batch: int = 512, lr: float = 1e-3, seed: int = 0, log_every: int = 0):
+        """Adam on the angle-regression loss. X [N, 131], Y [N, 2] device tensors."""
+        torch = _torch()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(seed)
+        N = X.shape[0]
+        losses = []
+        for s in range(steps):
+            idx = torch.randint(0, N, (min(batch, N),), device="cuda", generator=gen)
+            xb, yb = X[idx].contiguous(), Y[idx].contiguous()
+            out, act = g.gqaoa_mlp_forward(self.params, xb)
+            dout, loss = g.gqaoa_mlp_loss(out, yb)
+            g.gqaoa_mlp_backward(self.params, act, dout, grads=self.grads)
+            self.step += 1
+            g.gqaoa_mlp_adam(self.params, self.grads, self.state, self.step, lr=lr)
+            if log_every and (s % log_every == 0 or s == steps - 1):
+                losses.append((s, float(loss.item())))
+        return losses
+
+
+def features_for(hists_dev, ns, ms, p: int):
+    """Network inputs of every instance for round count p (device kernel)."""
+    torch = _torch()
+    I = hists_dev.shape[0]
+    nd = torch.tensor(np.asarray(ns, dtype=np.int32), device="cuda")
+    md = torch.tensor(np.asarray(ms, dtype=np.int32), device="cuda")
+    pd = torch.full((I,), p, dtype=torch.int32, device="cuda")
+    return g.gqaoa_mlp_features(hists_dev.contiguous(), nd, md, pd)
+
+
+def training_set(insts, p_list, grid=(128, 64)):
+    """(X [I*P, 131], Y [I*P, 2], labels dict) from batched-optimizer labels."""
+    torch = _torch()
+    ns = [it.n for it in insts]
+    ms = [it.m for it in insts]
+    stride = max(max(ms) + 1, 2)
+    hists_dev = g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=stride)
+    hists = hists_dev.cpu().numpy()
+    beta, gamma, psol, _ = optim.batched_single_pair(ns, ms, hists, p_list, grid=grid)
+    X = torch.cat([features_for(hists_dev, ns, ms, p) for p in p_list], dim=0)
+    Y = torch.tensor(np.concatenate([np.stack([beta[:, q], gamma[:, q]], 1) for q in range(len(p_list))]),
+                     dtype=torch.float32, device="cuda")
+    return X, Y, {"beta": beta, "gamma": gamma, "psol": psol, "hists": hists, "hists_dev": hists_dev,
+                  "ns": ns, "ms": ms}
+
+
+def cluster_median(labels, p_list):
+    """One (beta, gamma) per p: the median of the optimized training pairs."""
+    return {p: (float(np.median(labels["beta"][:, q])), float(np.median(labels["gamma"][:, q])))
+            for q, p in enumerate(p_list)}
+
+
+def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
+    """P_sol of every instance at its own (beta, gamma) after p rounds."""
+    I = len(ns)
+    b = np.asarray(betas, dtype=np.float64).reshape(I, 1)
+    gm = np.asarray(gammas, dtype=np.float64).reshape(I, 1)
+    ps, _ = g.gqaoa_scan_batched(ns, ms, hists, b, gm, [p], with_energy=False)
+    return ps.reshape(I).cpu().numpy().astype(np.float64)
+
+
+def refine_local(ns, ms, hists, betas, gammas, p: int, width: float = 0.08, zoom: int = 16):
+    """Best pair on a zoom x zoom window around each instance's pair (one launch)."""
+    I = len(ns)
+    offs = np.linspace(-width, width, zoom)
+    bgrid = np.asarray(betas)[:, None] + offs[None, :]
+    ggrid = np.clip(np.asarray(gammas)[:, None] + offs[None, :] / 2, 0.0, math.pi)
+    ps, _ = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], with_energy=False)
+    v = ps[:, 0].reshape(I, -1)
+    j = v.argmax(dim=1).cpu().numpy()
+    best = v.cpu().numpy()[np.arange(I), j].astype(np.float64)
+    return bgrid[np.arange(I), j % zoom], ggrid[np.arange(I), j // zoom], best

@@ -101,15 +101,16 @@ def test_grad_and_scan_argument_checks():
     hist = np.zeros((1, 43), dtype=np.uint64)
     hist[0, :5] = 1
     pl = np.array([4, 2], dtype=np.int32)                      # not ascending
-    ws = lib.gqaoa_scan_workspace_bytes(1, 43, 4, 4, 2)
+    ws = lib.gqaoa_scan_workspace_bytes(1, 43, 4, 4, 2, 0)
     assert lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 43, None, 4, g._np_ptr(b), 4,
-                                  g._np_ptr(b), 2, g._np_ptr(pl), d, None, None, d, ws, None) == -1
+                                  g._np_ptr(b), 0, 2, g._np_ptr(pl), d, None, None, d, ws, None) == -1
     pl = np.array([2, 4], dtype=np.int32)
     tile = np.array([3, 4], dtype=np.int32)                    # 3 waves per block is not offered
     assert lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 43, None, 4, g._np_ptr(b), 4,
-                                  g._np_ptr(b), 2, g._np_ptr(pl), d, None, g._np_ptr(tile), d, ws, None) == -1
+                                  g._np_ptr(b), 0, 2, g._np_ptr(pl), d, None, g._np_ptr(tile), d, ws, None) == -1
     assert lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 43, None, 4, g._np_ptr(b), 4,
-                                  g._np_ptr(b), 2, g._np_ptr(pl), d, None, None, d, ws - 1, None) == -3
+                                  g._np_ptr(b), 0, 2, g._np_ptr(pl), d, None, None, d, ws - 1, None) == -3
+    assert lib.gqaoa_scan_workspace_bytes(1, 43, 4, 4, 2, 1) >= ws
 
 
 def test_mlp_argument_checks():

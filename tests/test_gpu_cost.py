@@ -37,7 +37,7 @@ def test_cost_table_deterministic_and_two_level():
 
 def test_hist_batched_matches_oracle():
     need_gpu()
-    insts = inst.batched_scan_instances(3, 24, 3, 14, sat_only=False)
+    insts = inst.batched_scan_instances(3, 24, 4, 14, sat_only=False)
     ns = [it.n for it in insts]
     ms = [it.m for it in insts]
     hists = g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=80).cpu().numpy()

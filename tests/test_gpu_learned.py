@@ -1,0 +1,92 @@
+"""GPU: the learned angle predictor against the methods without it.
+
+Trains the device MLP on batched-optimizer labels of small seeded instances
+and checks on held-out instances that
+  * training reduces the loss,
+  * the predicted pairs beat the single fixed cluster-median pair per p (the
+    clustering-only baseline) in mean P_sol,
+  * with one local window scan, the learned form reaches >= 0.99 of the
+    batched optimizer's mean P_sol,
+  * the batched optimizer agrees with the plain per-call optimizer.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import log, need_gpu
+from oracle.cost import cost_table, level_histogram
+from oracle.evolve import psol_single_pair_hist
+from paper_2402_02585_amd import gqaoa as g
+from paper_2402_02585_amd import instances as inst
+from paper_2402_02585_amd import learned, optim
+
+pytestmark = pytest.mark.gpu
+P_LIST = [1, 4, 16]
+
+
+@pytest.fixture(scope="module")
+def trained():
+    torch = need_gpu()
+    train = inst.batched_scan_instances(5, 800, 10, 16)
+    X, Y, lab = learned.training_set(train, P_LIST, grid=(64, 32))
+    model = learned.AngleMLP(seed=0)
+    losses = model.train(X, Y, steps=1500, batch=256, lr=2e-3, log_every=500)
+    log(f"losses {losses}")
+    test = inst.batched_scan_instances(6, 200, 10, 16)
+    ns = [it.n for it in test]
+    ms = [it.m for it in test]
+    hd = g.gqaoa_hist_batched(ns, ms, [it.lits for it in test], hist_stride=max(ms) + 1)
+    return dict(model=model, losses=losses, lab=lab, test=test, ns=ns, ms=ms, hists_dev=hd,
+                hists=hd.cpu().numpy(), torch=torch)
+
+
+def test_training_reduces_loss(trained):
+    losses = trained["losses"]
+    assert losses[-1][1] < 0.5 * losses[0][1], losses
+
+
+def test_labels_match_oracle(trained):
+    """The batched optimizer's reported P_sol at its chosen pair is the oracle's."""
+    lab = trained["lab"]
+    rng = np.random.Generator(np.random.PCG64(1))
+    for i in rng.choice(len(lab["ns"]), 5, replace=False):
+        h = lab["hists"][i, :lab["ms"][i] + 1]
+        for q, p in enumerate(P_LIST):
+            ref = psol_single_pair_hist(h, lab["beta"][i, q], lab["gamma"][i, q], p)
+            assert abs(lab["psol"][i, q] - ref) < 1e-4
+
+
+def test_learned_beats_cluster_median_and_tracks_optimizer(trained):
+    model, lab = trained["model"], trained["lab"]
+    ns, ms, H, hd = trained["ns"], trained["ms"], trained["hists"], trained["hists_dev"]
+    med = learned.cluster_median(lab, P_LIST)
+    opt_b, opt_g, opt_p, _ = optim.batched_single_pair(ns, ms, H, P_LIST, grid=(64, 32))
+    for q, p in enumerate(P_LIST):
+        x = learned.features_for(hd, ns, ms, p)
+        bl, gl = model.angles(x)
+        p_learn = learned.evaluate_pairs(ns, ms, H, bl, gl, p)
+        p_med = learned.evaluate_pairs(ns, ms, H, np.full(len(ns), med[p][0]), np.full(len(ns), med[p][1]), p)
+        _, _, p_ref = learned.refine_local(ns, ms, H, bl, gl, p)
+        log(f"p={p}: learned {p_learn.mean():.4f}  cluster-median {p_med.mean():.4f}  "
+            f"learned+window {p_ref.mean():.4f}  optimizer {opt_p[:, q].mean():.4f}")
+        assert p_learn.mean() > p_med.mean()
+        assert p_ref.mean() >= 0.99 * opt_p[:, q].mean()
+
+
+def test_plain_optimizer_agrees_with_batched():
+    torch = need_gpu()
+    its = inst.batched_scan_instances(9, 3, 9, 11)
+    ns = [it.n for it in its]
+    ms = [it.m for it in its]
+    H = np.zeros((3, max(ms) + 1), dtype=np.int64)
+    for i, it in enumerate(its):
+        H[i, :it.m + 1] = level_histogram(cost_table(it.n, it.lits), it.m)
+    gb, gg = optim.fundamental_grid(48, 24)
+    ob, og, op, _ = optim.batched_single_pair(ns, ms, H, [4], grid=(48, 24))
+    for i, it in enumerate(its):
+        hdev = torch.tensor(H[i, :it.m + 1], device="cuda")
+        r = optim.plain_single_pair(it.n, it.m, hdev, 4, gb, gg)
+        assert r["psol"] >= op[i, 0] - 2e-3
+        assert r["psol"] == pytest.approx(psol_single_pair_hist(H[i, :it.m + 1], r["beta"], r["gamma"], 4), abs=1e-12)
+        assert op[i, 0] >= r["psol"] - 2e-3

@@ -28,6 +28,13 @@ def test_generator_is_deterministic():
     np.testing.assert_array_equal(a.lits, c.lits)
 
 
+def test_impossible_clause_count_raises():
+    rng = np.random.Generator(np.random.PCG64(3))
+    with pytest.raises(ValueError):
+        inst.random_3sat(rng, 3, 9)                      # only 8 distinct clauses on 3 variables
+    assert inst.random_3sat(rng, 3, 8).shape == (8, 3)
+
+
 def test_drop_mode_can_shrink():
     rng = np.random.Generator(np.random.PCG64(3))
     lits = inst.random_3sat(rng, 3, 8, dup="drop")     # only 8 distinct clauses exist
