@@ -155,6 +155,50 @@ def batched_leg(torch, g, inst, steps: int):
     }
 
 
+def adjoint_leg(torch, g, inst, reps: int = 2):
+    """Adjoint workload: 256 satisfiable instances, n = 20, m = 85, p = 32
+    independent angles, complex128, checkpoints every 8 rounds."""
+    n, m, p, I, ckpt = 20, 85, 32, 256, 8
+    lits = []
+    for _, l in inst.sat_stream(4, n, m):
+        if inst.dpll_satisfiable(n, l):
+            lits.append(l)
+        if len(lits) == I:
+            break
+    costs = torch.empty((I, 1 << n), dtype=torch.uint8, device="cuda")
+    for i, l in enumerate(lits):
+        g.gqaoa_cost_table(n, l, with_hist=False, cost=costs[i])
+    betas = np.stack([inst.uniform_angles(100 + i, p)[0] for i in range(I)])
+    gammas = np.stack([inst.uniform_angles(100 + i, p)[1] for i in range(I)])
+    ws = torch.empty(g.gqaoa_grad_workspace_bytes(I, n, p, g.C128, ckpt), dtype=torch.uint8, device="cuda")
+    g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, g.C128, None, ckpt, workspace=ws)   # warm-up
+    torch.cuda.synchronize()
+    g.gqaoa_profile_reset()
+    g.gqaoa_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P, db, dg = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, g.C128, None, ckpt, workspace=ws)
+    dt = (time.perf_counter() - t0) / reps
+    g.gqaoa_profile_enable(False)
+    rev_ms, rev_cnt = g.gqaoa_profile_read("sv_reverse_c128")
+    fwd_ms, fwd_cnt = g.gqaoa_profile_read("sv_round_c128")
+    N = I * (1 << n)
+    amp_rounds = N * p
+    # algorithmic bytes: forward 33 B, segment recompute 33 B, reverse 49 B per amplitude-round
+    rev_bytes = N * 49
+    fwd_bytes = N * 33
+    return {
+        "workload": f"{I} satisfiable instances n={n} m={m} (seed 4 stream), p={p} independent angles, complex128, "
+                    f"checkpoint every {ckpt} rounds",
+        "seconds_per_gradient_batch": dt, "amplitude_rounds_per_s": amp_rounds / dt,
+        "reverse_pass": {"avg_launch_ms": rev_ms / max(rev_cnt, 1),
+                         "GBps": rev_bytes / (rev_ms / max(rev_cnt, 1) * 1e-3) / 1e9},
+        "forward_pass": {"avg_launch_ms": fwd_ms / max(fwd_cnt, 1),
+                         "GBps": fwd_bytes / (fwd_ms / max(fwd_cnt, 1) * 1e-3) / 1e9},
+        "mean_psol": float(np.mean(P)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,8 +206,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the cpu_baseline leg")
     ap.add_argument("--skip-batched", action="store_true", help="omit the batched-scan leg")
+    ap.add_argument("--skip-adjoint", action="store_true", help="omit the adjoint-gradient leg")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 2 GiB device copy (for counter calibration) and exit")
+                    help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is not implemented)",
@@ -186,8 +231,9 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        log("copied 3 x 2 GiB")
-        return
+        log("copied 3 x 2 GiB (2^31 bytes read and written per copy)")
+        del src, dst
+        torch.cuda.empty_cache()
 
     it = inst.first_satisfiable(2, N_VARS, M_CLAUSES)
     beta, gamma = inst.uniform_angles(2, P_ROUNDS)
@@ -228,7 +274,7 @@ def main():
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "sv_forward_kernel<float,PHASE,WRITE,4,4>", "avg_launch_ms": avg_round_ms,
+                "kernel": "sv_forward_kernel<float, true, true, 2, 8, 1>", "avg_launch_ms": avg_round_ms,
                 "launches": round_cnt, "algorithmic_bytes_per_launch": bytes_per_launch}
     cost_table = {"avg_launch_ms": ct_ms / max(ct_cnt, 1),
                   "clause_evals_per_s": M_CLAUSES * N / (ct_ms / max(ct_cnt, 1) * 1e-3)}
@@ -244,8 +290,12 @@ def main():
         "roofline": roofline,
         "cost_table": cost_table,
     }
+    del psi, ws
+    torch.cuda.empty_cache()
     if not args.skip_batched:
         out["batched"] = batched_leg(torch, g, inst, max(3, args.steps // 2))
+    if not args.skip_adjoint:
+        out["adjoint"] = adjoint_leg(torch, g, inst)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

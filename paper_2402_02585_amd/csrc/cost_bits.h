@@ -59,11 +59,17 @@ GQ_HD bool high_literals_false(uint64_t zwave, uint64_t hivar, uint64_t hineg) {
     return ((zwave ^ hineg) & hivar) == 0;
 }
 
-// Carry-save adder: a + b + c = 2*hi + lo, bitwise.
+// Carry-save adder: a + b + c = 2*hi + lo, bitwise. On the device each output
+// is one v_bitop3_b32 (truth tables 0x96 = three-input XOR, 0xE8 = majority).
 GQ_HD void csa(uint32_t &hi, uint32_t &lo, uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    hi = __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+    lo = __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
     const uint32_t u = a ^ b;
     hi = (a & b) | (u & c);
     lo = u ^ c;
+#endif
 }
 
 // Bit-sliced 8-bit counters, one per word bit: count = sum_b plane[b] << b.
@@ -139,14 +145,19 @@ inline void pack_clauses(int m, const int32_t *lits, std::vector<ClauseRec> &vec
             const int lit = lits[3 * i + j];
             const int v = lit >> 1, neg = lit & 1;
             if (v < kLowBits) {
-                const uint32_t pat = low_var_pattern(v);
+                static const uint32_t kLowPat[kLowBits] = {low_var_pattern(0), low_var_pattern(1),
+                                                          low_var_pattern(2), low_var_pattern(3),
+                                                          low_var_pattern(4)};
+                const uint32_t pat = kLowPat[v];
                 r.P &= neg ? pat : ~pat;     // false iff bit v == neg
                 uniform = false;
             } else if (v < kHighBit0) {
-                uint64_t L = 0;
-                for (int l = 0; l < 64; ++l)
-                    if (((l >> (v - kLowBits)) & 1) == neg) L |= 1ull << l;
-                r.L &= L;
+                // lanes whose bit (v - 5) is 1
+                static const uint64_t kLaneBit[kLaneBits] = {
+                    0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+                    0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+                const uint64_t ones = kLaneBit[v - kLowBits];
+                r.L &= neg ? ones : ~ones;   // false iff the lane's bit equals neg
                 uniform = false;
             } else {
                 r.hivar |= 1ull << v;

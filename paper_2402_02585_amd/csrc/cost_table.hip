@@ -5,11 +5,14 @@
 // N_k = #{z : C(z) = k} is the per-level state count of App. C. The word
 // layout and clause records are described in cost_bits.h.
 //
-// Each lane evaluates one 32-assignment word per loop trip: per clause one
-// v_cndmask selects the low-literal pattern P when the clause is active for
-// this lane, then a carry-save adder tree folds 16 clauses at a time into
-// eight bit-planes; 8x8 bit transposes turn the planes into byte costs.
-// Clauses whose variables all sit in wave-uniform bits add a scalar count.
+// Each lane evaluates one 32-assignment word per loop trip. Per wave tile the
+// lanes first test the wave-uniform (high) literals of 64 clauses at a time and
+// leave each clause's effective lane mask in wave-private LDS; then, per
+// clause, one LDS broadcast read and a sign-extended bit extract select the
+// low-literal pattern P for this lane, and a carry-save adder tree folds 16
+// clauses at a time into eight bit-planes; 8x8 bit transposes turn the planes
+// into byte costs. Clauses whose variables all sit in wave-uniform bits add a
+// count found by a ballot.
 // The histogram is tallied in LDS (one copy per wave) and written as per-block
 // rows, which a second kernel sums in a fixed order.
 #include "internal.h"
@@ -23,29 +26,60 @@ namespace gqaoa {
 
 constexpr int kCostThreads = 256;
 constexpr int kCostWaves = kCostThreads / kWave;
+constexpr int kMaxVec = 256;  // padded clause records per instance (m <= 255)
+// LDS histogram copies per block: two per wave (by lane parity), so lanes that
+// tally the same level are spread over more addresses.
+constexpr int kHistCopies = kCostWaves * 2;
 
-// Costs of the 32 assignments of word w (bytes, p[r] byte q = C(32w + 4r + q)).
-__device__ __forceinline__ void eval_word(const ClauseRec *__restrict__ vec, int nvec,
-                                          const UniformRec *__restrict__ uni, int nuni,
-                                          uint64_t w, uint32_t (&out)[8]) {
-    const uint64_t zw = (w & ~63ull) << kLowBits;
-    // every active lane of the wave has the same high bits: make them scalar
-    const uint32_t zlo = __builtin_amdgcn_readfirstlane((uint32_t)zw);
-    const uint32_t zhi = __builtin_amdgcn_readfirstlane((uint32_t)(zw >> 32));
-    const uint64_t zwave = ((uint64_t)zhi << 32) | zlo;
+// A clause's effective masks for one wave-tile, as each half-wave reads them:
+// entry [c][h] = {P, bits 32h..32h+31 of L_eff} with L_eff = L if the clause's
+// high literals are all false in this tile, else 0.
+struct EffEntry {
+    uint32_t P, Lhalf;
+};
 
+struct CostLds {
+    EffEntry eff[kCostWaves][kMaxVec][2];
+    uint32_t hist[kHistCopies][256];
+};
+
+__device__ __forceinline__ uint32_t *hist_copy(CostLds &s) {
+    return s.hist[(threadIdx.x / kWave) * 2 + (threadIdx.x & 1)];
+}
+
+// Costs of the 32 assignments of word tile*64 + lane (bytes: out[r] byte q is
+// C(32 w + 4 r + q)). Every lane of the wave must call this with the same tile.
+__device__ __forceinline__ void eval_tile(const ClauseRec *__restrict__ vec, int nvec,
+                                          const UniformRec *__restrict__ uni, int nuni, uint64_t tile,
+                                          EffEntry (*eff)[2], uint32_t (&out)[8]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t zwave = (tile * kWave) << kLowBits;   // z of lane 0, bit 0
+    // 1) high-literal test of 64 clauses at a time, one per lane
+    for (int c = lane; c < nvec; c += kWave) {
+        const ClauseRec r = vec[c];
+        const uint64_t L = high_literals_false(zwave, r.hivar, r.hineg) ? r.L : 0ull;
+        eff[c][0] = EffEntry{r.P, (uint32_t)L};
+        eff[c][1] = EffEntry{r.P, (uint32_t)(L >> 32)};
+    }
     uint32_t u = 0;
-    for (int i = 0; i < nuni; ++i) u += high_literals_false(zwave, uni[i].hivar, uni[i].hineg);
-
+    for (int c0 = 0; c0 < nuni; c0 += kWave) {
+        const int c = c0 + lane;
+        const bool f = c < nuni && high_literals_false(zwave, uni[c].hivar, uni[c].hineg);
+        u += (uint32_t)__popcll(__ballot(f));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 2) per clause: the lane's bit of L_eff selects P; 16 clauses per adder tree
+    const int half = lane >> 5, bit = lane & 31;
     SlicedCounter cnt;
     cnt.clear();
     for (int g = 0; g < nvec; g += kGroup) {
         uint32_t f[kGroup];
 #pragma unroll
         for (int i = 0; i < kGroup; ++i) {
-            const ClauseRec r = vec[g + i];
-            const uint64_t L = high_literals_false(zwave, r.hivar, r.hineg) ? r.L : 0ull;
-            f[i] = __builtin_amdgcn_inverse_ballot_w64(L) ? r.P : 0u;
+            const EffEntry e = eff[g + i][half];
+            f[i] = e.P & (uint32_t)__builtin_amdgcn_sbfe((int)e.Lhalf, bit, 1);
         }
         cnt.add16(f);
     }
@@ -53,6 +87,8 @@ __device__ __forceinline__ void eval_word(const ClauseRec *__restrict__ vec, int
     const uint32_t ub = u * 0x01010101u;  // no byte overflows: every count <= m <= 255
 #pragma unroll
     for (int r = 0; r < 8; ++r) out[r] = cnt.p[r] + ub;
+    // the next tile rewrites eff: every lane's reads of this one come first
+    __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ void tally(uint32_t *h, uint32_t v) {
@@ -62,51 +98,69 @@ __device__ __forceinline__ void tally(uint32_t *h, uint32_t v) {
     atomicAdd(h + (v >> 24), 1u);
 }
 
+__device__ __forceinline__ void tally_word(uint32_t *h, const uint32_t (&t)[8], uint32_t nbits) {
+    if (nbits == 32u) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) tally(h, t[r]);
+    } else {
+        for (uint32_t z = 0; z < nbits; ++z) atomicAdd(h + ((t[z >> 2] >> (8 * (z & 3))) & 0xFFu), 1u);
+    }
+}
+
 __global__ void __launch_bounds__(kCostThreads)
 cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec *__restrict__ uni,
                   int nuni, int n, uint8_t *__restrict__ cost, uint32_t *__restrict__ block_hist,
                   int hist_len) {
-    __shared__ uint32_t lhist[kCostWaves][256];
-    for (int i = threadIdx.x; i < kCostWaves * 256; i += kCostThreads) (&lhist[0][0])[i] = 0;
+    __shared__ CostLds lds;
+    for (int i = threadIdx.x; i < kHistCopies * 256; i += kCostThreads) (&lds.hist[0][0])[i] = 0;
     __syncthreads();
-    uint32_t *h = lhist[threadIdx.x / kWave];
+    uint32_t *h = hist_copy(lds);
+    EffEntry(*eff)[2] = lds.eff[threadIdx.x / kWave];
     const uint64_t N = 1ull << n;
     const uint64_t nwords = n >= kLowBits ? (N >> kLowBits) : 1;
-    const uint64_t stride = (uint64_t)gridDim.x * kCostThreads;
-    for (uint64_t w = (uint64_t)blockIdx.x * kCostThreads + threadIdx.x; w < nwords; w += stride) {
+    const uint64_t ntiles = (nwords + kWave - 1) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * kCostWaves;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (uint64_t tile = (uint64_t)blockIdx.x * kCostWaves + threadIdx.x / kWave; tile < ntiles; tile += nwaves) {
         uint32_t t[8];
-        eval_word(vec, nvec, uni, nuni, w, t);
+        eval_tile(vec, nvec, uni, nuni, tile, eff, t);
+        const uint64_t w = tile * kWave + lane;
+        if (w >= nwords) continue;
         if (n >= kLowBits) {
             typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
             u32x4 *dst = reinterpret_cast<u32x4 *>(cost + (w << kLowBits));
             dst[0] = u32x4{t[0], t[1], t[2], t[3]};
             dst[1] = u32x4{t[4], t[5], t[6], t[7]};
-#pragma unroll
-            for (int r = 0; r < 8; ++r) tally(h, t[r]);
+            tally_word(h, t, 32u);
         } else {
-            for (uint32_t z = 0; z < (uint32_t)N; ++z) {
-                const uint32_t v = (t[z >> 2] >> (8 * (z & 3))) & 0xFFu;
-                cost[z] = (uint8_t)v;
-                atomicAdd(h + v, 1u);
-            }
+            for (uint32_t z = 0; z < (uint32_t)N; ++z) cost[z] = (uint8_t)((t[z >> 2] >> (8 * (z & 3))) & 0xFFu);
+            tally_word(h, t, (uint32_t)N);
         }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < hist_len; k += kCostThreads) {
         uint32_t s = 0;
-        for (int wv = 0; wv < kCostWaves; ++wv) s += lhist[wv][k];
+        for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c][k];
         block_hist[(size_t)blockIdx.x * hist_len + k] = s;
     }
 }
 
-// hist[k] = sum over blocks of block_hist[b][k], fixed order.
-__global__ void hist_reduce_kernel(const uint32_t *__restrict__ block_hist, int nblocks,
-                                   int hist_len, unsigned long long *__restrict__ hist) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= hist_len) return;
+// hist[k] = sum over blocks of block_hist[b][k]: one block per level k, every
+// thread sums a strided subset of rows (integer sums, so the order is free).
+__global__ void __launch_bounds__(256) hist_reduce_kernel(const uint32_t *__restrict__ block_hist,
+                                                          int nblocks, int hist_len,
+                                                          unsigned long long *__restrict__ hist) {
+    __shared__ unsigned long long red[256];
+    const int k = blockIdx.x;
     unsigned long long s = 0;
-    for (int b = 0; b < nblocks; ++b) s += block_hist[(size_t)b * hist_len + k];
-    hist[k] = s;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += block_hist[(size_t)b * hist_len + k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hist[k] = red[0];
 }
 
 // ---- many instances, histograms only ---------------------------------------
@@ -123,28 +177,27 @@ __global__ void __launch_bounds__(kCostThreads)
 hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restrict__ units,
                     const ClauseRec *__restrict__ vec, const UniformRec *__restrict__ uni,
                     unsigned long long *__restrict__ hists, int hist_stride) {
-    __shared__ uint32_t lhist[kCostWaves][256];
-    for (int i = threadIdx.x; i < kCostWaves * 256; i += kCostThreads) (&lhist[0][0])[i] = 0;
+    __shared__ CostLds lds;
+    for (int i = threadIdx.x; i < kHistCopies * 256; i += kCostThreads) (&lds.hist[0][0])[i] = 0;
     __syncthreads();
     const HistUnit unit = units[blockIdx.x];
     const HistInst in = insts[unit.inst];
-    uint32_t *h = lhist[threadIdx.x / kWave];
+    uint32_t *h = hist_copy(lds);
+    EffEntry(*eff)[2] = lds.eff[threadIdx.x / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
     const uint32_t nbits = in.n >= kLowBits ? 32u : (1u << in.n);
-    for (uint32_t i = threadIdx.x; i < unit.nwords; i += kCostThreads) {
-        const uint64_t w = (uint64_t)unit.word0 + i;
+    const uint32_t ntiles = (unit.nwords + kWave - 1) / kWave;
+    for (uint32_t t0 = threadIdx.x / kWave; t0 < ntiles; t0 += kCostWaves) {
+        // word0 is a multiple of 64, so tile (word0 / 64 + t0) starts at word0 + 64 t0
+        const uint64_t tile = (uint64_t)unit.word0 / kWave + t0;
         uint32_t t[8];
-        eval_word(vec + in.vec_off, in.nvec, uni + in.uni_off, in.nuni, w, t);
-        if (nbits == 32u) {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) tally(h, t[r]);
-        } else {
-            for (uint32_t z = 0; z < nbits; ++z) atomicAdd(h + ((t[z >> 2] >> (8 * (z & 3))) & 0xFFu), 1u);
-        }
+        eval_tile(vec + in.vec_off, in.nvec, uni + in.uni_off, in.nuni, tile, eff, t);
+        if (t0 * kWave + lane < unit.nwords) tally_word(h, t, nbits);
     }
     __syncthreads();
     for (int k = threadIdx.x; k <= in.m; k += kCostThreads) {
         uint32_t s = 0;
-        for (int wv = 0; wv < kCostWaves; ++wv) s += lhist[wv][k];
+        for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c][k];
         if (s) atomicAdd(hists + (size_t)unit.inst * hist_stride + k, (unsigned long long)s);
     }
 }
@@ -181,7 +234,7 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     ps.end();
     GQ_LAUNCH_CHECK();
     if (hist) {
-        hipLaunchKernelGGL(hist_reduce_kernel, dim3(1), dim3(256), 0, stream, d_bh, nblocks, hist_len,
+        hipLaunchKernelGGL(hist_reduce_kernel, dim3(hist_len), dim3(256), 0, stream, d_bh, nblocks, hist_len,
                            reinterpret_cast<unsigned long long *>(hist));
         GQ_LAUNCH_CHECK();
     }

@@ -34,6 +34,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSvThreads = 256;
+constexpr int kMaxPassRowsPerInst = 4096;  // blocks of one instance in a streaming pass
 constexpr int kFwdR = 7;   // S.re, S.im, psol, energy, norm, T.re, T.im (T = sum over target level)
 constexpr int kRevR = 4;   // L.re, L.im (sum of lambda_{k-1}), G.re, G.im
 
@@ -52,17 +53,29 @@ __device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {  // conj(a) * b
 }
 
 // ---- vectorized amplitude and cost I/O ---------------------------------------
-template <typename T, int AMP>
+// NT = 1: nontemporal loads and stores (streamed data is not kept in the caches).
+template <int NT, typename V>
+__device__ __forceinline__ V ld(const V *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <int NT, typename V>
+__device__ __forceinline__ void st(V v, V *p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename T, int AMP, int NT = 1>
 struct AmpIO;
 
-template <int AMP>
-struct AmpIO<float, AMP> {
+template <int AMP, int NT>
+struct AmpIO<float, AMP, NT> {
     static_assert(AMP >= 2 && AMP % 2 == 0, "complex64 chunks hold pairs of amplitudes");
     static __device__ __forceinline__ void load(const void *p, Cx<float> (&a)[AMP]) {
         const f32x4 *q = reinterpret_cast<const f32x4 *>(p);
 #pragma unroll
         for (int i = 0; i < AMP / 2; ++i) {
-            const f32x4 v = __builtin_nontemporal_load(q + i);
+            const f32x4 v = ld<NT>(q + i);
             a[2 * i] = {v.x, v.y};
             a[2 * i + 1] = {v.z, v.w};
         }
@@ -71,24 +84,24 @@ struct AmpIO<float, AMP> {
         f32x4 *q = reinterpret_cast<f32x4 *>(p);
 #pragma unroll
         for (int i = 0; i < AMP / 2; ++i)
-            __builtin_nontemporal_store(f32x4{a[2 * i].re, a[2 * i].im, a[2 * i + 1].re, a[2 * i + 1].im}, q + i);
+            st<NT>(f32x4{a[2 * i].re, a[2 * i].im, a[2 * i + 1].re, a[2 * i + 1].im}, q + i);
     }
 };
 
-template <int AMP>
-struct AmpIO<double, AMP> {
+template <int AMP, int NT>
+struct AmpIO<double, AMP, NT> {
     static __device__ __forceinline__ void load(const void *p, Cx<double> (&a)[AMP]) {
         const f64x2 *q = reinterpret_cast<const f64x2 *>(p);
 #pragma unroll
         for (int i = 0; i < AMP; ++i) {
-            const f64x2 v = __builtin_nontemporal_load(q + i);
+            const f64x2 v = ld<NT>(q + i);
             a[i] = {v.x, v.y};
         }
     }
     static __device__ __forceinline__ void store(void *p, const Cx<double> (&a)[AMP]) {
         f64x2 *q = reinterpret_cast<f64x2 *>(p);
 #pragma unroll
-        for (int i = 0; i < AMP; ++i) __builtin_nontemporal_store(f64x2{a[i].re, a[i].im}, q + i);
+        for (int i = 0; i < AMP; ++i) st<NT>(f64x2{a[i].re, a[i].im}, q + i);
     }
 };
 
@@ -129,6 +142,92 @@ struct Acc<double> {
     using t = double;
 };
 
+struct FinArgs {
+    const double *partials;  // [inst][nblocks][kFwdR]
+    int nblocks;
+    double inv_N;
+    // per instance (strided by the *_stride fields, all in doubles)
+    const double *mixf;      // e^{-i beta_j} - 1 for this round; null in the last pass
+    int mixf_stride;
+    double *delta_out;       // delta_j
+    double *S_out;           // S_j
+    double *readout_out;     // psol, E, norm of the state before this pass's phase
+    double *T_out;           // sum over the target level (last pass only)
+    int stride;              // stride for delta_out/S_out/T_out per instance
+    int readout_stride;
+    // adjoint set-up after the last forward pass: eps_p and dbeta_p
+    const double *mixb;      // e^{+i beta_p} - 1, null: skip
+    const double *ebeta;     // e^{-i beta_p}
+    const double *S_p;       // S_p
+    double *eps_out;
+    double *dbeta_out;
+    int mix_stride;          // doubles per instance in mixb / ebeta (2p)
+    int grad_stride;         // doubles per instance in dbeta (p)
+};
+
+// Turn the summed partials of one instance into its readouts and delta_j.
+__device__ __forceinline__ void finalize_apply(const FinArgs &a, int inst, const double (&r)[kFwdR]) {
+    if (a.readout_out) {
+        double *ro = a.readout_out + (size_t)inst * a.readout_stride;
+        ro[0] = r[2];
+        ro[1] = r[3];
+        ro[2] = r[4];
+    }
+    if (a.mixf) {
+        const double *mf = a.mixf + (size_t)inst * a.mixf_stride;
+        const double sr = r[0] * a.inv_N, si = r[1] * a.inv_N;
+        double *d = a.delta_out + (size_t)inst * a.stride;
+        d[0] = mf[0] * sr - mf[1] * si;
+        d[1] = mf[0] * si + mf[1] * sr;
+        if (a.S_out) {
+            double *s = a.S_out + (size_t)inst * a.stride;
+            s[0] = r[0];
+            s[1] = r[1];
+        }
+    }
+    if (a.T_out) {
+        double *t = a.T_out + (size_t)inst * a.stride;
+        t[0] = r[5];
+        t[1] = r[6];
+    }
+    if (a.mixb) {
+        // eps_p = (e^{+i beta_p}-1) sum(lambda_p)/N, sum(lambda_p) = T
+        const double *mb = a.mixb + (size_t)inst * a.mix_stride;
+        const double tr = r[5], ti = r[6];
+        double *e = a.eps_out + (size_t)inst * 2;
+        e[0] = (mb[0] * tr - mb[1] * ti) * a.inv_N;
+        e[1] = (mb[0] * ti + mb[1] * tr) * a.inv_N;
+        // dbeta_p = 2 Re(-i e^{-i beta_p} conj(T) S_p) / N
+        const double *eb = a.ebeta + (size_t)inst * a.mix_stride;
+        const double *sp = a.S_p + (size_t)inst * a.stride;
+        const double xr = tr * sp[0] + ti * sp[1], xi = tr * sp[1] - ti * sp[0];  // conj(T) S
+        const double yi = eb[0] * xi + eb[1] * xr;                                // Im(e^{-i b} x)
+        a.dbeta_out[(size_t)inst * a.grad_stride] = 2.0 * yi * a.inv_N;          // Re(-i y) = Im y
+    }
+}
+
+// Fixed-order sum of the nrows x R partials of one instance by kThreads
+// threads (rows strided over threads, then a block reduction).
+template <int R, int kThreads>
+__device__ __forceinline__ void reduce_rows(const double *p, int nrows, double (&r)[R], double *lds) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) r[k] = 0.0;
+    for (int b0 = threadIdx.x; b0 < nrows; b0 += 4 * kThreads) {
+        double v[4][R];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int b = b0 + i * kThreads;
+#pragma unroll
+            for (int k = 0; k < R; ++k) v[i][k] = b < nrows ? p[(size_t)b * R + k] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int k = 0; k < R; ++k) r[k] += v[i][k];
+    }
+    block_sum<R, kThreads>(r, lds);
+}
+
 // ---- forward pass ---------------------------------------------------------------
 struct FwdArgs {
     const uint8_t *cost;     // [inst][N]
@@ -144,9 +243,14 @@ struct FwdArgs {
     double init_amp;
     const int32_t *target;   // [inst]
     double *partials;        // [inst][gridDim.x][kFwdR]
+    unsigned int *counter;   // [inst] blocks finished (fused finalize only; zero between launches)
+    FinArgs fin;             // finalize of this round (fused finalize only)
 };
 
-template <typename T, bool PHASE, bool WRITE, int AMP, int UNROLL>
+// FUSED: the last block of each instance to finish (counted with a device-scope
+// atomic after a release fence) sums all partial rows in the fixed row order
+// and applies the finalize itself, so a round is a single launch.
+template <typename T, bool PHASE, bool WRITE, int AMP, int UNROLL, int NT = 1, bool FUSED = false>
 __global__ void __launch_bounds__(kSvThreads) sv_forward_kernel(FwdArgs a) {
     __shared__ Cx<T> lut_s[256];
     __shared__ double red_s[kFwdR * kSvThreads / kWave];
@@ -181,7 +285,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_forward_kernel(FwdArgs a) {
             const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
             if (idx < a.N) {
                 load_costs<AMP>(cost + idx, c[u]);
-                if (!a.init_uniform) AmpIO<T, AMP>::load(src + idx, v[u]);
+                if (!a.init_uniform) AmpIO<T, AMP, NT>::load(src + idx, v[u]);
             } else {
 #pragma unroll
                 for (int i = 0; i < AMP; ++i) c[u][i] = 0xFFFFu;  // never a target level
@@ -217,7 +321,7 @@ __global__ void __launch_bounds__(kSvThreads) sv_forward_kernel(FwdArgs a) {
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
                 const uint64_t idx = base + (uint64_t)u * kWave * AMP + (uint64_t)lane * AMP;
-                if (idx < a.N) AmpIO<T, AMP>::store(dst + idx, v[u]);
+                if (idx < a.N) AmpIO<T, AMP, NT>::store(dst + idx, v[u]);
             }
         }
     }
@@ -227,6 +331,24 @@ __global__ void __launch_bounds__(kSvThreads) sv_forward_kernel(FwdArgs a) {
         double *out = a.partials + ((size_t)inst * gridDim.x + blockIdx.x) * kFwdR;
 #pragma unroll
         for (int k = 0; k < kFwdR; ++k) out[k] = r[k];
+    }
+    if constexpr (FUSED) {
+        __shared__ int last_s;
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned int done = atomicAdd(a.counter + inst, 1u);
+            last_s = done == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (last_s) {
+            __threadfence();
+            double t[kFwdR];
+            reduce_rows<kFwdR, kSvThreads>(a.partials + (size_t)inst * gridDim.x * kFwdR, gridDim.x, t, red_s);
+            if (threadIdx.x == 0) {
+                finalize_apply(a.fin, inst, t);
+                a.counter[inst] = 0u;
+            }
+        }
     }
 }
 
@@ -334,83 +456,37 @@ __global__ void __launch_bounds__(kSvThreads) sv_reverse_kernel(RevArgs a) {
 }
 
 // ---- finalizers (one block per instance, fixed-order sums) ------------------------
+// 1024 threads, each summing at most kFinRows rows of partials whose loads
+// are all issued before the first add: the finalize sits between two
+// bandwidth-bound passes, so its cost is one memory latency, not a chain.
+constexpr int kFinThreads = 1024;
+constexpr int kFinRows = kMaxPassRowsPerInst / kFinThreads;
+
 template <int R>
 __device__ __forceinline__ void reduce_partials(const double *p, int nblocks, double (&r)[R],
                                                 double *lds) {
+    double v[kFinRows][R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) r[k] = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kSvThreads)
+    for (int i = 0; i < kFinRows; ++i) {
+        const int b = threadIdx.x + i * kFinThreads;
 #pragma unroll
-        for (int k = 0; k < R; ++k) r[k] += p[(size_t)b * R + k];
-    block_sum<R, kSvThreads>(r, lds);
+        for (int k = 0; k < R; ++k) v[i][k] = b < nblocks ? p[(size_t)b * R + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        r[k] = 0.0;
+#pragma unroll
+        for (int i = 0; i < kFinRows; ++i) r[k] += v[i][k];
+    }
+    block_sum<R, kFinThreads>(r, lds);
 }
 
-struct FinArgs {
-    const double *partials;  // [inst][nblocks][kFwdR]
-    int nblocks;
-    double inv_N;
-    // per instance (strided by the *_stride fields, all in doubles)
-    const double *mixf;      // e^{-i beta_j} - 1 for this round; null in the last pass
-    int mixf_stride;
-    double *delta_out;       // delta_j
-    double *S_out;           // S_j
-    double *readout_out;     // psol, E, norm of the state before this pass's phase
-    double *T_out;           // sum over the target level (last pass only)
-    int stride;              // stride for delta_out/S_out/T_out per instance
-    int readout_stride;
-    // adjoint set-up after the last forward pass: eps_p and dbeta_p
-    const double *mixb;      // e^{+i beta_p} - 1, null: skip
-    const double *ebeta;     // e^{-i beta_p}
-    const double *S_p;       // S_p
-    double *eps_out;
-    double *dbeta_out;
-    int mix_stride;          // doubles per instance in mixb / ebeta (2p)
-    int grad_stride;         // doubles per instance in dbeta (p)
-};
-
-__global__ void __launch_bounds__(kSvThreads) sv_finalize_kernel(FinArgs a) {
-    __shared__ double lds[kFwdR * kSvThreads / kWave];
+__global__ void __launch_bounds__(kFinThreads) sv_finalize_kernel(FinArgs a) {
+    __shared__ double lds[kFwdR * kFinThreads / kWave];
     const int inst = blockIdx.x;
     double r[kFwdR];
     reduce_partials<kFwdR>(a.partials + (size_t)inst * a.nblocks * kFwdR, a.nblocks, r, lds);
-    if (threadIdx.x != 0) return;
-    if (a.readout_out) {
-        double *ro = a.readout_out + (size_t)inst * a.readout_stride;
-        ro[0] = r[2];
-        ro[1] = r[3];
-        ro[2] = r[4];
-    }
-    if (a.mixf) {
-        const double *mf = a.mixf + (size_t)inst * a.mixf_stride;
-        const double sr = r[0] * a.inv_N, si = r[1] * a.inv_N;
-        double *d = a.delta_out + (size_t)inst * a.stride;
-        d[0] = mf[0] * sr - mf[1] * si;
-        d[1] = mf[0] * si + mf[1] * sr;
-        if (a.S_out) {
-            double *s = a.S_out + (size_t)inst * a.stride;
-            s[0] = r[0];
-            s[1] = r[1];
-        }
-    }
-    if (a.T_out) {
-        double *t = a.T_out + (size_t)inst * a.stride;
-        t[0] = r[5];
-        t[1] = r[6];
-    }
-    if (a.mixb) {
-        // eps_p = (e^{+i beta_p}-1) sum(lambda_p)/N, sum(lambda_p) = T
-        const double *mb = a.mixb + (size_t)inst * a.mix_stride;
-        const double tr = r[5], ti = r[6];
-        double *e = a.eps_out + (size_t)inst * 2;
-        e[0] = (mb[0] * tr - mb[1] * ti) * a.inv_N;
-        e[1] = (mb[0] * ti + mb[1] * tr) * a.inv_N;
-        // dbeta_p = 2 Re(-i e^{-i beta_p} conj(T) S_p) / N
-        const double *eb = a.ebeta + (size_t)inst * a.mix_stride;
-        const double *sp = a.S_p + (size_t)inst * a.stride;
-        const double xr = tr * sp[0] + ti * sp[1], xi = tr * sp[1] - ti * sp[0];  // conj(T) S
-        const double yr = eb[0] * xr - eb[1] * xi, yi = eb[0] * xi + eb[1] * xr;  // e^{-i b} x
-        a.dbeta_out[(size_t)inst * a.grad_stride] = 2.0 * yi * a.inv_N;          // Re(-i y) = Im y
-    }
+    if (threadIdx.x == 0) finalize_apply(a, inst, r);
 }
 
 struct RevFinArgs {
@@ -428,8 +504,8 @@ struct RevFinArgs {
     int grad_stride;
 };
 
-__global__ void __launch_bounds__(kSvThreads) sv_rev_finalize_kernel(RevFinArgs a) {
-    __shared__ double lds[kRevR * kSvThreads / kWave];
+__global__ void __launch_bounds__(kFinThreads) sv_rev_finalize_kernel(RevFinArgs a) {
+    __shared__ double lds[kRevR * kFinThreads / kWave];
     const int inst = blockIdx.x;
     double r[kRevR];
     reduce_partials<kRevR>(a.partials + (size_t)inst * a.nblocks * kRevR, a.nblocks, r, lds);
@@ -451,40 +527,78 @@ __global__ void __launch_bounds__(kSvThreads) sv_rev_finalize_kernel(RevFinArgs 
 
 // ---- launch shapes ------------------------------------------------------------------
 struct PassShape {
-    int amp, unroll, blocks_x;
+    int amp, unroll, blocks_x, nt;
 };
 
 constexpr int kMaxPassBlocks = 4096;  // partial-sum rows per launch (all instances)
 
+// Launch shape of the streaming passes. A lane moves exactly one 16-byte
+// chunk of the state per group (2 complex64 or 1 complex128 amplitudes), so
+// each wave-wide load or store instruction covers 1 KiB of contiguous memory;
+// UNROLL groups per loop trip keep that many loads in flight per lane.
+// GQAOA_SV_SHAPE="amp,unroll,blocks_per_cu,nt" overrides the round pass (a
+// tuning hook; shapes outside the compiled set fall back to the default).
 static PassShape pass_shape(uint64_t N, int num_inst, int dtype, const DeviceInfo &dev) {
     PassShape s;
-    if (dtype == GQAOA_C64) {
-        s.amp = 4;
-        s.unroll = 4;
-        if (N < (uint64_t)kWave * 16) { s.amp = 2; s.unroll = 1; }
-    } else {
-        s.amp = 2;
-        s.unroll = 4;
-        if (N < (uint64_t)kWave * 8) { s.amp = 1; s.unroll = 1; }
+    int bpc = 16;
+    s.nt = 1;
+    s.amp = dtype == GQAOA_C64 ? 2 : 1;
+    s.unroll = 8;
+    if (const char *e = getenv("GQAOA_SV_SHAPE")) {
+        int a = 0, u = 0, b = 0, t = 1;
+        if (sscanf(e, "%d,%d,%d,%d", &a, &u, &b, &t) >= 3 && a > 0 && u > 0 && b > 0) {
+            s.amp = a;
+            s.unroll = u;
+            bpc = b;
+            s.nt = t ? 1 : 0;
+        }
+    }
+    if (N < (uint64_t)kWave * s.amp * s.unroll) {  // fewer amplitudes than one tile
+        s.amp = dtype == GQAOA_C64 ? 2 : 1;
+        s.unroll = 1;
+        s.nt = 1;
     }
     const uint64_t per_block = (uint64_t)kSvThreads * s.amp * s.unroll;
     const uint64_t want = (N + per_block - 1) / per_block;
-    const uint64_t cap = std::max<uint64_t>(1, (uint64_t)std::min(kMaxPassBlocks, dev.num_cus * 8) / num_inst);
+    const uint64_t cap = std::max<uint64_t>(1, (uint64_t)std::min(kMaxPassBlocks, dev.num_cus * bpc) / num_inst);
+    static_assert(kMaxPassBlocks <= kMaxPassRowsPerInst, "finalize covers every row of an instance");
     s.blocks_x = (int)std::max<uint64_t>(1, std::min(want, cap));
     return s;
 }
+
+#define GQ_FWD_SHAPE(TT, A, U, NTF)                                                                  \
+    if (s.amp == A && s.unroll == U && s.nt == NTF) {                                             \
+        hipLaunchKernelGGL((sv_forward_kernel<TT, PHASE, WRITE, A, U, NTF>), grid, block, 0, st, a); \
+        return;                                                                                    \
+    }
 
 template <typename T, bool PHASE, bool WRITE>
 static void launch_fwd_t(const PassShape &s, int num_inst, const FwdArgs &a, hipStream_t st) {
     const dim3 grid(s.blocks_x, num_inst), block(kSvThreads);
     if constexpr (sizeof(T) == 4) {
-        if (s.amp == 4) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 4, 4>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 1>), grid, block, 0, st, a);
+        if constexpr (PHASE && WRITE) {  // the round pass: every compiled tuning shape
+            if (a.counter && s.amp == 2 && s.unroll == 8 && s.nt == 1) {
+                hipLaunchKernelGGL((sv_forward_kernel<T, true, true, 2, 8, 1, true>), grid, block, 0, st, a);
+                return;
+            }
+            GQ_FWD_SHAPE(T, 2, 4, 1) GQ_FWD_SHAPE(T, 2, 16, 1) GQ_FWD_SHAPE(T, 2, 8, 0) GQ_FWD_SHAPE(T, 2, 16, 0)
+            GQ_FWD_SHAPE(T, 4, 4, 1) GQ_FWD_SHAPE(T, 4, 4, 0)
+        }
+        if (s.unroll == 1) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 8>), grid, block, 0, st, a);
     } else {
-        if (s.amp == 2) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 4>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 1>), grid, block, 0, st, a);
+        if constexpr (PHASE && WRITE) {
+            if (a.counter && s.amp == 1 && s.unroll == 8 && s.nt == 1) {
+                hipLaunchKernelGGL((sv_forward_kernel<T, true, true, 1, 8, 1, true>), grid, block, 0, st, a);
+                return;
+            }
+            GQ_FWD_SHAPE(T, 1, 4, 1) GQ_FWD_SHAPE(T, 1, 16, 1) GQ_FWD_SHAPE(T, 1, 8, 0) GQ_FWD_SHAPE(T, 2, 4, 1)
+        }
+        if (s.unroll == 1) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 8>), grid, block, 0, st, a);
     }
 }
+#undef GQ_FWD_SHAPE
 
 static void launch_fwd(int dtype, bool phase, bool write, const PassShape &s, int num_inst,
                        const FwdArgs &a, hipStream_t st) {
@@ -503,11 +617,11 @@ template <typename T, bool FIRST, bool WRITE>
 static void launch_rev_t(const PassShape &s, int num_inst, const RevArgs &a, hipStream_t st) {
     const dim3 grid(s.blocks_x, num_inst), block(kSvThreads);
     if constexpr (sizeof(T) == 4) {
-        if (s.amp == 4) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 4, 4>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 1>), grid, block, 0, st, a);
+        if (s.unroll == 1) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 8>), grid, block, 0, st, a);
     } else {
-        if (s.amp == 2) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 4>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 1>), grid, block, 0, st, a);
+        if (s.unroll == 1) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 1>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 8>), grid, block, 0, st, a);
     }
 }
 
@@ -535,7 +649,7 @@ static void launch_rev(int dtype, bool first, bool write, const PassShape &s, in
 // ---- workspace layout ---------------------------------------------------------------
 // Small tables first (per instance), then the state slots used by the adjoint.
 struct SvLayout {
-    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, target, partials;
+    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, target, counter, partials;
     size_t slots, slot_bytes, nslots, total;
 };
 
@@ -559,6 +673,7 @@ static SvLayout sv_layout(int num_inst, int n, int p, int dtype, int ckpt_every,
     L.dbeta = o;    o += al256(I * P * 8);
     L.dgamma = o;   o += al256(I * P * 8);
     L.target = o;   o += al256(I * 4);
+    L.counter = o;  o += al256(I * 4);
     L.partials = o; o += al256(std::max<size_t>(kMaxPassBlocks, I) * kFwdR * 8);
     L.slots = o;
     L.slot_bytes = al256(I * ((size_t)1 << n) * cs);
@@ -659,6 +774,18 @@ static FinArgs base_fin_args(const FwdPlan &P) {
     return f;
 }
 
+// GQAOA_SV_FUSE=1 folds the finalize into the last block of the round pass
+// (one launch per round). It is off by default: the release fence each block
+// needs before counting itself done writes back its XCD's L2, which costs more
+// bandwidth than the separate finalize launch saves (0.99 vs 0.75 ms per
+// round at n = 28, complex64).
+static bool fused_round(const FwdPlan &P) {
+    const char *e = getenv("GQAOA_SV_FUSE");
+    if (!e || e[0] != '1') return false;
+    const PassShape &s = P.shape;
+    return s.unroll == 8 && s.nt == 1 && s.amp == (P.dtype == GQAOA_C64 ? 2 : 1);
+}
+
 // One forward round j (1-based): psi_in holds phi_{j-1} (or |s> if j == 1 and
 // uniform), psi_out receives phi_j. With finalize, writes delta_j, S_j and the
 // readout of round j-1.
@@ -671,17 +798,22 @@ static int forward_round(const FwdPlan &P, int j, const void *psi_in, void *psi_
     a.lut = P.ws + P.L.lut + (size_t)(j - 1) * 256 * cs;
     a.delta = j > 1 ? reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * (j - 1) : nullptr;
     a.init_uniform = uniform ? 1 : 0;
+    FinArgs f = base_fin_args(P);
+    f.mixf = reinterpret_cast<double *>(P.ws + P.L.mixf) + 2 * (j - 1);
+    f.delta_out = reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * j;
+    f.S_out = reinterpret_cast<double *>(P.ws + P.L.S) + 2 * j;
+    f.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * (j - 1);
+    const bool fused = finalize && fused_round(P);
+    if (fused) {
+        a.counter = reinterpret_cast<unsigned int *>(P.ws + P.L.counter);
+        a.fin = f;
+    }
     ProfScope ps(P.dtype == GQAOA_C64 ? "sv_round_c64" : "sv_round_c128", st);
     launch_fwd(P.dtype, true, true, P.shape, P.num_inst, a, st);
     ps.end();
     GQ_LAUNCH_CHECK();
-    if (finalize) {
-        FinArgs f = base_fin_args(P);
-        f.mixf = reinterpret_cast<double *>(P.ws + P.L.mixf) + 2 * (j - 1);
-        f.delta_out = reinterpret_cast<double *>(P.ws + P.L.delta) + 2 * j;
-        f.S_out = reinterpret_cast<double *>(P.ws + P.L.S) + 2 * j;
-        f.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * (j - 1);
-        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, f);
+    if (finalize && !fused) {
+        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
         GQ_LAUNCH_CHECK();
     }
     return GQAOA_OK;
@@ -700,7 +832,7 @@ static int final_pass(const FwdPlan &P, const void *psi_in, void *psi_out, bool 
     GQ_LAUNCH_CHECK();
     FinArgs f = base_fin_args(P);
     f.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * P.p;
-    hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, f);
+    hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
 }
@@ -734,6 +866,7 @@ static int prepare_plan(FwdPlan &P, int num_inst, int n, const int32_t *m_of, co
     keep_t.assign(targets, targets + num_inst);
     if ((s = upload(P.ws + P.L.target, keep_t.data(), keep_t.size() * 4, st))) return s;
     GQ_HIP(hipMemsetAsync(P.ws + P.L.delta, 0, (size_t)num_inst * (p + 1) * 16, st));
+    GQ_HIP(hipMemsetAsync(P.ws + P.L.counter, 0, (size_t)num_inst * 4, st));
     return GQAOA_OK;
 }
 
@@ -832,7 +965,7 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
         fa.stride = 2 * (p + 1);
         fa.eps_out = reinterpret_cast<double *>(P.ws + P.L.eps);
         fa.dbeta_out = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (p - 1);
-        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, fa);
+        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, fa);
         GQ_LAUNCH_CHECK();
     }
     // reverse sweep, segment by segment
@@ -880,7 +1013,7 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
                 rf.eps_out = reinterpret_cast<double *>(P.ws + P.L.eps);
                 rf.dbeta_km1 = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (k - 2);
             }
-            hipLaunchKernelGGL(sv_rev_finalize_kernel, dim3(P.num_inst), dim3(kSvThreads), 0, st, rf);
+            hipLaunchKernelGGL(sv_rev_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, rf);
             GQ_LAUNCH_CHECK();
         }
     }

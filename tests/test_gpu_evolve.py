@@ -131,3 +131,23 @@ def test_full_size_n28_p64_complex64():
     assert np.abs(psol64 - psol128).max() < 1e-5
     assert np.abs(psol128 - rp).max() < 1e-10
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt", [g.C64, g.C128])
+def test_fused_and_separate_finalize_agree(dt, monkeypatch):
+    """The round pass either launches its finalize separately (default) or
+    folds it into its last block (GQAOA_SV_FUSE=1); both sum the same partial
+    rows, in different fixed orders, so results agree to rounding."""
+    need_gpu()
+    n, m = 18, 76
+    lits = rand_lits(n, m, 44)
+    beta, gamma = inst.uniform_angles(44, 12)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    sep = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=dt)
+    monkeypatch.setenv("GQAOA_SV_FUSE", "1")
+    fused = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=dt)
+    monkeypatch.delenv("GQAOA_SV_FUSE")
+    for a, b in zip(fused[1:], sep[1:]):
+        assert np.abs(a - b).max() < (1e-14 if dt == g.C128 else 1e-6)
+    ref = evolve_sv(n, cost_table(n, lits), beta, gamma)
+    _check(fused, ref, dt, m)
