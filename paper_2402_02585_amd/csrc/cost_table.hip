@@ -39,9 +39,20 @@ struct EffEntry {
 };
 
 struct CostLds {
+    ClauseRec rec[kMaxVec];          // the instance's clause records, staged once per block
+    UniformRec urec[kMaxVec];
     EffEntry eff[kCostWaves][kMaxVec][2];
     uint32_t hist[kHistCopies][256];
 };
+
+// Zero the histogram copies and stage the clause records in LDS.
+__device__ __forceinline__ void stage(CostLds &s, const ClauseRec *__restrict__ vec, int nvec,
+                                      const UniformRec *__restrict__ uni, int nuni) {
+    for (int i = threadIdx.x; i < kHistCopies * 256; i += kCostThreads) (&s.hist[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < nvec; i += kCostThreads) s.rec[i] = vec[i];
+    for (int i = threadIdx.x; i < nuni; i += kCostThreads) s.urec[i] = uni[i];
+    __syncthreads();
+}
 
 __device__ __forceinline__ uint32_t *hist_copy(CostLds &s) {
     return s.hist[(threadIdx.x / kWave) * 2 + (threadIdx.x & 1)];
@@ -49,9 +60,8 @@ __device__ __forceinline__ uint32_t *hist_copy(CostLds &s) {
 
 // Costs of the 32 assignments of word tile*64 + lane (bytes: out[r] byte q is
 // C(32 w + 4 r + q)). Every lane of the wave must call this with the same tile.
-__device__ __forceinline__ void eval_tile(const ClauseRec *__restrict__ vec, int nvec,
-                                          const UniformRec *__restrict__ uni, int nuni, uint64_t tile,
-                                          EffEntry (*eff)[2], uint32_t (&out)[8]) {
+__device__ __forceinline__ void eval_tile(const ClauseRec *vec, int nvec, const UniformRec *uni, int nuni,
+                                          uint64_t tile, EffEntry (*eff)[2], uint32_t (&out)[8]) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t zwave = (tile * kWave) << kLowBits;   // z of lane 0, bit 0
     // 1) high-literal test of 64 clauses at a time, one per lane
@@ -112,8 +122,7 @@ cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec 
                   int nuni, int n, uint8_t *__restrict__ cost, uint32_t *__restrict__ block_hist,
                   int hist_len) {
     __shared__ CostLds lds;
-    for (int i = threadIdx.x; i < kHistCopies * 256; i += kCostThreads) (&lds.hist[0][0])[i] = 0;
-    __syncthreads();
+    stage(lds, vec, nvec, uni, nuni);
     uint32_t *h = hist_copy(lds);
     EffEntry(*eff)[2] = lds.eff[threadIdx.x / kWave];
     const uint64_t N = 1ull << n;
@@ -123,7 +132,7 @@ cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec 
     const int lane = threadIdx.x & (kWave - 1);
     for (uint64_t tile = (uint64_t)blockIdx.x * kCostWaves + threadIdx.x / kWave; tile < ntiles; tile += nwaves) {
         uint32_t t[8];
-        eval_tile(vec, nvec, uni, nuni, tile, eff, t);
+        eval_tile(lds.rec, nvec, lds.urec, nuni, tile, eff, t);
         const uint64_t w = tile * kWave + lane;
         if (w >= nwords) continue;
         if (n >= kLowBits) {
@@ -178,10 +187,9 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
                     const ClauseRec *__restrict__ vec, const UniformRec *__restrict__ uni,
                     unsigned long long *__restrict__ hists, int hist_stride) {
     __shared__ CostLds lds;
-    for (int i = threadIdx.x; i < kHistCopies * 256; i += kCostThreads) (&lds.hist[0][0])[i] = 0;
-    __syncthreads();
     const HistUnit unit = units[blockIdx.x];
     const HistInst in = insts[unit.inst];
+    stage(lds, vec + in.vec_off, in.nvec, uni + in.uni_off, in.nuni);
     uint32_t *h = hist_copy(lds);
     EffEntry(*eff)[2] = lds.eff[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -191,7 +199,7 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
         // word0 is a multiple of 64, so tile (word0 / 64 + t0) starts at word0 + 64 t0
         const uint64_t tile = (uint64_t)unit.word0 / kWave + t0;
         uint32_t t[8];
-        eval_tile(vec + in.vec_off, in.nvec, uni + in.uni_off, in.nuni, tile, eff, t);
+        eval_tile(lds.rec, in.nvec, lds.urec, in.nuni, tile, eff, t);
         if (t0 * kWave + lane < unit.nwords) tally_word(h, t, nbits);
     }
     __syncthreads();

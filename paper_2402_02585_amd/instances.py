@@ -191,29 +191,52 @@ def uniform_angles(seed: int, p: int, lo: float = 0.0, hi: float = np.pi):
     return beta, gamma
 
 
+def _child_instance(args):
+    seed, count, k, n_lo, n_hi, densities, sat_only = args
+    # child k of SeedSequence(seed).spawn(count), built directly
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(k,))))
+    n = int(rng.integers(n_lo, n_hi + 1))
+    d = float(densities[int(rng.integers(0, len(densities)))])
+    m = m_from_density(n, d)
+    draw = 0
+    while True:
+        lits = random_3sat(rng, n, m)
+        if not sat_only or dpll_satisfiable(n, lits):
+            break
+        draw += 1
+    return Instance(n=n, lits=lits, seed=k, draw=draw, d=d)
+
+
 def batched_scan_instances(seed: int, count: int, n_lo: int, n_hi: int,
                            densities=(3.0, 4.2, 5.0), sat_only: bool = True,
-                           accept=None) -> list:
-    """``count`` instances, child k from SeedSequence(seed).spawn(count).
+                           accept=None, workers: int = 1) -> list:
+    """``count`` instances; child k draws from SeedSequence(seed) child k.
 
     Each child draws n ~ U{n_lo..n_hi}, d ~ U(densities), m = round(n d), then
-    clause sets until one is accepted (satisfiable when ``sat_only``).
+    clause sets until one is satisfiable (when ``sat_only``). ``workers`` > 1
+    splits the children over processes (same instances for any value).
     """
-    accept = accept or dpll_satisfiable
-    out = []
-    for k, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
-        rng = np.random.Generator(np.random.PCG64(child))
-        n = int(rng.integers(n_lo, n_hi + 1))
-        d = float(densities[int(rng.integers(0, len(densities)))])
-        m = m_from_density(n, d)
-        draw = 0
-        while True:
-            lits = random_3sat(rng, n, m)
-            if not sat_only or accept(n, lits):
-                break
-            draw += 1
-        out.append(Instance(n=n, lits=lits, seed=k, draw=draw, d=d))
-    return out
+    if accept is not None:
+        out = []
+        for k, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
+            rng = np.random.Generator(np.random.PCG64(child))
+            n = int(rng.integers(n_lo, n_hi + 1))
+            d = float(densities[int(rng.integers(0, len(densities)))])
+            m = m_from_density(n, d)
+            draw = 0
+            while True:
+                lits = random_3sat(rng, n, m)
+                if not sat_only or accept(n, lits):
+                    break
+                draw += 1
+            out.append(Instance(n=n, lits=lits, seed=k, draw=draw, d=d))
+        return out
+    args = [(seed, count, k, n_lo, n_hi, tuple(densities), sat_only) for k in range(count)]
+    if workers <= 1:
+        return [_child_instance(a) for a in args]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_child_instance, args, chunksize=max(1, count // (8 * workers)))
 
 
 # --- the paper's two worked instances (footnote of Sec. IV) -----------------
