@@ -54,6 +54,39 @@ GQ_HD uint32_t low_var_pattern(int v) {
     return p;
 }
 
+// low_var_pattern(v) in closed form: z bit 0 <-> word bit 3, bit 1 <-> 4, bit 2 <-> 0,
+// bit 3 <-> 1, bit 4 <-> 2.
+constexpr uint32_t kLowVarPattern[kLowBits] = {0xFF00FF00u, 0xFFFF0000u, 0xAAAAAAAAu, 0xCCCCCCCCu, 0xF0F0F0F0u};
+// Lanes whose lane-index bit b is 1 (b = v - 5 for a variable on z bits 5..10).
+constexpr uint64_t kLaneBitPattern[kLaneBits] = {
+    0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
+    0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
+
+// Record of one clause (validated literals: lit = 2*var + neg, distinct vars).
+// Sets *uniform when every variable sits at z bits >= 11.
+GQ_HD ClauseRec make_record(int32_t l0, int32_t l1, int32_t l2, bool *uniform) {
+    ClauseRec r{0xFFFFFFFFu, 0u, ~0ull, 0ull, 0ull};
+    bool uni = true;
+    const int32_t lits[3] = {l0, l1, l2};
+    for (int j = 0; j < 3; ++j) {
+        const int v = lits[j] >> 1, neg = lits[j] & 1;
+        if (v < kLowBits) {
+            const uint32_t pat = kLowVarPattern[v];
+            r.P &= neg ? pat : ~pat;     // false iff bit v == neg
+            uni = false;
+        } else if (v < kHighBit0) {
+            const uint64_t ones = kLaneBitPattern[v - kLowBits];
+            r.L &= neg ? ones : ~ones;   // false iff the lane's bit equals neg
+            uni = false;
+        } else {
+            r.hivar |= 1ull << v;
+            r.hineg |= (uint64_t)neg << v;
+        }
+    }
+    if (uniform) *uniform = uni;
+    return r;
+}
+
 // A clause is active for a wave when its high literals are all false there.
 GQ_HD bool high_literals_false(uint64_t zwave, uint64_t hivar, uint64_t hineg) {
     return ((zwave ^ hineg) & hivar) == 0;
@@ -139,31 +172,8 @@ inline void pack_clauses(int m, const int32_t *lits, std::vector<ClauseRec> &vec
     vec.clear();
     uni.clear();
     for (int i = 0; i < m; ++i) {
-        ClauseRec r{0xFFFFFFFFu, 0u, ~0ull, 0ull, 0ull};
-        bool uniform = true;
-        for (int j = 0; j < 3; ++j) {
-            const int lit = lits[3 * i + j];
-            const int v = lit >> 1, neg = lit & 1;
-            if (v < kLowBits) {
-                static const uint32_t kLowPat[kLowBits] = {low_var_pattern(0), low_var_pattern(1),
-                                                          low_var_pattern(2), low_var_pattern(3),
-                                                          low_var_pattern(4)};
-                const uint32_t pat = kLowPat[v];
-                r.P &= neg ? pat : ~pat;     // false iff bit v == neg
-                uniform = false;
-            } else if (v < kHighBit0) {
-                // lanes whose bit (v - 5) is 1
-                static const uint64_t kLaneBit[kLaneBits] = {
-                    0xAAAAAAAAAAAAAAAAull, 0xCCCCCCCCCCCCCCCCull, 0xF0F0F0F0F0F0F0F0ull,
-                    0xFF00FF00FF00FF00ull, 0xFFFF0000FFFF0000ull, 0xFFFFFFFF00000000ull};
-                const uint64_t ones = kLaneBit[v - kLowBits];
-                r.L &= neg ? ones : ~ones;   // false iff the lane's bit equals neg
-                uniform = false;
-            } else {
-                r.hivar |= 1ull << v;
-                r.hineg |= (uint64_t)neg << v;
-            }
-        }
+        bool uniform = false;
+        const ClauseRec r = make_record(lits[3 * i], lits[3 * i + 1], lits[3 * i + 2], &uniform);
         if (uniform)
             uni.push_back(UniformRec{r.hivar, r.hineg});
         else

@@ -27,9 +27,12 @@ namespace gqaoa {
 constexpr int kCostThreads = 256;
 constexpr int kCostWaves = kCostThreads / kWave;
 constexpr int kMaxVec = 256;  // padded clause records per instance (m <= 255)
-// LDS histogram copies per block: two per wave (by lane parity), so lanes that
-// tally the same level are spread over more addresses.
-constexpr int kHistCopies = kCostWaves * 2;
+// LDS histogram copies per block: four per wave (by lane & 3). Copies are
+// kHistStride = 257 words apart, so one level in different copies falls in
+// different LDS banks: lanes of different copies tallying the same level
+// neither share an address nor a bank.
+constexpr int kHistCopies = kCostWaves * 4;
+constexpr int kHistStride = 257;
 
 // A clause's effective masks for one wave-tile, as each half-wave reads them:
 // entry [c][h] = {P, bits 32h..32h+31 of L_eff} with L_eff = L if the clause's
@@ -38,24 +41,37 @@ struct EffEntry {
     uint32_t P, Lhalf;
 };
 
+// Dynamic LDS of a cost block, sized by the padded clause count nvec:
+// clause records [nvec], per-wave effective masks [waves][nvec][2], and the
+// histogram copies [copies][kHistStride].
 struct CostLds {
-    ClauseRec rec[kMaxVec];          // the instance's clause records, staged once per block
-    UniformRec urec[kMaxVec];
-    EffEntry eff[kCostWaves][kMaxVec][2];
-    uint32_t hist[kHistCopies][256];
+    ClauseRec *rec;
+    EffEntry *eff;
+    uint32_t *hist;
+    __device__ CostLds(unsigned char *smem, int nvec)
+        : rec(reinterpret_cast<ClauseRec *>(smem)),
+          eff(reinterpret_cast<EffEntry *>(smem + sizeof(ClauseRec) * nvec)),
+          hist(reinterpret_cast<uint32_t *>(smem + sizeof(ClauseRec) * nvec +
+                                            sizeof(EffEntry) * 2 * kCostWaves * nvec)) {}
+    __device__ EffEntry (*wave_eff(int nvec))[2] {
+        return reinterpret_cast<EffEntry(*)[2]>(eff + (size_t)2 * nvec * (threadIdx.x / kWave));
+    }
 };
 
+size_t cost_lds_bytes(int nvec) {
+    return sizeof(ClauseRec) * nvec + sizeof(EffEntry) * 2 * kCostWaves * nvec +
+           sizeof(uint32_t) * kHistCopies * kHistStride;
+}
+
 // Zero the histogram copies and stage the clause records in LDS.
-__device__ __forceinline__ void stage(CostLds &s, const ClauseRec *__restrict__ vec, int nvec,
-                                      const UniformRec *__restrict__ uni, int nuni) {
-    for (int i = threadIdx.x; i < kHistCopies * 256; i += kCostThreads) (&s.hist[0][0])[i] = 0;
+__device__ __forceinline__ void stage(CostLds &s, const ClauseRec *__restrict__ vec, int nvec) {
+    for (int i = threadIdx.x; i < kHistCopies * kHistStride; i += kCostThreads) s.hist[i] = 0;
     for (int i = threadIdx.x; i < nvec; i += kCostThreads) s.rec[i] = vec[i];
-    for (int i = threadIdx.x; i < nuni; i += kCostThreads) s.urec[i] = uni[i];
     __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t *hist_copy(CostLds &s) {
-    return s.hist[(threadIdx.x / kWave) * 2 + (threadIdx.x & 1)];
+    return s.hist + ((threadIdx.x / kWave) * 4 + (threadIdx.x & 3)) * kHistStride;
 }
 
 // Costs of the 32 assignments of word tile*64 + lane (bytes: out[r] byte q is
@@ -121,10 +137,11 @@ __global__ void __launch_bounds__(kCostThreads)
 cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec *__restrict__ uni,
                   int nuni, int n, uint8_t *__restrict__ cost, uint32_t *__restrict__ block_hist,
                   int hist_len) {
-    __shared__ CostLds lds;
-    stage(lds, vec, nvec, uni, nuni);
+    extern __shared__ unsigned char smem[];
+    CostLds lds(smem, nvec);
+    stage(lds, vec, nvec);
     uint32_t *h = hist_copy(lds);
-    EffEntry(*eff)[2] = lds.eff[threadIdx.x / kWave];
+    EffEntry(*eff)[2] = lds.wave_eff(nvec);
     const uint64_t N = 1ull << n;
     const uint64_t nwords = n >= kLowBits ? (N >> kLowBits) : 1;
     const uint64_t ntiles = (nwords + kWave - 1) / kWave;
@@ -132,7 +149,7 @@ cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec 
     const int lane = threadIdx.x & (kWave - 1);
     for (uint64_t tile = (uint64_t)blockIdx.x * kCostWaves + threadIdx.x / kWave; tile < ntiles; tile += nwaves) {
         uint32_t t[8];
-        eval_tile(lds.rec, nvec, lds.urec, nuni, tile, eff, t);
+        eval_tile(lds.rec, nvec, uni, nuni, tile, eff, t);
         const uint64_t w = tile * kWave + lane;
         if (w >= nwords) continue;
         if (n >= kLowBits) {
@@ -149,7 +166,7 @@ cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec 
     __syncthreads();
     for (int k = threadIdx.x; k < hist_len; k += kCostThreads) {
         uint32_t s = 0;
-        for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c][k];
+        for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c * kHistStride + k];
         block_hist[(size_t)blockIdx.x * hist_len + k] = s;
     }
 }
@@ -173,10 +190,14 @@ __global__ void __launch_bounds__(256) hist_reduce_kernel(const uint32_t *__rest
 }
 
 // ---- many instances, histograms only ---------------------------------------
+// Clause ingest runs on the device here: each block builds its instance's
+// records from the raw literals straight into LDS (every clause as a vector
+// record, padded to the adder-tree group), so the host uploads 12 bytes per
+// clause and packs nothing.
 struct HistInst {
-    uint32_t vec_off, nvec, uni_off, nuni;
+    uint32_t lit_off;   // first clause of the instance in the literal array
     int32_t n, m;
-    uint32_t pad0, pad1;
+    uint32_t pad;
 };
 struct HistUnit {
     uint32_t inst, word0, nwords, pad;
@@ -184,14 +205,20 @@ struct HistUnit {
 
 __global__ void __launch_bounds__(kCostThreads)
 hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restrict__ units,
-                    const ClauseRec *__restrict__ vec, const UniformRec *__restrict__ uni,
-                    unsigned long long *__restrict__ hists, int hist_stride) {
-    __shared__ CostLds lds;
+                    const int32_t *__restrict__ lits, unsigned long long *__restrict__ hists, int hist_stride) {
+    extern __shared__ unsigned char smem[];
     const HistUnit unit = units[blockIdx.x];
     const HistInst in = insts[unit.inst];
-    stage(lds, vec + in.vec_off, in.nvec, uni + in.uni_off, in.nuni);
+    const int nvec = (in.m + kGroup - 1) / kGroup * kGroup;
+    CostLds lds(smem, nvec);
+    const int32_t *L = lits + 3 * (size_t)in.lit_off;
+    for (int i = threadIdx.x; i < kHistCopies * kHistStride; i += kCostThreads) lds.hist[i] = 0;
+    for (int c = threadIdx.x; c < nvec; c += kCostThreads)
+        lds.rec[c] = c < in.m ? make_record(L[3 * c], L[3 * c + 1], L[3 * c + 2], nullptr)
+                              : ClauseRec{0u, 0u, 0ull, 0ull, 0ull};
+    __syncthreads();
     uint32_t *h = hist_copy(lds);
-    EffEntry(*eff)[2] = lds.eff[threadIdx.x / kWave];
+    EffEntry(*eff)[2] = lds.wave_eff(nvec);
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t nbits = in.n >= kLowBits ? 32u : (1u << in.n);
     const uint32_t ntiles = (unit.nwords + kWave - 1) / kWave;
@@ -199,13 +226,13 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
         // word0 is a multiple of 64, so tile (word0 / 64 + t0) starts at word0 + 64 t0
         const uint64_t tile = (uint64_t)unit.word0 / kWave + t0;
         uint32_t t[8];
-        eval_tile(lds.rec, in.nvec, lds.urec, in.nuni, tile, eff, t);
+        eval_tile(lds.rec, nvec, nullptr, 0, tile, eff, t);
         if (t0 * kWave + lane < unit.nwords) tally_word(h, t, nbits);
     }
     __syncthreads();
     for (int k = threadIdx.x; k <= in.m; k += kCostThreads) {
         uint32_t s = 0;
-        for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c][k];
+        for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c * kHistStride + k];
         if (s) atomicAdd(hists + (size_t)unit.inst * hist_stride + k, (unsigned long long)s);
     }
 }
@@ -237,8 +264,8 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     GQ_HIP(hipMemcpyAsync(scratch, staging.data(), rec_bytes, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipStreamSynchronize(stream));  // staging is host pageable memory owned here
     ProfScope ps("cost_table", stream);
-    hipLaunchKernelGGL(cost_table_kernel, dim3(nblocks), dim3(kCostThreads), 0, stream, d_vec,
-                       (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len);
+    hipLaunchKernelGGL(cost_table_kernel, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes((int)vec.size()), stream,
+                       d_vec, (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len);
     ps.end();
     GQ_LAUNCH_CHECK();
     if (hist) {
@@ -252,52 +279,40 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
 
 int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
                         const int32_t *lits, uint64_t *hists, int hist_stride, hipStream_t stream) {
-    std::vector<ClauseRec> vec_all, vec;
-    std::vector<UniformRec> uni_all, uni;
     std::vector<HistInst> insts(num_inst);
     std::vector<HistUnit> units;
     constexpr uint32_t kUnitWords = kCostThreads * 4;
     size_t off = 0;
+    int max_m = 1;
+    for (int i = 0; i < num_inst; ++i) max_m = std::max(max_m, m_host[i]);
+    const size_t smem_bytes = cost_lds_bytes((max_m + kGroup - 1) / kGroup * kGroup);
     for (int i = 0; i < num_inst; ++i) {
-        pack_clauses(m_host[i], lits + 3 * off, vec, uni);
+        insts[i] = HistInst{(uint32_t)off, n_host[i], m_host[i], 0u};
         off += (size_t)m_host[i];
-        insts[i] = HistInst{(uint32_t)vec_all.size(), (uint32_t)vec.size(), (uint32_t)uni_all.size(),
-                            (uint32_t)uni.size(), n_host[i], m_host[i], 0u, 0u};
-        vec_all.insert(vec_all.end(), vec.begin(), vec.end());
-        uni_all.insert(uni_all.end(), uni.begin(), uni.end());
         const uint64_t nwords = n_host[i] >= kLowBits ? (1ull << (n_host[i] - kLowBits)) : 1;
         for (uint64_t w0 = 0; w0 < nwords; w0 += kUnitWords)
             units.push_back(HistUnit{(uint32_t)i, (uint32_t)w0,
                                      (uint32_t)std::min<uint64_t>(kUnitWords, nwords - w0), 0u});
     }
-    if (vec_all.empty()) vec_all.push_back(ClauseRec{0u, 0u, 0ull, 0ull, 0ull});
-    if (uni_all.empty()) uni_all.push_back(UniformRec{0ull, 0ull});
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t b_inst = sizeof(HistInst) * insts.size();
     const size_t b_unit = sizeof(HistUnit) * units.size();
-    const size_t b_vec = sizeof(ClauseRec) * vec_all.size();
-    const size_t b_uni = sizeof(UniformRec) * uni_all.size();
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t total = al(b_inst) + al(b_unit) + al(b_vec) + al(b_uni);
-    std::vector<char> staging(total, 0);
-    size_t o_inst = 0, o_unit = al(b_inst), o_vec = o_unit + al(b_unit), o_uni = o_vec + al(b_vec);
-    memcpy(staging.data() + o_inst, insts.data(), b_inst);
-    memcpy(staging.data() + o_unit, units.data(), b_unit);
-    memcpy(staging.data() + o_vec, vec_all.data(), b_vec);
-    memcpy(staging.data() + o_uni, uni_all.data(), b_uni);
+    const size_t b_lits = sizeof(int32_t) * 3 * off;
+    const size_t o_unit = al(b_inst), o_lits = o_unit + al(b_unit);
     void *scratch = nullptr;
-    GQ_HIP(hipMallocAsync(&scratch, total, stream));
+    GQ_HIP(hipMallocAsync(&scratch, o_lits + al(b_lits), stream));
     char *base = reinterpret_cast<char *>(scratch);
-    GQ_HIP(hipMemcpyAsync(scratch, staging.data(), total, hipMemcpyHostToDevice, stream));
-    GQ_HIP(hipStreamSynchronize(stream));
+    GQ_HIP(hipMemcpyAsync(base, insts.data(), b_inst, hipMemcpyHostToDevice, stream));
+    GQ_HIP(hipMemcpyAsync(base + o_unit, units.data(), b_unit, hipMemcpyHostToDevice, stream));
+    GQ_HIP(hipMemcpyAsync(base + o_lits, lits, b_lits, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipMemsetAsync(hists, 0, sizeof(uint64_t) * (size_t)num_inst * hist_stride, stream));
-    hipLaunchKernelGGL(hist_batched_kernel, dim3((unsigned)units.size()), dim3(kCostThreads), 0,
-                       stream, reinterpret_cast<const HistInst *>(base + o_inst),
-                       reinterpret_cast<const HistUnit *>(base + o_unit),
-                       reinterpret_cast<const ClauseRec *>(base + o_vec),
-                       reinterpret_cast<const UniformRec *>(base + o_uni),
+    hipLaunchKernelGGL(hist_batched_kernel, dim3((unsigned)units.size()), dim3(kCostThreads), smem_bytes, stream,
+                       reinterpret_cast<const HistInst *>(base), reinterpret_cast<const HistUnit *>(base + o_unit),
+                       reinterpret_cast<const int32_t *>(base + o_lits),
                        reinterpret_cast<unsigned long long *>(hists), hist_stride);
     GQ_LAUNCH_CHECK();
     GQ_HIP(hipFreeAsync(scratch, stream));
+    GQ_HIP(hipStreamSynchronize(stream));  // the host tables above end with this call
     return GQAOA_OK;
 }
 

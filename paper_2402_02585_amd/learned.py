@@ -84,7 +84,7 @@ def features_for(hists_dev, ns, ms, p: int):
     return g.gqaoa_mlp_features(hists_dev.contiguous(), nd, md, pd)
 
 
-def training_set(insts, p_list, grid=(128, 64)):
+def training_set(insts, p_list, grid=None):
     """(X [I*P, 131], Y [I*P, 2], labels dict) from batched-optimizer labels."""
     torch = _torch()
     ns = [it.n for it in insts]
@@ -115,14 +115,23 @@ def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
     return ps.reshape(I).cpu().numpy().astype(np.float64)
 
 
-def refine_local(ns, ms, hists, betas, gammas, p: int, width: float = 0.08, zoom: int = 16):
-    """Best pair on a zoom x zoom window around each instance's pair (one launch)."""
+def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.2, 0.03), zoom: int = 16):
+    """Best pair after one zoom x zoom window scan per width, each centred on the
+    previous best (one launch per width, all instances)."""
     I = len(ns)
-    offs = np.linspace(-width, width, zoom)
-    bgrid = np.asarray(betas)[:, None] + offs[None, :]
-    ggrid = np.clip(np.asarray(gammas)[:, None] + offs[None, :] / 2, 0.0, math.pi)
-    ps, _ = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], with_energy=False)
-    v = ps[:, 0].reshape(I, -1)
-    j = v.argmax(dim=1).cpu().numpy()
-    best = v.cpu().numpy()[np.arange(I), j].astype(np.float64)
-    return bgrid[np.arange(I), j % zoom], ggrid[np.arange(I), j // zoom], best
+    b = np.asarray(betas, dtype=np.float64).copy()
+    gm = np.asarray(gammas, dtype=np.float64).copy()
+    best = evaluate_pairs(ns, ms, hists, b, gm, p)
+    for w in widths:
+        offs = np.linspace(-w, w, zoom)
+        bgrid = b[:, None] + offs[None, :]
+        ggrid = np.clip(gm[:, None] + offs[None, :] / 2, 0.0, math.pi)
+        ps, _ = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], with_energy=False)
+        v = ps[:, 0].reshape(I, -1)
+        j = v.argmax(dim=1).cpu().numpy()
+        vj = v.cpu().numpy()[np.arange(I), j].astype(np.float64)
+        better = vj > best
+        b[better] = bgrid[better, j[better] % zoom]
+        gm[better] = ggrid[better, j[better] // zoom]
+        best[better] = vj[better]
+    return b, gm, best

@@ -3,12 +3,12 @@ instances, and compare with the optimizers and the clustering-only baseline.
 
 Workload (defaults): training instances from SeedSequence(5), n ~ U{12..20},
 d ~ U{3.0, 4.2, 5.0}, satisfiable; labels are the batched optimizer's
-P_sol-maximizing pairs over the fundamental domain (128 x 64 grid, two zoom
-levels) at p in {1, 4, 16, 64}. Inference instances from SeedSequence(6),
+P_sol-maximizing pairs over the fundamental domain (the paper's pi/180 grid,
+then two zoom levels) at p in {1, 4, 16, 64}. Inference instances from SeedSequence(6),
 n ~ U{12..24}. Reported, per p and overall:
 
-* mean P_sol of the learned pair, of the learned pair plus one 16 x 16 local
-  window scan, of the fixed cluster-median pair (clustering alone), of the
+* mean P_sol of the learned pair, of the learned pair plus two 16 x 16 local
+  window scans, of the fixed cluster-median pair (clustering alone), of the
   batched optimizer (all inference instances) and of the plain per-instance
   optimizer (a seeded subsample);
 * instances per second of each form on the GPU, the fallback count (learned
@@ -42,6 +42,8 @@ def main(argv=None):
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--test", type=int, default=65536)
     ap.add_argument("--plain", type=int, default=16, help="instances for the plain optimizer")
+    ap.add_argument("--plain-grid", type=int, nargs=2, default=[360, 181],
+                    help="beta x gamma grid of the plain optimizer (default: the paper's pi/180 spacing)")
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--workers", type=int, default=16)
@@ -114,7 +116,7 @@ def main(argv=None):
         p_final = np.where(fb, op[:, q], p_win)
         # plain optimizer on the subsample (one device call per evaluation)
         plain_p, plain_t = [], 0.0
-        gb, gg = optim.fundamental_grid(64, 32)
+        gb, gg = optim.fundamental_grid(*a.plain_grid)
         for i in sub:
             hdev = hd[i, :ms[i] + 1].contiguous()
             t0 = time.perf_counter()
@@ -130,6 +132,7 @@ def main(argv=None):
             "ratio_learned_to_median": float(p_learn.mean() / p_med.mean()),
             "plain_subsample": {"instances": int(len(sub)), "mean_psol_plain": float(plain_p.mean()),
                                 "mean_psol_learned_window_same": float(p_win[sub].mean()),
+                                "mean_psol_batched_optimizer_same": float(op[sub, q].mean()),
                                 "ratio_learned_window_to_plain": float(p_win[sub].mean() / plain_p.mean()),
                                 "seconds_per_instance": plain_t / len(sub)},
             "cluster_median_pair": list(med[p]),
@@ -139,7 +142,8 @@ def main(argv=None):
         total["median"] += p_med.mean()
         total["optimizer"] += op[:, q].mean()
         log(f"p={p}: learned {p_learn.mean():.4f} window {p_win.mean():.4f} median {p_med.mean():.4f} "
-            f"optimizer {op[:, q].mean():.4f} plain(sub) {plain_p.mean():.4f}")
+            f"optimizer {op[:, q].mean():.4f} | subsample: plain {plain_p.mean():.4f} "
+            f"learned+window {p_win[sub].mean():.4f} optimizer {op[sub, q].mean():.4f}")
     plain_sec = np.mean([res["per_p"][str(p)]["plain_subsample"]["seconds_per_instance"] for p in P_LIST])
     res["throughput_instances_per_s"] = {
         "learned": I * len(P_LIST) / t_learn, "learned_window": I * len(P_LIST) / t_win,
@@ -149,7 +153,7 @@ def main(argv=None):
     res["fallbacks"] = fallbacks
     res["mean_over_p"] = {k: v / len(P_LIST) for k, v in total.items()}
     res["ratio_window_to_optimizer_mean_over_p"] = total["window"] / total["optimizer"]
-    out = json.dumps(res)
+    out = json.dumps(res, default=float)
     print(out, flush=True)
     if a.out:
         with open(a.out, "w") as f:

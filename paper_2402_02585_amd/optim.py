@@ -68,30 +68,53 @@ def plain_single_pair(n: int, m: int, hist_dev, p: int, betas_grid, gammas_grid,
             "evals": evals}
 
 
-def batched_single_pair(ns, ms, hists, p_list, grid=(128, 64), zoom_levels: int = 2, zoom: int = 16,
-                        objective: str = "psol", targets=None, tile=None):
+def paper_grid():
+    """The paper's pi/180 spacing over the fundamental domain: 360 x 181 pairs."""
+    return 360, 181
+
+
+def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, zoom: int = 16,
+                        objective: str = "psol", targets=None, tile=None, max_out_bytes: float = 2e9):
     """Single-pair optimum of every instance and p in ``p_list``.
 
+    Grid stage over the fundamental domain (default: the paper's pi/180
+    spacing), instances taken in chunks so the [chunk, P, ng, nb] output stays
+    under ``max_out_bytes``; then ``zoom_levels`` rounds of a zoom x zoom
+    window around each best pair (one launch per p and round, all instances).
     Returns arrays beta[I, P], gamma[I, P], psol[I, P], energy[I, P]."""
     hists = np.asarray(hists)
+    ns = np.asarray(ns)
+    ms = np.asarray(ms)
     I = hists.shape[0]
     P = len(p_list)
-    gb, gg = fundamental_grid(*grid)
-    psol, energy = g.gqaoa_scan_batched(ns, ms, hists, gb, gg, p_list, targets=targets, tile=tile)
-    val = -psol if objective == "psol" else energy
-    flat = val.reshape(I, P, -1)
-    idx = flat.argmin(dim=2).cpu().numpy()                # ties -> lowest (gamma, beta) index
-    gi, bi = idx // gb.size, idx % gb.size
-    beta = gb[bi].astype(np.float64)
-    gamma = gg[gi].astype(np.float64)
+    gb, gg = fundamental_grid(*(grid or paper_grid()))
+    tg = None if targets is None else np.asarray(targets)
+    want_e = objective != "psol"
+    per_inst = P * gb.size * gg.size * 4 * (2 if want_e else 1)
+    chunk = max(1, int(max_out_bytes // per_inst))
+    beta = np.empty((I, P))
+    gamma = np.empty((I, P))
+    best_v = np.empty((I, P))
+    for c0 in range(0, I, chunk):
+        sl = slice(c0, min(I, c0 + chunk))
+        psol, energy = g.gqaoa_scan_batched(ns[sl], ms[sl], hists[sl], gb, gg, p_list,
+                                            targets=None if tg is None else tg[sl], tile=tile, with_energy=want_e)
+        val = -psol if objective == "psol" else energy
+        flat = val.reshape(sl.stop - sl.start, P, -1)
+        idx = flat.argmin(dim=2)                       # ties -> lowest (gamma, beta) index
+        best_v[sl] = flat.gather(2, idx[:, :, None])[:, :, 0].cpu().numpy()
+        idx = idx.cpu().numpy()
+        beta[sl] = gb[idx % gb.size]
+        gamma[sl] = gg[idx // gb.size]
+        del psol, energy, val, flat
     db, dg = gb[1] - gb[0], gg[1] - gg[0]
-    best_v = np.take_along_axis(flat.cpu().numpy(), idx[:, :, None], axis=2)[:, :, 0]
     for _ in range(zoom_levels):
         offs = (np.arange(zoom) - (zoom - 1) / 2.0) * (2.0 / zoom)
         for q, p in enumerate(p_list):
             bgrid = beta[:, q:q + 1] + offs[None, :] * db
             ggrid = np.clip(gamma[:, q:q + 1] + offs[None, :] * dg, 0.0, math.pi)
-            ps, en = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], targets=targets, tile=tile)
+            ps, en = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], targets=targets, tile=tile,
+                                          with_energy=want_e)
             v = (-ps if objective == "psol" else en)[:, 0].reshape(I, -1)
             j = v.argmin(dim=1).cpu().numpy()
             vj = v.cpu().numpy()[np.arange(I), j]
@@ -104,8 +127,8 @@ def batched_single_pair(ns, ms, hists, p_list, grid=(128, 64), zoom_levels: int 
     ps, en = g.gqaoa_scan_batched(ns, ms, hists, beta, gamma, p_list, targets=targets, tile=tile)
     ps = ps.cpu().numpy()
     en = en.cpu().numpy()
-    out_p = np.stack([ps[:, q, q, q] for q in range(P)], axis=1)
-    out_e = np.stack([en[:, q, q, q] for q in range(P)], axis=1)
+    out_p = np.stack([ps[:, q, q, q] for q in range(P)], axis=1).astype(np.float64)
+    out_e = np.stack([en[:, q, q, q] for q in range(P)], axis=1).astype(np.float64)
     return np.mod(beta, 2 * math.pi), gamma, out_p, out_e
 
 
