@@ -102,6 +102,20 @@ int gqaoa_evolve(int n, int m, const uint8_t *cost_dev, int p, const double *bet
                  int target_level, double *psol_host, double *energy_host,
                  double *norm_host, void *ws_dev, size_t ws_bytes, void *stream);
 
+/* ---- X-QAOA comparator (Sec. II.B, rows "X" of Table I) -------------------
+ * The same rounds with the transverse-field mixer in place of |s><s|: for
+ * j = 1..p, psi <- exp(-i gamma_j H_P) psi, then psi <- exp(-i beta_j H_X) psi,
+ * H_X = sum_q X_q, i.e. on every qubit q the amplitude pairs (a, b) differing
+ * in bit q of z become (cos b_j a - i sin b_j b, cos b_j b - i sin b_j a).
+ * Arguments, readouts, dtypes and errors as gqaoa_evolve (init_uniform starts
+ * from |+>); the level-space shortcut does not apply to this mixer.
+ * ws: gqaoa_x_workspace_bytes(n, p, dtype) bytes (0 for invalid arguments). */
+size_t gqaoa_x_workspace_bytes(int n, int p, int dtype);
+int gqaoa_evolve_x(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host,
+                   const double *gamma_host, int dtype, int init_uniform, void *psi_dev,
+                   int target_level, double *psol_host, double *energy_host,
+                   double *norm_host, void *ws_dev, size_t ws_bytes, void *stream);
+
 /* Solution probability of a given state (the readout of Sec. III, P_sol):
  * *out_host = sum over z with C(z) = target_level of |psi_z|^2.
  * ws: gqaoa_workspace_bytes(n, 0, dtype, 0) bytes. */
@@ -217,7 +231,7 @@ int gqaoa_mlp_features(int batch, const uint64_t *hists_dev, int hist_stride, co
  * kernels with HIP events on the launch stream and accumulates their
  * durations under a name: "sv_round_c64", "sv_round_c128" (forward round
  * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table"
- * and "scan". Durations are collected when the call that launched them
+ * "scan", and "x_round_c64", "x_round_c128" (whole X-QAOA rounds). Durations are collected when the call that launched them
  * synchronizes. gqaoa_profile_read returns GQAOA_EINVAL for an unknown name. */
 int gqaoa_profile_enable(int on);
 void gqaoa_profile_reset(void);

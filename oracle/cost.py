@@ -19,22 +19,28 @@ import itertools
 import numpy as np
 
 
+def cost_of(z, lits) -> np.ndarray:
+    """C(z) for the given assignments z (any int array): the number of
+    clauses whose three literals are all false."""
+    z = np.asarray(z, dtype=np.int64)
+    lits = np.asarray(lits, dtype=np.int64).reshape(-1, 3)
+    c = np.zeros(z.shape, dtype=np.int64)
+    for clause in lits:
+        unsat = np.ones(z.shape, dtype=bool)
+        for lit in clause:
+            var, neg = lit >> 1, lit & 1
+            unsat &= ((z >> var) & 1) == neg
+        c += unsat
+    return c
+
+
 def cost_table(n: int, lits, chunk_bits: int = 22) -> np.ndarray:
     """C(z) for z in [0, 2^n): the number of unsatisfied clauses (int64)."""
-    lits = np.asarray(lits, dtype=np.int64).reshape(-1, 3)
     N = 1 << n
     out = np.empty(N, dtype=np.int64)
     step = 1 << min(n, chunk_bits)
     for lo in range(0, N, step):
-        z = np.arange(lo, lo + step, dtype=np.int64)
-        c = np.zeros(step, dtype=np.int64)
-        for clause in lits:
-            unsat = np.ones(step, dtype=bool)
-            for lit in clause:
-                var, neg = lit >> 1, lit & 1
-                unsat &= ((z >> var) & 1) == neg
-            c += unsat
-        out[lo:lo + step] = c
+        out[lo:lo + step] = cost_of(np.arange(lo, lo + step, dtype=np.int64), lits)
     return out
 
 

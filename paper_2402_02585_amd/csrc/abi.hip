@@ -30,6 +30,10 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
              const int32_t *target_host, int nb, const double *betas, int ng, const double *gammas, int per_inst,
              int num_p, const int32_t *p_list, float *psol, float *energy, const int32_t *tile, void *ws,
              hipStream_t st);
+size_t x_workspace_bytes(int p, int dtype);
+int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
+                 int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
+                 hipStream_t st);
 size_t mlp_act_bytes(int batch);
 int run_mlp_forward(const float *prm, int batch, const float *x, float *out, void *act, hipStream_t st);
 int run_mlp_backward(const float *prm, int batch, const void *act, const float *dout, float *grads,
@@ -71,7 +75,7 @@ struct ProfTotal {
     int64_t count = 0;
 };
 static const char *kProfNames[] = {"sv_round_c64", "sv_round_c128", "sv_reverse_c64", "sv_reverse_c128",
-                                   "cost_table", "scan"};
+                                   "cost_table", "scan", "x_round_c64", "x_round_c128"};
 static ProfTotal g_prof_tot[sizeof(kProfNames) / sizeof(kProfNames[0])];
 
 bool prof_on() { return g_prof_on; }
@@ -226,6 +230,28 @@ int gqaoa_evolve(int n, int m, const uint8_t *cost_dev, int p, const double *bet
     if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     return run_evolve(n, m, cost_dev, p, beta_host, gamma_host, dtype, init_uniform, psi_dev, target_level, psol_host,
                       energy_host, norm_host, ws_dev, (hipStream_t)stream);
+}
+
+size_t gqaoa_x_workspace_bytes(int n, int p, int dtype) {
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N || p < 0 || p > kMaxP || !dtype_ok(dtype)) return 0;
+    return x_workspace_bytes(p, dtype);
+}
+
+int gqaoa_evolve_x(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host, const double *gamma_host,
+                   int dtype, int init_uniform, void *psi_dev, int target_level, double *psol_host,
+                   double *energy_host, double *norm_host, void *ws_dev, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (m < 1 || m > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "m=%d outside [1, 255]", m);
+    if (p < 0 || p > kMaxP) return fail(GQAOA_ERANGE, "p=%d outside [0, %d]", p, kMaxP);
+    if (target_level < 0 || target_level > m) return fail(GQAOA_ERANGE, "target_level=%d outside [0, m]", target_level);
+    if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
+    if (!cost_dev || !psi_dev || !ws_dev) return fail(GQAOA_EINVAL, "NULL cost_dev, psi_dev or ws_dev");
+    if (p > 0 && (!beta_host || !gamma_host)) return fail(GQAOA_EINVAL, "NULL angles");
+    const size_t need = x_workspace_bytes(p, dtype);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    return run_evolve_x(n, cost_dev, p, beta_host, gamma_host, dtype, init_uniform, psi_dev, target_level, psol_host,
+                        energy_host, norm_host, ws_dev, (hipStream_t)stream);
 }
 
 int gqaoa_solution_prob(int n, const uint8_t *cost_dev, const void *psi_dev, int dtype, int target_level,

@@ -34,6 +34,8 @@ _SIGS = {
     "gqaoa_workspace_bytes": ([_i32, _i32, _i32, _i32], _sz),
     "gqaoa_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_solution_prob": ([_i32, _vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_x_workspace_bytes": ([_i32, _i32, _i32], _sz),
+    "gqaoa_evolve_x": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_grad_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32], _sz),
     "gqaoa_grad": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_grad_batched": ([_i32, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
@@ -149,23 +151,57 @@ def _workspace(torch, nbytes: int):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
 
 
+def _state_args(torch, n, cost, betas, gammas, dt, psi):
+    """Host-side shape checks shared by the statevector entry points."""
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).ravel())
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).ravel())
+    if b.size != g.size:
+        raise ValueError(f"{b.size} betas but {g.size} gammas")
+    cdt = torch.complex64 if dt == C64 else torch.complex128
+    if psi is None:
+        psi = torch.empty(1 << n, dtype=cdt, device="cuda")
+    if psi.dtype != cdt or psi.numel() != (1 << n) or not psi.is_contiguous() or not psi.is_cuda:
+        raise ValueError(f"psi must be a contiguous device {cdt} tensor of 2^{n} entries")
+    if cost.numel() < (1 << n) or cost.dtype != torch.uint8 or not cost.is_cuda:
+        raise ValueError(f"cost must be a device uint8 tensor of 2^{n} entries")
+    return b, g, psi
+
+
 def gqaoa_evolve(n: int, m: int, cost, betas, gammas, dtype=C64, psi=None, init_uniform: bool = True,
                  target_level: int = 0, workspace=None, stream=None):
     """Eq. (3) on the device. Returns (psi, psol[p+1], energy[p+1], norm[p+1])."""
     torch = _torch()
     lib = load_library()
     dt = _dtype_code(dtype)
-    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
-    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    b, g, psi = _state_args(torch, n, cost, betas, gammas, dt, psi)
     p = b.size
-    if psi is None:
-        psi = torch.empty(1 << n, dtype=torch.complex64 if dt == C64 else torch.complex128, device="cuda")
     need = lib.gqaoa_workspace_bytes(n, p, dt, 0)
     ws = workspace if workspace is not None else _workspace(torch, need)
     psol, energy, norm = np.empty(p + 1), np.empty(p + 1), np.empty(p + 1)
     _check(lib.gqaoa_evolve(n, m, _ptr(cost), p, _np_ptr(b), _np_ptr(g), dt, int(bool(init_uniform)), _ptr(psi),
                             target_level, _np_ptr(psol), _np_ptr(energy), _np_ptr(norm), _ptr(ws),
                             ws.numel(), _stream(torch, stream)))
+    return psi, psol, energy, norm
+
+
+def gqaoa_x_workspace_bytes(n: int, p: int, dtype=C64) -> int:
+    return int(load_library().gqaoa_x_workspace_bytes(n, p, _dtype_code(dtype)))
+
+
+def gqaoa_evolve_x(n: int, m: int, cost, betas, gammas, dtype=C64, psi=None, init_uniform: bool = True,
+                   target_level: int = 0, workspace=None, stream=None):
+    """X-QAOA rounds (transverse-field mixer) on the device.
+    Returns (psi, psol[p+1], energy[p+1], norm[p+1])."""
+    torch = _torch()
+    lib = load_library()
+    dt = _dtype_code(dtype)
+    b, g, psi = _state_args(torch, n, cost, betas, gammas, dt, psi)
+    p = b.size
+    ws = workspace if workspace is not None else _workspace(torch, lib.gqaoa_x_workspace_bytes(n, p, dt))
+    psol, energy, norm = np.empty(p + 1), np.empty(p + 1), np.empty(p + 1)
+    _check(lib.gqaoa_evolve_x(n, m, _ptr(cost), p, _np_ptr(b), _np_ptr(g), dt, int(bool(init_uniform)), _ptr(psi),
+                              target_level, _np_ptr(psol), _np_ptr(energy), _np_ptr(norm), _ptr(ws),
+                              ws.numel(), _stream(torch, stream)))
     return psi, psol, energy, norm
 
 

@@ -85,6 +85,31 @@ def test_evolve_argument_checks():
     assert call(wsb=need - 1) == -3
 
 
+def test_evolve_x_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    b = np.zeros(3)
+    bp = g._np_ptr(b)
+    need = lib.gqaoa_x_workspace_bytes(10, 3, 1)
+    assert need > lib.gqaoa_x_workspace_bytes(10, 3, 0) > 0
+    assert lib.gqaoa_x_workspace_bytes(2, 3, 0) == 0
+    assert lib.gqaoa_x_workspace_bytes(10, -1, 0) == 0
+
+    def call(n=10, m=42, p=3, t=0, dt=1, cost=d, psi=d, beta=bp, wsb=need):
+        return lib.gqaoa_evolve_x(n, m, cost, p, beta, bp, dt, 1, psi, t, None, None, None, d, wsb, None)
+
+    assert call(n=2) == -2
+    assert call(n=35) == -2
+    assert call(m=0) == -2
+    assert call(p=-1) == -2
+    assert call(t=43) == -2
+    assert call(dt=2) == -1
+    assert call(cost=None) == -1
+    assert call(psi=None) == -1
+    assert call(beta=None) == -1
+    assert call(wsb=need - 1) == -3
+
+
 def test_grad_and_scan_argument_checks():
     lib = g.load_library()
     d = ctypes.c_void_p(16)
