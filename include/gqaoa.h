@@ -189,6 +189,22 @@ int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_hos
                        float *psol_dev, float *energy_dev, const int32_t *tile, void *ws_dev,
                        size_t ws_bytes, void *stream);
 
+/* Rounds-to-target form of the scan (the minimum-rounds search of Sec. III.A
+ * and its Max-SAT variant): the same single-angle-pair level-space rounds,
+ * run up to p_i rounds, recording for every (i, g, b)
+ *   first_p_dev[(i*ng + g)*nb + b] = the first round j in [1, p_i] after
+ *   which P_sol (at target_host[i]) >= threshold, or 0 if none.
+ * p_i = p_max_host[i] (each in [1, p_max]), or p_max for every instance when
+ * p_max_host is NULL; p_max in [1, 100000]; threshold in (0, 1]. The
+ * decision is taken on the float32 P_sol. Other arguments, workspace (with
+ * num_p = 1) and errors as gqaoa_scan_batched. */
+int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                        const uint64_t *hists_host, int hist_stride, const int32_t *target_host,
+                        int nb, const double *betas_host, int ng, const double *gammas_host,
+                        int per_instance_grid, int p_max, const int32_t *p_max_host,
+                        float threshold, int32_t *first_p_dev,
+                        const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream);
+
 /* ---- angle-predictor MLP (bfloat16 MFMA, float32 accumulation) -------------
  * The paper suggests deriving angles from statistics of the density of
  * states (Sec. V) and reports clustering of optimized pairs (Sec. III.B).

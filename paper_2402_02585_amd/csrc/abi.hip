@@ -28,8 +28,8 @@ size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int n
 int scan_max_levels();
 int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists, int hist_stride,
              const int32_t *target_host, int nb, const double *betas, int ng, const double *gammas, int per_inst,
-             int num_p, const int32_t *p_list, float *psol, float *energy, const int32_t *tile, void *ws,
-             hipStream_t st);
+             int num_p, const int32_t *p_list, float *psol, float *energy, float threshold, int32_t *first_p,
+             const int32_t *pmax_host, const int32_t *tile, void *ws, hipStream_t st);
 size_t x_workspace_bytes(int p, int dtype);
 int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
                  int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
@@ -323,17 +323,16 @@ size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng,
     return scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p, per_instance_grid ? 1 : 0);
 }
 
-int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
-                       int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
-                       const double *gammas_host, int per_instance_grid, int num_p, const int32_t *p_list_host,
-                       float *psol_dev,
-                       float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream) {
-    clear_error();
+// Checks shared by the two scan entry points (everything but the outputs).
+static int check_scan_args(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
+                           int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
+                           const double *gammas_host, int num_p, const int32_t *p_list_host, const int32_t *tile,
+                           const void *ws_dev) {
     if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d", num_inst);
     if (nb < 1 || nb > 4096 || ng < 1 || ng > 4096) return fail(GQAOA_ERANGE, "grid %d x %d outside [1, 4096]^2", nb, ng);
     if (num_p < 1 || num_p > 16) return fail(GQAOA_ERANGE, "num_p=%d outside [1, 16]", num_p);
     if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
-    if (!n_host || !m_host || !hists_host || !betas_host || !gammas_host || !p_list_host || !psol_dev || !ws_dev)
+    if (!n_host || !m_host || !hists_host || !betas_host || !gammas_host || !p_list_host || !ws_dev)
         return fail(GQAOA_EINVAL, "NULL argument");
     for (int q = 0; q < num_p; ++q) {
         if (p_list_host[q] < 1 || p_list_host[q] > kMaxP) return fail(GQAOA_ERANGE, "p_list[%d]=%d", q, p_list_host[q]);
@@ -353,11 +352,49 @@ int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_hos
         for (int k = 0; k <= m_host[i]; ++k) K += hists_host[(size_t)i * hist_stride + k] != 0;
         if (K > scan_max_levels()) return fail(GQAOA_ERANGE, "instance %d: %d occupied levels (max %d)", i, K, scan_max_levels());
     }
+    return GQAOA_OK;
+}
+
+int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
+                       int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
+                       const double *gammas_host, int per_instance_grid, int num_p, const int32_t *p_list_host,
+                       float *psol_dev,
+                       float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream) {
+    clear_error();
+    int s = check_scan_args(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng,
+                            gammas_host, num_p, p_list_host, tile, ws_dev);
+    if (s) return s;
+    if (!psol_dev) return fail(GQAOA_EINVAL, "NULL psol_dev");
     const int pig = per_instance_grid ? 1 : 0;
     const size_t need = scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p, pig);
     if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     return run_scan(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng, gammas_host,
-                    pig, num_p, p_list_host, psol_dev, energy_dev, tile, ws_dev, (hipStream_t)stream);
+                    pig, num_p, p_list_host, psol_dev, energy_dev, 0.f, nullptr, nullptr, tile, ws_dev,
+                    (hipStream_t)stream);
+}
+
+int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
+                        int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
+                        const double *gammas_host, int per_instance_grid, int p_max, const int32_t *p_max_host,
+                        float threshold, int32_t *first_p_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes,
+                        void *stream) {
+    clear_error();
+    const int32_t pl[1] = {p_max};
+    int s = check_scan_args(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng,
+                            gammas_host, 1, pl, tile, ws_dev);
+    if (s) return s;
+    if (p_max_host)
+        for (int i = 0; i < num_inst; ++i)
+            if (p_max_host[i] < 1 || p_max_host[i] > p_max)
+                return fail(GQAOA_ERANGE, "instance %d: p_max=%d outside [1, %d]", i, p_max_host[i], p_max);
+    if (!first_p_dev) return fail(GQAOA_EINVAL, "NULL first_p_dev");
+    if (!(threshold > 0.f && threshold <= 1.f)) return fail(GQAOA_ERANGE, "threshold=%g outside (0, 1]", (double)threshold);
+    const int pig = per_instance_grid ? 1 : 0;
+    const size_t need = scan_workspace_bytes(num_inst, hist_stride, nb, ng, 1, pig);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    return run_scan(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng, gammas_host,
+                    pig, 1, pl, nullptr, nullptr, threshold, first_p_dev, p_max_host, tile, ws_dev,
+                    (hipStream_t)stream);
 }
 
 size_t gqaoa_mlp_act_bytes(int batch) {

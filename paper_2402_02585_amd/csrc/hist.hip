@@ -166,6 +166,8 @@ struct ScanSlot {          // one instance inside a bucket, in queue order
     int32_t lev_off;       // into lev/w
     int32_t K;             // occupied levels
     int32_t t_idx;         // position of the target level among them, -1 if unoccupied
+    int32_t pmax;          // rounds to run for this instance
+    int32_t pad[3];
 };
 
 struct ScanArgs {
@@ -176,6 +178,8 @@ struct ScanArgs {
     const double *gammas;
     float *psol;
     float *energy;
+    int32_t *first_p;      // crossing mode: [inst][ng][nb] first round with P >= threshold (0: none)
+    float threshold;
     unsigned int *counter;
     unsigned int total_items;
     int nb, ng, ntiles, num_p;
@@ -183,12 +187,14 @@ struct ScanArgs {
     int p_list[kScanMaxP];
 };
 
-template <int KMAX>
+// CROSS = false: P_sol (and E) after each p in p_list. CROSS = true: the
+// first round j <= p_list[0] with P >= threshold; a wave stops once every
+// lane has crossed.
+template <int KMAX, bool CROSS>
 __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
     __shared__ float4 tab_s[kScanMaxWaves][KMAX];   // e^{-i gamma k}.re/.im, w_k, k w_k
     const int lane = threadIdx.x & 63;
     float4 *tab = tab_s[threadIdx.x >> 6];
-    const int pmax = a.p_list[a.num_p - 1];
     for (;;) {
         unsigned int item = 0;
         if (lane == 0) item = atomicAdd(a.counter, 1u);
@@ -198,6 +204,7 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
         const unsigned rest = item / (unsigned)a.ntiles;
         const int g = (int)(rest % (unsigned)a.ng);
         const ScanSlot sl = a.slots[rest / (unsigned)a.ng];
+        const int pmax = sl.pmax;
         const double gam = a.gammas[(a.per_inst ? (size_t)sl.inst * a.ng : 0) + g];
         for (int k = lane; k < KMAX; k += 64) {
             float4 e = {1.f, 0.f, 0.f, 0.f};
@@ -226,6 +233,7 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
             bi[k] = 0.f;
         }
         int q = 0;
+        int found = 0;
         for (int j = 1; j <= pmax; ++j) {
             // Small tables stay in registers across rounds; larger ones are
             // re-read from LDS (broadcast) each round to bound register use.
@@ -247,7 +255,14 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
                 br[k] += cr;
                 bi[k] += ci;
             }
-            if (j == a.p_list[q]) {
+            if constexpr (CROSS) {
+                float P = 0.f;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    P += k == sl.t_idx ? tab[k].z * (br[k] * br[k] + bi[k] * bi[k]) : 0.f;
+                if (found == 0 && P >= a.threshold) found = j;
+                if (__ballot(active && found == 0) == 0) break;  // wave-uniform
+            } else if (j == a.p_list[q]) {
                 float P = 0.f, E = 0.f;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
@@ -264,6 +279,8 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
                 ++q;
             }
         }
+        if constexpr (CROSS)
+            if (active) a.first_p[((size_t)sl.inst * a.ng + g) * a.nb + b] = found;
         // the next item rewrites tab: keep every lane's reads of this one first
         __builtin_amdgcn_wave_barrier();
     }
@@ -280,22 +297,24 @@ constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
 constexpr int kScanMaxK = 128;
 
 typedef void (*ScanFn)(ScanArgs);
-static ScanFn scan_fn(int bucket) {
+template <bool CROSS>
+static ScanFn scan_fn_t(int bucket) {
     switch (kBuckets[bucket]) {
-        case 8: return scan_kernel<8>;
-        case 16: return scan_kernel<16>;
-        case 24: return scan_kernel<24>;
-        case 32: return scan_kernel<32>;
-        case 40: return scan_kernel<40>;
-        case 48: return scan_kernel<48>;
-        case 56: return scan_kernel<56>;
-        case 64: return scan_kernel<64>;
-        case 80: return scan_kernel<80>;
-        case 96: return scan_kernel<96>;
-        case 112: return scan_kernel<112>;
-        default: return scan_kernel<128>;
+        case 8: return scan_kernel<8, CROSS>;
+        case 16: return scan_kernel<16, CROSS>;
+        case 24: return scan_kernel<24, CROSS>;
+        case 32: return scan_kernel<32, CROSS>;
+        case 40: return scan_kernel<40, CROSS>;
+        case 48: return scan_kernel<48, CROSS>;
+        case 56: return scan_kernel<56, CROSS>;
+        case 64: return scan_kernel<64, CROSS>;
+        case 80: return scan_kernel<80, CROSS>;
+        case 96: return scan_kernel<96, CROSS>;
+        case 112: return scan_kernel<112, CROSS>;
+        default: return scan_kernel<128, CROSS>;
     }
 }
+static ScanFn scan_fn(int bucket, bool cross) { return cross ? scan_fn_t<true>(bucket) : scan_fn_t<false>(bucket); }
 
 int scan_max_levels() { return kScanMaxK; }
 
@@ -341,7 +360,7 @@ static int launch_bucket(int bucket, const TileChoice &tc, const DeviceInfo &dev
     a.counter = counter;
     const unsigned want = (a.total_items + tc.waves - 1) / tc.waves;
     const unsigned blocks = std::max(1u, std::min<unsigned>(want, (unsigned)(dev.num_cus * tc.blocks_per_cu)));
-    hipLaunchKernelGGL(scan_fn(bucket), dim3(blocks), dim3(64 * tc.waves), 0, st, a);
+    hipLaunchKernelGGL(scan_fn(bucket, a.first_p != nullptr), dim3(blocks), dim3(64 * tc.waves), 0, st, a);
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
 }
@@ -349,7 +368,8 @@ static int launch_bucket(int bucket, const TileChoice &tc, const DeviceInfo &dev
 static int tune_bucket(int bucket, const DeviceInfo &dev, const ScanArgs &a, unsigned int *counter,
                        hipStream_t st, TileChoice *out) {
     const std::string key = std::string(dev.arch) + ":k" + std::to_string(kBuckets[bucket]) + ":t" +
-                            std::to_string(a.ntiles) + ":p" + std::to_string(a.p_list[a.num_p - 1] > 16 ? 64 : 16);
+                            std::to_string(a.ntiles) + ":p" + std::to_string(a.p_list[a.num_p - 1] > 16 ? 64 : 16) +
+                            (a.first_p ? ":x" : "");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
@@ -407,7 +427,8 @@ size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int n
 int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
              int hist_stride, const int32_t *target_host, int nb, const double *betas, int ng,
              const double *gammas, int per_inst, int num_p, const int32_t *p_list, float *psol, float *energy,
-             const int32_t *tile, void *ws, hipStream_t st) {
+             float threshold, int32_t *first_p, const int32_t *pmax_host, const int32_t *tile, void *ws,
+             hipStream_t st) {
     DeviceInfo dev;
     int s = device_info(&dev);
     if (s) return s;
@@ -444,7 +465,8 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
         auto &mb = members[bk];
         std::stable_sort(mb.begin(), mb.end(), [&](int x, int y) { return K[x] > K[y]; });
         bucket_first[bk] = (int)slots.size();
-        for (int i : mb) slots.push_back(ScanSlot{i, off[i], K[i], tidx[i]});
+        for (int i : mb)
+            slots.push_back(ScanSlot{i, off[i], K[i], tidx[i], pmax_host ? pmax_host[i] : p_list[num_p - 1], {0, 0, 0}});
     }
     bucket_first[kNumBuckets] = (int)slots.size();
     // device copies
@@ -475,6 +497,8 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
     a.gammas = d_g;
     a.psol = psol;
     a.energy = energy;
+    a.first_p = first_p;
+    a.threshold = threshold;
     a.nb = nb;
     a.ng = ng;
     a.ntiles = (nb + 63) / 64;

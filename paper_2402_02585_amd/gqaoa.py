@@ -43,6 +43,8 @@ _SIGS = {
     "gqaoa_scan_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32, _i32], _sz),
     "gqaoa_scan_batched": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                             _sz, _vp], _i32),
+    "gqaoa_scan_crossing": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _f32, _vp, _vp,
+                             _vp, _sz, _vp], _i32),
     "gqaoa_mlp_act_bytes": ([_i32], _sz),
     "gqaoa_mlp_forward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_mlp_backward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
@@ -269,6 +271,25 @@ def gqaoa_scan_workspace_bytes(num_inst: int, hist_stride: int, nb: int, ng: int
                                                          int(bool(per_instance_grid))))
 
 
+def _scan_common(ns, ms, hists, betas, gammas, targets, tile):
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    h = np.ascontiguousarray(np.asarray(hists).astype(np.uint64))
+    I, stride = h.shape
+    if ns.shape != (I,) or ms.shape != (I,):
+        raise ValueError(f"ns and ms must have {I} entries")
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+    per_inst = b.ndim == 2
+    if per_inst != (g.ndim == 2) or (per_inst and (b.shape[0] != I or g.shape[0] != I)):
+        raise ValueError("betas and gammas must both be 1-D, or both [num_inst, *]")
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    if tg is not None and tg.shape != (I,):
+        raise ValueError(f"targets must have {I} entries")
+    tl = None if tile is None else np.ascontiguousarray(np.asarray(tile, dtype=np.int32))
+    return ns, ms, h, I, stride, b, g, per_inst, b.shape[-1], g.shape[-1], tg, tl
+
+
 def gqaoa_scan_batched(ns, ms, hists, betas, gammas, p_list, targets=None, tile=None, with_energy: bool = True,
                        out=None, workspace=None, stream=None):
     """Single-angle-pair scan. hists: host int64/uint64 [I, stride]. betas, gammas:
@@ -276,31 +297,45 @@ def gqaoa_scan_batched(ns, ms, hists, betas, gammas, p_list, targets=None, tile=
     instance). Returns (psol, energy) float32 device tensors [I, num_p, ng, nb]."""
     torch = _torch()
     lib = load_library()
-    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
-    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
-    h = np.ascontiguousarray(np.asarray(hists).astype(np.uint64))
-    I, stride = h.shape
-    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
-    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
-    per_inst = b.ndim == 2
-    if per_inst != (g.ndim == 2) or (per_inst and (b.shape[0] != I or g.shape[0] != I)):
-        raise ValueError("betas and gammas must both be 1-D, or both [num_inst, *]")
-    nb, ng = b.shape[-1], g.shape[-1]
+    ns, ms, h, I, stride, b, g, per_inst, nb, ng, tg, tl = _scan_common(ns, ms, hists, betas, gammas, targets, tile)
     pl = np.ascontiguousarray(np.asarray(p_list, dtype=np.int32))
-    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
-    tl = None if tile is None else np.ascontiguousarray(np.asarray(tile, dtype=np.int32))
     shape = (I, pl.size, ng, nb)
     if out is None:
         psol = torch.empty(shape, dtype=torch.float32, device="cuda")
         energy = torch.empty(shape, dtype=torch.float32, device="cuda") if with_energy else None
     else:
         psol, energy = out
+    for t in (psol, energy):
+        if t is not None and (tuple(t.shape) != shape or t.dtype != torch.float32 or not t.is_contiguous()):
+            raise ValueError(f"scan outputs must be contiguous float32 {shape}")
     need = lib.gqaoa_scan_workspace_bytes(I, stride, nb, ng, pl.size, int(per_inst))
     ws = workspace if workspace is not None else _workspace(torch, need)
     _check(lib.gqaoa_scan_batched(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), nb, _np_ptr(b),
                                   ng, _np_ptr(g), int(per_inst), pl.size, _np_ptr(pl), _ptr(psol), _ptr(energy),
                                   _np_ptr(tl), _ptr(ws), ws.numel(), _stream(torch, stream)))
     return psol, energy
+
+
+def gqaoa_scan_crossing(ns, ms, hists, betas, gammas, p_max, threshold: float, targets=None, tile=None,
+                        workspace=None, stream=None):
+    """First round j <= p_max with P_sol >= threshold for every (instance, gamma,
+    beta) of the grid (0 if none): int32 device tensor [I, ng, nb]. p_max is
+    one int or one per instance."""
+    torch = _torch()
+    lib = load_library()
+    ns, ms, h, I, stride, b, g, per_inst, nb, ng, tg, tl = _scan_common(ns, ms, hists, betas, gammas, targets, tile)
+    pm = np.ascontiguousarray(np.asarray(p_max, dtype=np.int32).reshape(-1))
+    if pm.size not in (1, I):
+        raise ValueError(f"p_max must be one value or {I}")
+    pm_all = None if pm.size == 1 else pm
+    first = torch.empty((I, ng, nb), dtype=torch.int32, device="cuda")
+    need = lib.gqaoa_scan_workspace_bytes(I, stride, nb, ng, 1, int(per_inst))
+    ws = workspace if workspace is not None else _workspace(torch, need)
+    _check(lib.gqaoa_scan_crossing(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), nb, _np_ptr(b),
+                                   ng, _np_ptr(g), int(per_inst), int(pm.max()), _np_ptr(pm_all), float(threshold),
+                                   _ptr(first),
+                                   _np_ptr(tl), _ptr(ws), ws.numel(), _stream(torch, stream)))
+    return first
 
 
 # ---- MLP ---------------------------------------------------------------------------------

@@ -191,17 +191,30 @@ def uniform_angles(seed: int, p: int, lo: float = 0.0, hi: float = np.pi):
     return beta, gamma
 
 
+def _draw_density(rng, densities, density_range):
+    if density_range is not None:
+        return float(rng.uniform(density_range[0], density_range[1]))
+    return float(densities[int(rng.integers(0, len(densities)))])
+
+
+def _keep(n, lits, want):
+    if want == "any":
+        return True
+    sat = dpll_satisfiable(n, lits)
+    return sat if want == "sat" else not sat
+
+
 def _child_instance(args):
-    seed, count, k, n_lo, n_hi, densities, sat_only = args
+    seed, count, k, n_lo, n_hi, densities, want, density_range, dup = args
     # child k of SeedSequence(seed).spawn(count), built directly
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed, spawn_key=(k,))))
     n = int(rng.integers(n_lo, n_hi + 1))
-    d = float(densities[int(rng.integers(0, len(densities)))])
+    d = _draw_density(rng, densities, density_range)
     m = m_from_density(n, d)
     draw = 0
     while True:
-        lits = random_3sat(rng, n, m)
-        if not sat_only or dpll_satisfiable(n, lits):
+        lits = random_3sat(rng, n, m, dup=dup)
+        if _keep(n, lits, want):
             break
         draw += 1
     return Instance(n=n, lits=lits, seed=k, draw=draw, d=d)
@@ -209,29 +222,36 @@ def _child_instance(args):
 
 def batched_scan_instances(seed: int, count: int, n_lo: int, n_hi: int,
                            densities=(3.0, 4.2, 5.0), sat_only: bool = True,
-                           accept=None, workers: int = 1) -> list:
+                           accept=None, workers: int = 1, want: str | None = None,
+                           density_range=None, dup: str = "redraw") -> list:
     """``count`` instances; child k draws from SeedSequence(seed) child k.
 
-    Each child draws n ~ U{n_lo..n_hi}, d ~ U(densities), m = round(n d), then
-    clause sets until one is satisfiable (when ``sat_only``). ``workers`` > 1
-    splits the children over processes (same instances for any value).
+    Each child draws n ~ U{n_lo..n_hi}, d ~ U(densities) (or d ~ U(lo, hi)
+    with ``density_range=(lo, hi)``, the paper's recipe), m = round(n d), then
+    clause sets until one is kept: ``want`` = "sat" (the default when
+    ``sat_only``), "unsat" (the Max-SAT set above the threshold) or "any".
+    ``dup`` as in ``random_3sat``. ``workers`` > 1 splits the children over
+    processes (same instances for any value).
     """
+    want = want or ("sat" if sat_only else "any")
+    if want not in ("sat", "unsat", "any"):
+        raise ValueError("want must be 'sat', 'unsat' or 'any'")
     if accept is not None:
         out = []
         for k, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
             rng = np.random.Generator(np.random.PCG64(child))
             n = int(rng.integers(n_lo, n_hi + 1))
-            d = float(densities[int(rng.integers(0, len(densities)))])
+            d = _draw_density(rng, densities, density_range)
             m = m_from_density(n, d)
             draw = 0
             while True:
-                lits = random_3sat(rng, n, m)
-                if not sat_only or accept(n, lits):
+                lits = random_3sat(rng, n, m, dup=dup)
+                if want == "any" or accept(n, lits):
                     break
                 draw += 1
             out.append(Instance(n=n, lits=lits, seed=k, draw=draw, d=d))
         return out
-    args = [(seed, count, k, n_lo, n_hi, tuple(densities), sat_only) for k in range(count)]
+    args = [(seed, count, k, n_lo, n_hi, tuple(densities), want, density_range, dup) for k in range(count)]
     if workers <= 1:
         return [_child_instance(a) for a in args]
     import multiprocessing as mp
