@@ -247,7 +247,7 @@ int gqaoa_mlp_features(int batch, const uint64_t *hists_dev, int hist_stride, co
  * kernels with HIP events on the launch stream and accumulates their
  * durations under a name: "sv_round_c64", "sv_round_c128" (forward round
  * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table"
- * "scan", and "x_round_c64", "x_round_c128" (whole X-QAOA rounds). Durations are collected when the call that launched them
+ * "scan", and "x_pass_c64", "x_pass_c128" (X-QAOA streaming passes). Durations are collected when the call that launched them
  * synchronizes. gqaoa_profile_read returns GQAOA_EINVAL for an unknown name. */
 int gqaoa_profile_enable(int on);
 void gqaoa_profile_reset(void);

@@ -30,7 +30,7 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
              const int32_t *target_host, int nb, const double *betas, int ng, const double *gammas, int per_inst,
              int num_p, const int32_t *p_list, float *psol, float *energy, float threshold, int32_t *first_p,
              const int32_t *pmax_host, const int32_t *tile, void *ws, hipStream_t st);
-size_t x_workspace_bytes(int p, int dtype);
+size_t x_workspace_bytes(int n, int p, int dtype);
 int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
                  int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
                  hipStream_t st);
@@ -75,7 +75,7 @@ struct ProfTotal {
     int64_t count = 0;
 };
 static const char *kProfNames[] = {"sv_round_c64", "sv_round_c128", "sv_reverse_c64", "sv_reverse_c128",
-                                   "cost_table", "scan", "x_round_c64", "x_round_c128"};
+                                   "cost_table", "scan", "x_pass_c64", "x_pass_c128"};
 static ProfTotal g_prof_tot[sizeof(kProfNames) / sizeof(kProfNames[0])];
 
 bool prof_on() { return g_prof_on; }
@@ -234,7 +234,7 @@ int gqaoa_evolve(int n, int m, const uint8_t *cost_dev, int p, const double *bet
 
 size_t gqaoa_x_workspace_bytes(int n, int p, int dtype) {
     if (n < GQAOA_MIN_N || n > GQAOA_MAX_N || p < 0 || p > kMaxP || !dtype_ok(dtype)) return 0;
-    return x_workspace_bytes(p, dtype);
+    return x_workspace_bytes(n, p, dtype);
 }
 
 int gqaoa_evolve_x(int n, int m, const uint8_t *cost_dev, int p, const double *beta_host, const double *gamma_host,
@@ -248,7 +248,7 @@ int gqaoa_evolve_x(int n, int m, const uint8_t *cost_dev, int p, const double *b
     if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
     if (!cost_dev || !psi_dev || !ws_dev) return fail(GQAOA_EINVAL, "NULL cost_dev, psi_dev or ws_dev");
     if (p > 0 && (!beta_host || !gamma_host)) return fail(GQAOA_EINVAL, "NULL angles");
-    const size_t need = x_workspace_bytes(p, dtype);
+    const size_t need = x_workspace_bytes(n, p, dtype);
     if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
     return run_evolve_x(n, cost_dev, p, beta_host, gamma_host, dtype, init_uniform, psi_dev, target_level, psol_host,
                         energy_host, norm_host, ws_dev, (hipStream_t)stream);
