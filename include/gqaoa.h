@@ -242,13 +242,42 @@ int gqaoa_mlp_loss(int batch, const float *out_dev, const float *targets_dev, fl
 int gqaoa_mlp_features(int batch, const uint64_t *hists_dev, int hist_stride, const int32_t *n_dev,
                        const int32_t *m_dev, const int32_t *p_dev, float *x_dev, void *stream);
 
+/* ---- fair-sampling metrics (Sec. IV, Table I, the two right-hand columns) ---
+ * Monte Carlo on the device over noiseless output probabilities. Random
+ * numbers: SplitMix64 (Steele, Lea and Flood, 2014) used counter-based, draw
+ * d of run r is output r * 2^32 + d of the generator started from state seed,
+ * u = (x >> 11) * 2^-53; a draw is the first category k with u < cdf[k]
+ * (running sums in index order).
+ *
+ * gqaoa_shots_to_all: p_host[k] = probability of solution k in the output
+ * distribution (k < num_solutions <= 64, sum <= 1; the remaining mass is the
+ * non-solution outcome). For every run r < runs, shots_dev[r] (int32,
+ * device) = the number of shots until every solution has appeared, or 0 if
+ * that takes more than max_shots.
+ *
+ * gqaoa_draws_to_reject: draws from the distribution conditioned on
+ * solutions (q_host, num_solutions in [2, 64], normalized here; the last
+ * solution takes any rounding rest). For every trial, after each draw N >=
+ * n_min the chi-squared statistic against the uniform distribution is
+ * compared with crit (the caller's critical value for num_solutions - 1
+ * degrees of freedom) in the exact form K sum_k O_k^2 - N^2 > crit N;
+ * draws_dev[trial] = the first such N, or 0 if none up to max_draws (<= 1e7).
+ * Both synchronize the stream. Errors: ERANGE (counts and limits), EINVAL
+ * (NULL pointers, negative or non-finite probabilities, crit). */
+int gqaoa_shots_to_all(int num_solutions, const double *p_host, int runs, uint64_t seed,
+                       int max_shots, int32_t *shots_dev, void *stream);
+int gqaoa_draws_to_reject(int num_solutions, const double *q_host, int trials, uint64_t seed,
+                          double crit, int n_min, int max_draws, int32_t *draws_dev,
+                          void *stream);
+
 /* ---- instrumentation ---------------------------------------------------------
  * When enabled, the library brackets each launch of its streaming round
  * kernels with HIP events on the launch stream and accumulates their
  * durations under a name: "sv_round_c64", "sv_round_c128" (forward round
- * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table"
- * "scan", and "x_pass_c64", "x_pass_c128" (X-QAOA streaming passes). Durations are collected when the call that launched them
- * synchronizes. gqaoa_profile_read returns GQAOA_EINVAL for an unknown name. */
+ * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table",
+ * "scan", and "x_pass_c64", "x_pass_c128" (X-QAOA streaming passes).
+ * Durations are collected when the call that launched them synchronizes.
+ * gqaoa_profile_read returns GQAOA_EINVAL for an unknown name. */
 int gqaoa_profile_enable(int on);
 void gqaoa_profile_reset(void);
 int gqaoa_profile_read(const char *name, double *total_ms, int64_t *count);

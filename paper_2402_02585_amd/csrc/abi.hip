@@ -3,6 +3,8 @@
 // call, so an invalid call returns without touching the device.
 #include "internal.h"
 
+#include <cmath>
+
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -34,6 +36,9 @@ size_t x_workspace_bytes(int n, int p, int dtype);
 int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
                  int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
                  hipStream_t st);
+int run_shots_to_all(int K, const double *p, int runs, uint64_t seed, int max_shots, int32_t *out, hipStream_t st);
+int run_draws_to_reject(int K, const double *q, int trials, uint64_t seed, double crit, int n_min, int max_draws,
+                        int32_t *out, hipStream_t st);
 size_t mlp_act_bytes(int batch);
 int run_mlp_forward(const float *prm, int batch, const float *x, float *out, void *act, hipStream_t st);
 int run_mlp_backward(const float *prm, int batch, const void *act, const float *dout, float *grads,
@@ -395,6 +400,41 @@ int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_ho
     return run_scan(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng, gammas_host,
                     pig, 1, pl, nullptr, nullptr, threshold, first_p_dev, p_max_host, tile, ws_dev,
                     (hipStream_t)stream);
+}
+
+int gqaoa_shots_to_all(int num_solutions, const double *p_host, int runs, uint64_t seed, int max_shots,
+                       int32_t *shots_dev, void *stream) {
+    clear_error();
+    if (num_solutions < 1 || num_solutions > 64) return fail(GQAOA_ERANGE, "num_solutions=%d outside [1, 64]", num_solutions);
+    if (runs < 1 || runs > (1 << 26)) return fail(GQAOA_ERANGE, "runs=%d", runs);
+    if (max_shots < 1) return fail(GQAOA_ERANGE, "max_shots=%d", max_shots);
+    if (!p_host || !shots_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    double tot = 0.0;
+    for (int k = 0; k < num_solutions; ++k) {
+        if (!(p_host[k] >= 0.0) || !std::isfinite(p_host[k])) return fail(GQAOA_EINVAL, "p[%d]=%g", k, p_host[k]);
+        tot += p_host[k];
+    }
+    if (!(tot > 0.0) || tot > 1.0 + 1e-9) return fail(GQAOA_EINVAL, "solution probabilities sum to %g", tot);
+    return run_shots_to_all(num_solutions, p_host, runs, seed, max_shots, shots_dev, (hipStream_t)stream);
+}
+
+int gqaoa_draws_to_reject(int num_solutions, const double *q_host, int trials, uint64_t seed, double crit, int n_min,
+                          int max_draws, int32_t *draws_dev, void *stream) {
+    clear_error();
+    if (num_solutions < 2 || num_solutions > 64) return fail(GQAOA_ERANGE, "num_solutions=%d outside [2, 64]", num_solutions);
+    if (trials < 1 || trials > (1 << 24)) return fail(GQAOA_ERANGE, "trials=%d", trials);
+    if (max_draws < 1 || max_draws > 10000000) return fail(GQAOA_ERANGE, "max_draws=%d outside [1, 1e7]", max_draws);
+    if (n_min < 1) return fail(GQAOA_ERANGE, "n_min=%d", n_min);
+    if (!(crit > 0.0) || !std::isfinite(crit)) return fail(GQAOA_EINVAL, "crit=%g", crit);
+    if (!q_host || !draws_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    double tot = 0.0;
+    for (int k = 0; k < num_solutions; ++k) {
+        if (!(q_host[k] >= 0.0) || !std::isfinite(q_host[k])) return fail(GQAOA_EINVAL, "q[%d]=%g", k, q_host[k]);
+        tot += q_host[k];
+    }
+    if (!(tot > 0.0)) return fail(GQAOA_EINVAL, "solution probabilities sum to %g", tot);
+    return run_draws_to_reject(num_solutions, q_host, trials, seed, crit, n_min, max_draws, draws_dev,
+                               (hipStream_t)stream);
 }
 
 size_t gqaoa_mlp_act_bytes(int batch) {

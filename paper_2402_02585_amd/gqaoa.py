@@ -45,6 +45,8 @@ _SIGS = {
                             _sz, _vp], _i32),
     "gqaoa_scan_crossing": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _f32, _vp, _vp,
                              _vp, _sz, _vp], _i32),
+    "gqaoa_shots_to_all": ([_i32, _vp, _i32, _c.c_uint64, _i32, _vp, _vp], _i32),
+    "gqaoa_draws_to_reject": ([_i32, _vp, _i32, _c.c_uint64, _c.c_double, _i32, _i32, _vp, _vp], _i32),
     "gqaoa_mlp_act_bytes": ([_i32], _sz),
     "gqaoa_mlp_forward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_mlp_backward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
@@ -336,6 +338,28 @@ def gqaoa_scan_crossing(ns, ms, hists, betas, gammas, p_max, threshold: float, t
                                    _ptr(first),
                                    _np_ptr(tl), _ptr(ws), ws.numel(), _stream(torch, stream)))
     return first
+
+
+# ---- fair-sampling metrics ------------------------------------------------------------
+def gqaoa_shots_to_all(p_sol, runs: int, seed: int, max_shots: int, stream=None):
+    """Shots until every solution is seen, per run: int32 device tensor [runs]."""
+    torch = _torch()
+    p = np.ascontiguousarray(np.asarray(p_sol, dtype=np.float64).ravel())
+    out = torch.empty(runs, dtype=torch.int32, device="cuda")
+    _check(load_library().gqaoa_shots_to_all(p.size, _np_ptr(p), runs, seed, max_shots, _ptr(out),
+                                             _stream(torch, stream)))
+    return out
+
+
+def gqaoa_draws_to_reject(q_sol, trials: int, seed: int, crit: float, n_min: int, max_draws: int, stream=None):
+    """Draws until the chi-squared test rejects uniform solution sampling, per
+    trial: int32 device tensor [trials] (0: not within max_draws)."""
+    torch = _torch()
+    q = np.ascontiguousarray(np.asarray(q_sol, dtype=np.float64).ravel())
+    out = torch.empty(trials, dtype=torch.int32, device="cuda")
+    _check(load_library().gqaoa_draws_to_reject(q.size, _np_ptr(q), trials, seed, float(crit), n_min, max_draws,
+                                                _ptr(out), _stream(torch, stream)))
+    return out
 
 
 # ---- MLP ---------------------------------------------------------------------------------

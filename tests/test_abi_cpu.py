@@ -138,6 +138,25 @@ def test_grad_and_scan_argument_checks():
     assert lib.gqaoa_scan_workspace_bytes(1, 43, 4, 4, 2, 1) >= ws
 
 
+def test_fairness_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    p = np.array([0.2, 0.3])
+    pp = g._np_ptr(p)
+    assert lib.gqaoa_shots_to_all(0, pp, 10, 1, 100, d, None) == -2
+    assert lib.gqaoa_shots_to_all(65, pp, 10, 1, 100, d, None) == -2
+    assert lib.gqaoa_shots_to_all(2, pp, 0, 1, 100, d, None) == -2
+    assert lib.gqaoa_shots_to_all(2, None, 10, 1, 100, d, None) == -1
+    bad = np.array([0.7, 0.6])
+    assert lib.gqaoa_shots_to_all(2, g._np_ptr(bad), 10, 1, 100, d, None) == -1   # sum > 1
+    neg = np.array([0.5, -0.1])
+    assert lib.gqaoa_shots_to_all(2, g._np_ptr(neg), 10, 1, 100, d, None) == -1
+    assert lib.gqaoa_draws_to_reject(1, pp, 10, 1, 3.8, 5, 100, d, None) == -2     # chi-squared needs K >= 2
+    assert lib.gqaoa_draws_to_reject(2, pp, 10, 1, 3.8, 5, 10 ** 7 + 1, d, None) == -2
+    assert lib.gqaoa_draws_to_reject(2, pp, 10, 1, 0.0, 5, 100, d, None) == -1
+    assert lib.gqaoa_draws_to_reject(2, pp, 10, 1, 3.8, 0, 100, d, None) == -2
+
+
 def test_mlp_argument_checks():
     lib = g.load_library()
     d = ctypes.c_void_p(16)
