@@ -14,7 +14,11 @@ Also reported (extra keys of the same JSON line):
   * ``batched``: the single-angle-pair scan over 4096 instances (n in 8..20,
     d in {3, 4.2, 5}, 64 x 64 angle grid, p in {1, 4, 16, 64}) against the
     plain one-instance-one-angle-pair path on the same GPU,
-  * ``cost_table``: clause evaluations per second of the cost-table kernel.
+  * ``cost_table``: clause evaluations per second of the cost-table kernel,
+  * ``adjoint``: batched adjoint gradients (256 instances, n = 20, p = 32),
+  * ``xqaoa``: the X-QAOA comparator on the headline instance (p = 16),
+  * ``rounds_to_target``: the single-pair rounds-to-target search over 512
+    instances.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -199,6 +203,69 @@ def adjoint_leg(torch, g, inst, reps: int = 2):
     }
 
 
+def xqaoa_leg(torch, g, inst, it, reps: int = 3):
+    """X-QAOA comparator (transverse-field mixer) on the headline instance:
+    n = 28, complex64, p = 16 (the first 16 headline angle pairs)."""
+    n, m, p = N_VARS, M_CLAUSES, 16
+    beta, gamma = inst.uniform_angles(2, P_ROUNDS)
+    beta, gamma = beta[:p], gamma[:p]
+    N = 1 << n
+    cost, _ = g.gqaoa_cost_table(n, it.lits, with_hist=False)
+    psi = torch.empty(N, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(g.gqaoa_x_workspace_bytes(n, p, g.C64), dtype=torch.uint8, device="cuda")
+    g.gqaoa_evolve_x(n, m, cost, beta, gamma, dtype=g.C64, psi=psi, workspace=ws)   # warm-up
+    torch.cuda.synchronize()
+    g.gqaoa_profile_reset()
+    g.gqaoa_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, psol, _, norm = g.gqaoa_evolve_x(n, m, cost, beta, gamma, dtype=g.C64, psi=psi, workspace=ws)
+    dt = (time.perf_counter() - t0) / reps
+    g.gqaoa_profile_enable(False)
+    pass_ms, pass_cnt = g.gqaoa_profile_read("x_pass_c64")
+    passes = pass_cnt // reps
+    # groups at n = 28: qubits 0-11, 12-19, 20-27; a round is two passes. The
+    # first pass starts from |s> (writes 8 B, reads 1 B of cost), every other
+    # pass reads and writes 16 B, and the p later readout passes (p - 1 fused
+    # round boundaries and the last pass) read 1 B of cost
+    pass_bytes = N * (9 + (passes - 1) * 16 + p * 1)
+    del psi, ws, cost
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"X-QAOA statevector, the headline instance n={n} m={m}, complex64, p={p} (first {p} headline angle pairs)",
+        "seconds_per_call": dt, "amplitude_rounds_per_s": N * p / dt, "passes_per_call": passes,
+        "pass": {"kernel": "x_pass_kernel<float>", "avg_launch_ms": pass_ms / max(pass_cnt, 1),
+                 "GBps": pass_bytes / (pass_ms / reps * 1e-3) / 1e9,
+                 "frac_of_hbm_peak": pass_bytes / (pass_ms / reps * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "round_algorithmic_GBps": 17.0 * N * p / dt / 1e9,
+        "final_psol": float(psol[-1]), "max_norm_error": float(np.abs(norm - 1).max()),
+    }
+
+
+def rounds_leg(torch, g, inst):
+    """Rounds-to-target search (single angle pair, S = 50%) for 512
+    satisfiable instances, n in 12..20, d ~ U(2, 4.5), the pi/180 grid."""
+    from paper_2402_02585_amd import rounds
+    its = inst.batched_scan_instances(41, 512, 12, 20, density_range=(2.0, 4.5), dup="drop", workers=8)
+    ns = np.array([x.n for x in its])
+    ms = np.array([x.m for x in its])
+    H = g.gqaoa_hist_batched(ns, ms, [x.lits for x in its], hist_stride=int(ms.max()) + 1).cpu().numpy()
+    P = H[:, 0] / np.exp2(ns)
+    caps = np.clip(np.ceil(3.0 / np.sqrt(P)), 8, 100000).astype(np.int32)
+    rounds.single_pair_rounds(ns[:8], ms[:8], H[:8], 0.5, caps[:8])   # warm-up (autotuning)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p_star, _, _ = rounds.single_pair_rounds(ns, ms, H, 0.5, caps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = p_star > 0
+    b, _, c = rounds.sqrt_fit(P[ok], p_star[ok])
+    return {"workload": "512 satisfiable random 3-SAT (seed 41), n~U{12..20}, d~U(2,4.5), S=0.5, pi/180 grid, "
+                        "two zoom levels, cap 3/sqrt(P)",
+            "seconds": dt, "instances_per_s": len(its) / dt, "reached": int(ok.sum()),
+            "fit_slope_log_p_vs_log_inv_P": b, "median_p_sqrtP": c}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +274,8 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the cpu_baseline leg")
     ap.add_argument("--skip-batched", action="store_true", help="omit the batched-scan leg")
     ap.add_argument("--skip-adjoint", action="store_true", help="omit the adjoint-gradient leg")
+    ap.add_argument("--skip-x", action="store_true", help="omit the X-QAOA leg")
+    ap.add_argument("--skip-rounds", action="store_true", help="omit the rounds-to-target leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
@@ -296,6 +365,10 @@ def main():
         out["batched"] = batched_leg(torch, g, inst, max(3, args.steps // 2))
     if not args.skip_adjoint:
         out["adjoint"] = adjoint_leg(torch, g, inst)
+    if not args.skip_x:
+        out["xqaoa"] = xqaoa_leg(torch, g, inst, it)
+    if not args.skip_rounds:
+        out["rounds_to_target"] = rounds_leg(torch, g, inst)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -115,9 +115,10 @@ def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
     return ps.reshape(I).cpu().numpy().astype(np.float64)
 
 
-def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.2, 0.03), zoom: int = 16):
+def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.25, 0.06, 0.015), zoom: int = 16):
     """Best pair after one zoom x zoom window scan per width, each centred on the
-    previous best (one launch per width, all instances)."""
+    previous best (one launch per width, all instances). The peak narrows as p
+    grows, hence three shrinking windows."""
     I = len(ns)
     b = np.asarray(betas, dtype=np.float64).copy()
     gm = np.asarray(gammas, dtype=np.float64).copy()
