@@ -271,9 +271,10 @@ int gqaoa_draws_to_reject(int num_solutions, const double *q_host, int trials, u
                           void *stream);
 
 /* ---- instrumentation ---------------------------------------------------------
- * When enabled, the library brackets each launch of its streaming round
- * kernels with HIP events on the launch stream and accumulates their
- * durations under a name: "sv_round_c64", "sv_round_c128" (forward round
+ * gqaoa_profile_enable(k) with k >= 1 makes the library bracket one launch
+ * in k (counted per name, from the last reset) of its streaming kernels with
+ * HIP events on the launch stream and accumulate their durations under a
+ * name (k = 0 disables; k < 0 is EINVAL): "sv_round_c64", "sv_round_c128" (forward round
  * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table",
  * "scan", and "x_pass_c64", "x_pass_c128" (X-QAOA streaming passes).
  * Durations are collected when the call that launched them synchronizes.

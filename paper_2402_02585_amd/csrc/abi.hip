@@ -74,6 +74,7 @@ struct ProfPending {
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static int g_prof_every = 1;  // time one launch in this many, per name
 static std::vector<ProfPending> g_prof_pending;
 struct ProfTotal {
     double ms = 0.0;
@@ -82,11 +83,19 @@ struct ProfTotal {
 static const char *kProfNames[] = {"sv_round_c64", "sv_round_c128", "sv_reverse_c64", "sv_reverse_c128",
                                    "cost_table", "scan", "x_pass_c64", "x_pass_c128"};
 static ProfTotal g_prof_tot[sizeof(kProfNames) / sizeof(kProfNames[0])];
+static int64_t g_prof_seen[sizeof(kProfNames) / sizeof(kProfNames[0])];  // launches seen while enabled
 
 bool prof_on() { return g_prof_on; }
 
 ProfScope::ProfScope(const char *name, hipStream_t st) : name_(name), st_(st) {
     if (!g_prof_on) return;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        bool sample = true;
+        for (size_t i = 0; i < sizeof(kProfNames) / sizeof(kProfNames[0]); ++i)
+            if (!strcmp(kProfNames[i], name)) sample = (g_prof_seen[i]++ % g_prof_every) == 0;
+        if (!sample) return;
+    }
     if (hipEventCreate(&e0_) != hipSuccess) { e0_ = nullptr; return; }
     if (hipEventRecord(e0_, st_) != hipSuccess) { (void)hipEventDestroy(e0_); e0_ = nullptr; }
 }
@@ -486,7 +495,10 @@ int gqaoa_mlp_features(int batch, const uint64_t *hists_dev, int hist_stride, co
 }
 
 int gqaoa_profile_enable(int on) {
+    if (on < 0) return fail(GQAOA_EINVAL, "profile interval %d", on);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    g_prof_every = on > 0 ? on : 1;
     return GQAOA_OK;
 }
 
@@ -494,6 +506,7 @@ void gqaoa_profile_reset(void) {
     prof_collect();
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &t : g_prof_tot) t = ProfTotal{};
+    for (auto &c : g_prof_seen) c = 0;
 }
 
 int gqaoa_profile_read(const char *name, double *total_ms, int64_t *count) {

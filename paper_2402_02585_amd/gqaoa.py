@@ -416,8 +416,9 @@ def gqaoa_mlp_features(hists, ns, ms, ps, x=None, stream=None):
 
 
 # ---- instrumentation ------------------------------------------------------------------------
-def gqaoa_profile_enable(on: bool = True):
-    _check(load_library().gqaoa_profile_enable(int(bool(on))))
+def gqaoa_profile_enable(on=True, every: int = 1):
+    """Time one launch in ``every`` (per kernel name) while ``on``."""
+    _check(load_library().gqaoa_profile_enable(int(every) if on else 0))
 
 
 def gqaoa_profile_reset():

@@ -166,6 +166,13 @@ def test_mlp_argument_checks():
     assert lib.gqaoa_mlp_act_bytes(256) > 256 * 256 * 4
 
 
+def test_profile_interval_checks():
+    lib = g.load_library()
+    assert lib.gqaoa_profile_enable(-1) == -1
+    assert lib.gqaoa_profile_enable(3) == 0
+    assert lib.gqaoa_profile_enable(0) == 0
+
+
 def test_binding_fails_loudly_without_gpu():
     import torch
     if torch.cuda.is_available():

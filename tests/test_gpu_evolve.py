@@ -151,3 +151,21 @@ def test_fused_and_separate_finalize_agree(dt, monkeypatch):
         assert np.abs(a - b).max() < (1e-14 if dt == g.C128 else 1e-6)
     ref = evolve_sv(n, cost_table(n, lits), beta, gamma)
     _check(fused, ref, dt, m)
+
+
+def test_sampled_profiling_counts():
+    """gqaoa_profile_enable(k) times one round pass in k; the evolution itself
+    is unchanged by profiling."""
+    need_gpu()
+    n, m = 14, 59
+    cost, _ = g.gqaoa_cost_table(n, rand_lits(n, m, 5))
+    beta, gamma = inst.uniform_angles(6, 10)
+    ref = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=g.C64)[1]
+    g.gqaoa_profile_reset()
+    g.gqaoa_profile_enable(True, every=4)
+    got = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=g.C64)[1]
+    g.gqaoa_profile_enable(False)
+    ms, cnt = g.gqaoa_profile_read("sv_round_c64")
+    g.gqaoa_profile_reset()
+    assert cnt == 3 and ms > 0          # passes 0, 4, 8 of the 10
+    assert (got == ref).all()
