@@ -71,6 +71,19 @@ def read_traffic():
     return d.get("hbm_bytes_per_launch")
 
 
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_baseline():
     """The oracle's statevector evolution (complex128, numpy) on a bounded
     sample: one seed-2 instance at n = 22, m = 92, p = 64 rounds."""
@@ -326,10 +339,13 @@ def main():
     g.gqaoa_profile_enable(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
-        hist, psol = step()
+        hist, psol = step()   # ends with the host copy of the readouts (the stream is synchronized)
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    per_step = np.diff(np.array([t0] + marks)) * 1e3
     g.gqaoa_profile_enable(False)
     round_ms, round_cnt = g.gqaoa_profile_read("sv_round_c64")
     ct_ms, ct_cnt = g.gqaoa_profile_read("cost_table")
@@ -355,13 +371,16 @@ def main():
     out = {
         "metric": "amplitude-rounds/s (n=28,p=64) + batched instance-angle evals/s vs plain, same GPU",
         "value": value, "unit": "amplitude-rounds/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": ms_per_step, "ms_per_step_median": float(np.median(per_step)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64", "data": "synthetic",
         "config": {"workload": "G-QAOA statevector, one random 3-SAT instance n=28 m=118 (seed 2, first satisfiable "
                                "draw), complex64, p=64 independent per-round angles U[0,pi] (seed 2)",
                    "n": N_VARS, "m": M_CLAUSES, "p": P_ROUNDS, "amplitudes": N, "parallelism": "single GPU"},
         "roofline": roofline,
         "cost_table": cost_table,
+        "host": host_info(),
+        "gpu": {"name": torch.cuda.get_device_name(0),
+                "arch": getattr(torch.cuda.get_device_properties(0), "gcnArchName", "")},
     }
     del psi, ws
     torch.cuda.empty_cache()

@@ -137,6 +137,18 @@ struct SlicedCounter {
             c = t;
         }
     }
+    // Add the same value u (< 256) to every word bit's count, bit-sliced:
+    // plane b gets p_b ^ u_b ^ carry and the carry becomes maj(p_b, u_b, carry).
+    GQ_HD void add_scalar(uint32_t u) {
+        uint32_t c = 0;
+        for (int b = 0; b < 8; ++b) {
+            const uint32_t ub = ((u >> b) & 1u) ? 0xFFFFFFFFu : 0u;
+            uint32_t s, carry;
+            csa(carry, s, p[b], ub, c);
+            p[b] = s;
+            c = carry;
+        }
+    }
     // Transpose: afterwards p[r] byte q = count of word bit 8q + r.
     GQ_HD void transpose_to_bytes() {
         for (int b = 0; b < 4; ++b) {

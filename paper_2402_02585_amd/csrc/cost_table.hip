@@ -19,6 +19,7 @@
 #include "cost_bits.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -74,10 +75,11 @@ __device__ __forceinline__ uint32_t *hist_copy(CostLds &s) {
     return s.hist + ((threadIdx.x / kWave) * 4 + (threadIdx.x & 3)) * kHistStride;
 }
 
-// Costs of the 32 assignments of word tile*64 + lane (bytes: out[r] byte q is
-// C(32 w + 4 r + q)). Every lane of the wave must call this with the same tile.
-__device__ __forceinline__ void eval_tile(const ClauseRec *vec, int nvec, const UniformRec *uni, int nuni,
-                                          uint64_t tile, EffEntry (*eff)[2], uint32_t (&out)[8]) {
+// Costs of the 32 assignments of word w = tile*64 + lane as bit planes: bit j
+// of v[b] is bit b of C(z) for the assignment at word bit j. Every lane of the
+// wave must call this with the same tile.
+__device__ __forceinline__ void eval_planes(const ClauseRec *vec, int nvec, const UniformRec *uni, int nuni,
+                                            uint64_t tile, EffEntry (*eff)[2], uint32_t (&v)[8]) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t zwave = (tile * kWave) << kLowBits;   // z of lane 0, bit 0
     // 1) high-literal test of 64 clauses at a time, one per lane
@@ -109,12 +111,81 @@ __device__ __forceinline__ void eval_tile(const ClauseRec *vec, int nvec, const 
         }
         cnt.add16(f);
     }
-    cnt.transpose_to_bytes();
-    const uint32_t ub = u * 0x01010101u;  // no byte overflows: every count <= m <= 255
+    cnt.add_scalar(u);  // no overflow: every count <= m <= 255
 #pragma unroll
-    for (int r = 0; r < 8; ++r) out[r] = cnt.p[r] + ub;
+    for (int b = 0; b < 8; ++b) v[b] = cnt.p[b];
     // the next tile rewrites eff: every lane's reads of this one come first
     __builtin_amdgcn_wave_barrier();
+}
+
+// Planes to bytes: out[r] byte q = C of word bit 8q + r, i.e. C(32 w + 4 r + q).
+__device__ __forceinline__ void planes_to_bytes(const uint32_t (&v)[8], uint32_t (&out)[8]) {
+    SlicedCounter c;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) c.p[b] = v[b];
+    c.transpose_to_bytes();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) out[r] = c.p[r];
+}
+
+// Per-lane level counters for NB aligned blocks of 32 levels starting at
+// level 32 a0, fed straight from the bit planes: the assignments of a word at
+// level 32 a + k are the word bits where the planes spell a (planes 5..7) and
+// k (planes 0..4), found with a shared AND tree and counted with popcounts.
+// Levels outside the window are returned as a word-bit mask for the caller.
+template <int NB>
+struct LevelWindow {
+    uint32_t cnt[NB][32];
+    int a0;
+    __device__ __forceinline__ void clear(int a) {
+        a0 = a;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int k = 0; k < 32; ++k) cnt[i][k] = 0;
+    }
+    __device__ __forceinline__ uint32_t add(const uint32_t (&v)[8]) {
+        uint32_t in = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int a = a0 + i;  // uniform
+            const uint32_t hi = (v[5] ^ ((a & 1) ? 0u : ~0u)) & (v[6] ^ ((a & 2) ? 0u : ~0u)) &
+                                (v[7] ^ ((a & 4) ? 0u : ~0u));
+            in |= hi;
+#pragma unroll
+            for (int k43 = 0; k43 < 4; ++k43) {
+                const uint32_t t3 = hi & ((k43 & 2) ? v[4] : ~v[4]) & ((k43 & 1) ? v[3] : ~v[3]);
+#pragma unroll
+                for (int b2 = 0; b2 < 2; ++b2) {
+                    const uint32_t t2 = t3 & (b2 ? v[2] : ~v[2]);
+#pragma unroll
+                    for (int k10 = 0; k10 < 4; ++k10) {
+                        const uint32_t leaf = t2 & ((k10 & 2) ? v[1] : ~v[1]) & ((k10 & 1) ? v[0] : ~v[0]);
+                        cnt[i][(k43 << 3) | (b2 << 2) | k10] += (uint32_t)__builtin_popcount(leaf);
+                    }
+                }
+            }
+        }
+        return ~in;
+    }
+    // add the counters into an LDS histogram (levels < 256)
+    __device__ __forceinline__ void flush(uint32_t *h) const {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (cnt[i][k] && a0 + i < 8) atomicAdd(h + 32 * (a0 + i) + k, cnt[i][k]);
+    }
+};
+
+// Tally the word bits of `mask` one by one from the cost bytes (the rare
+// levels outside the window).
+__device__ __forceinline__ void tally_bits(uint32_t *h, const uint32_t (&t)[8], uint32_t mask) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((mask >> (8 * q + r)) & 1u) atomicAdd(h + ((t[r] >> (8 * q)) & 0xFFu), 1u);
 }
 
 __device__ __forceinline__ void tally(uint32_t *h, uint32_t v) {
@@ -133,10 +204,11 @@ __device__ __forceinline__ void tally_word(uint32_t *h, const uint32_t (&t)[8], 
     }
 }
 
+template <int NB>
 __global__ void __launch_bounds__(kCostThreads)
 cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec *__restrict__ uni,
                   int nuni, int n, uint8_t *__restrict__ cost, uint32_t *__restrict__ block_hist,
-                  int hist_len) {
+                  int hist_len, int win_a0) {
     extern __shared__ unsigned char smem[];
     CostLds lds(smem, nvec);
     stage(lds, vec, nvec);
@@ -147,22 +219,28 @@ cost_table_kernel(const ClauseRec *__restrict__ vec, int nvec, const UniformRec 
     const uint64_t ntiles = (nwords + kWave - 1) / kWave;
     const uint64_t nwaves = (uint64_t)gridDim.x * kCostWaves;
     const int lane = threadIdx.x & (kWave - 1);
+    LevelWindow<NB> win;
+    win.clear(win_a0);
     for (uint64_t tile = (uint64_t)blockIdx.x * kCostWaves + threadIdx.x / kWave; tile < ntiles; tile += nwaves) {
-        uint32_t t[8];
-        eval_tile(lds.rec, nvec, uni, nuni, tile, eff, t);
+        uint32_t v[8], t[8];
+        eval_planes(lds.rec, nvec, uni, nuni, tile, eff, v);
         const uint64_t w = tile * kWave + lane;
         if (w >= nwords) continue;
         if (n >= kLowBits) {
+            const uint32_t outside = win.add(v);
+            planes_to_bytes(v, t);
             typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
             u32x4 *dst = reinterpret_cast<u32x4 *>(cost + (w << kLowBits));
             dst[0] = u32x4{t[0], t[1], t[2], t[3]};
             dst[1] = u32x4{t[4], t[5], t[6], t[7]};
-            tally_word(h, t, 32u);
+            if (outside) tally_bits(h, t, outside);
         } else {
+            planes_to_bytes(v, t);
             for (uint32_t z = 0; z < (uint32_t)N; ++z) cost[z] = (uint8_t)((t[z >> 2] >> (8 * (z & 3))) & 0xFFu);
             tally_word(h, t, (uint32_t)N);
         }
     }
+    win.flush(h);
     __syncthreads();
     for (int k = threadIdx.x; k < hist_len; k += kCostThreads) {
         uint32_t s = 0;
@@ -197,7 +275,7 @@ __global__ void __launch_bounds__(256) hist_reduce_kernel(const uint32_t *__rest
 struct HistInst {
     uint32_t lit_off;   // first clause of the instance in the literal array
     int32_t n, m;
-    uint32_t pad;
+    int32_t win_a0;     // first 32-level block of the counting window
 };
 struct HistUnit {
     uint32_t inst, word0, nwords, pad;
@@ -222,13 +300,26 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t nbits = in.n >= kLowBits ? 32u : (1u << in.n);
     const uint32_t ntiles = (unit.nwords + kWave - 1) / kWave;
+    LevelWindow<2> win;
+    win.clear(in.win_a0);
     for (uint32_t t0 = threadIdx.x / kWave; t0 < ntiles; t0 += kCostWaves) {
         // word0 is a multiple of 64, so tile (word0 / 64 + t0) starts at word0 + 64 t0
         const uint64_t tile = (uint64_t)unit.word0 / kWave + t0;
-        uint32_t t[8];
-        eval_tile(lds.rec, nvec, nullptr, 0, tile, eff, t);
-        if (t0 * kWave + lane < unit.nwords) tally_word(h, t, nbits);
+        uint32_t v[8], t[8];
+        eval_planes(lds.rec, nvec, nullptr, 0, tile, eff, v);
+        if (t0 * kWave + lane >= unit.nwords) continue;
+        if (nbits == 32u) {
+            const uint32_t outside = win.add(v);
+            if (outside) {
+                planes_to_bytes(v, t);
+                tally_bits(h, t, outside);
+            }
+        } else {
+            planes_to_bytes(v, t);
+            tally_word(h, t, nbits);
+        }
     }
+    win.flush(h);
     __syncthreads();
     for (int k = threadIdx.x; k <= in.m; k += kCostThreads) {
         uint32_t s = 0;
@@ -238,6 +329,19 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
 }
 
 // ---- host launchers (arguments already validated) ---------------------------
+// Counting window for an instance with m clauses: C has mean m/8 over all
+// assignments (each clause is false on 1/8 of them) and, for random clauses,
+// a spread of about sqrt(7m/64); the window is the aligned 32-level blocks
+// covering mean +- 4 spreads, at most two. Levels outside it are still
+// counted exactly, one by one.
+static void level_window(int m, int *a0, int *nb) {
+    const double mu = m / 8.0, sd = std::sqrt(m * 7.0 / 64.0);
+    const int lo = std::max(0, (int)std::floor(mu - 4.0 * sd));
+    const int hi = std::min(m, (int)std::ceil(mu + 4.0 * sd));
+    *a0 = lo / 32;
+    *nb = std::min(2, hi / 32 - *a0 + 1);
+}
+
 int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist,
                       hipStream_t stream) {
     DeviceInfo dev;
@@ -263,9 +367,15 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     if (!uni.empty()) memcpy(staging.data() + sizeof(ClauseRec) * vec.size(), uni.data(), sizeof(UniformRec) * uni.size());
     GQ_HIP(hipMemcpyAsync(scratch, staging.data(), rec_bytes, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipStreamSynchronize(stream));  // staging is host pageable memory owned here
+    int a0 = 0, nb = 1;
+    level_window(m, &a0, &nb);
     ProfScope ps("cost_table", stream);
-    hipLaunchKernelGGL(cost_table_kernel, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes((int)vec.size()), stream,
-                       d_vec, (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len);
+    if (nb == 1)
+        hipLaunchKernelGGL(cost_table_kernel<1>, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes((int)vec.size()),
+                           stream, d_vec, (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len, a0);
+    else
+        hipLaunchKernelGGL(cost_table_kernel<2>, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes((int)vec.size()),
+                           stream, d_vec, (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len, a0);
     ps.end();
     GQ_LAUNCH_CHECK();
     if (hist) {
@@ -287,7 +397,9 @@ int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_ho
     for (int i = 0; i < num_inst; ++i) max_m = std::max(max_m, m_host[i]);
     const size_t smem_bytes = cost_lds_bytes((max_m + kGroup - 1) / kGroup * kGroup);
     for (int i = 0; i < num_inst; ++i) {
-        insts[i] = HistInst{(uint32_t)off, n_host[i], m_host[i], 0u};
+        int a0 = 0, nb = 1;
+        level_window(m_host[i], &a0, &nb);
+        insts[i] = HistInst{(uint32_t)off, n_host[i], m_host[i], a0};
         off += (size_t)m_host[i];
         const uint64_t nwords = n_host[i] >= kLowBits ? (1ull << (n_host[i] - kLowBits)) : 1;
         for (uint64_t w0 = 0; w0 < nwords; w0 += kUnitWords)
