@@ -294,7 +294,7 @@ def main():
                     help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is not implemented)",
+        print("bench.py runs on one GPU; --gpus must be 1 (multi-GPU sharding is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
