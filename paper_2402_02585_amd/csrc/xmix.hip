@@ -252,19 +252,27 @@ __device__ __forceinline__ void x_mix(XC<T> (&v)[1 << R], XC<T> *lds, const XPla
     }
 }
 
+// Readouts of one tile's register values: sums in the state precision within
+// the tile, float64 across tiles.
 template <typename T, int R>
 __device__ __forceinline__ void x_readout(const XC<T> (&v)[1 << R], const uint32_t (&cz)[1 << R], double &aP,
                                           double &aE, double &aN, int target) {
+    T sP = 0, sE = 0, sN = 0;
 #pragma unroll
     for (int i = 0; i < (1 << R); ++i) {
-        const double pr = (double)v[i].re * v[i].re + (double)v[i].im * v[i].im;
-        aN += pr;
-        aE += (double)cz[i] * pr;
-        aP += cz[i] == (uint32_t)target ? pr : 0.0;
+        const T pr = v[i].re * v[i].re + v[i].im * v[i].im;
+        sN += pr;
+        sE += (T)cz[i] * pr;
+        sP += cz[i] == (uint32_t)target ? pr : T(0);
     }
+    aP += (double)sP;
+    aE += (double)sE;
+    aN += (double)sN;
 }
 
-template <typename T>
+// OPS: the XOP_* flags of the pass, fixed at compile time so that a pass
+// that only mixes carries no readout, cost or phase state.
+template <typename T, int OPS>
 __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     constexpr int TB = XCfg<T>::TB, R = XCfg<T>::R, E = 1 << R;
     static_assert(TB - R == kXThreadBits, "one tile per block of 256 threads");
@@ -273,14 +281,14 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     __shared__ XC<T> lut_s[2][256];
     __shared__ double red_s[3 * kXThreads / kWave];
     for (int i = threadIdx.x; i < 256; i += kXThreads) {
-        if (a.ops & XOP_PRE) lut_s[0][i] = reinterpret_cast<const XC<T> *>(a.lut_a)[i];
-        if (a.ops & XOP_MID) lut_s[1][i] = reinterpret_cast<const XC<T> *>(a.lut_b)[i];
+        if constexpr ((OPS & XOP_PRE) != 0) lut_s[0][i] = reinterpret_cast<const XC<T> *>(a.lut_a)[i];
+        if constexpr ((OPS & XOP_MID) != 0) lut_s[1][i] = reinterpret_cast<const XC<T> *>(a.lut_b)[i];
     }
     __syncthreads();
     const int t = threadIdx.x;
     const int rb0 = TB - R;
     const T ca = (T)a.ca, sa = (T)a.sa, cb = (T)a.cb, sb = (T)a.sb;
-    const bool store = (a.ops & (XOP_MIX_A | XOP_MID)) != 0;
+    constexpr bool store = (OPS & (XOP_MIX_A | XOP_MID)) != 0;
     XC<T> *psi = reinterpret_cast<XC<T> *>(a.psi);
     const int lowbits = a.q0 - a.mlo;         // z bits mlo..q0-1 come from the tile index
     const int hishift = a.q0 + TB - a.mlo;    // z bits above the group
@@ -300,6 +308,28 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
         for (int i = 0; i < E; ++i) w[i] = x_load(src + zmap((uint32_t)i << rb0));
     };
     XC<T> v[E];
+    if constexpr (OPS == XOP_MIX_A) {
+        // Mixing only: light enough in registers to keep the next tile's
+        // loads in flight while this tile is mixed and stored.
+        XC<T> nxt[E];
+        uint64_t tile = blockIdx.x;
+        if (tile < a.ntiles) load_tile(tile, nxt);
+        for (; tile < a.ntiles; tile += gridDim.x) {
+#pragma unroll
+            for (int i = 0; i < E; ++i) v[i] = nxt[i];
+            if (tile + gridDim.x < a.ntiles) load_tile(tile + gridDim.x, nxt);
+            int rb = rb0;
+            x_mix<T, R>(v, lds, a.plan, true, rb, ca, sa);
+            if ((int)sizeof(XC<T>) << (rb < a.contig ? rb : a.contig) < 128) {
+                x_exchange<T, R>(v, lds, rb, rb0);
+                rb = rb0;
+            }
+            XC<T> *dst = psi + tile_base(tile) + zmap((uint32_t)x_elem(t, 0, rb, R));
+#pragma unroll
+            for (int i = 0; i < E; ++i) x_store(v[i], dst + zmap((uint32_t)i << rb));
+        }
+        return;
+    }
     for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
         XC<T> *tp = psi + tile_base(tile);
         const uint8_t *ct = a.cost + (tile << TB);
@@ -317,25 +347,25 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
             load_tile(tile, v);
         }
         int rb = rb0;
-        if (a.ops & XOP_PRE) {
+        if constexpr ((OPS & XOP_PRE) != 0) {
             load_cost(rb);
             x_readout<T, R>(v, cz, aP, aE, aN, a.target);
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = xmul(lut_s[0][cz[i]], v[i]);
         }
-        if (a.ops & XOP_MIX_A) x_mix<T, R>(v, lds, a.plan, true, rb, ca, sa);
-        if (a.ops & XOP_MID) {
+        if constexpr ((OPS & XOP_MIX_A) != 0) x_mix<T, R>(v, lds, a.plan, true, rb, ca, sa);
+        if constexpr ((OPS & XOP_MID) != 0) {
             load_cost(rb);
             x_readout<T, R>(v, cz, aP, aE, aN, a.target);
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = xmul(lut_s[1][cz[i]], v[i]);
             x_mix<T, R>(v, lds, a.plan, false, rb, cb, sb);
         }
-        if (a.ops & XOP_POST) {
+        if constexpr ((OPS & XOP_POST) != 0) {
             load_cost(rb);
             x_readout<T, R>(v, cz, aP, aE, aN, a.target);
         }
-        if (store) {
+        if constexpr (store) {
             // store from a layout whose lanes cover runs of >= 128 bytes
             if ((int)sizeof(XC<T>) << (rb < a.contig ? rb : a.contig) < 128) {
                 x_exchange<T, R>(v, lds, rb, rb0);
@@ -346,7 +376,7 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
             for (int i = 0; i < E; ++i) x_store(v[i], dst + zmap((uint32_t)i << rb));
         }
     }
-    if (a.ops & (XOP_PRE | XOP_MID | XOP_POST)) {
+    if constexpr ((OPS & (XOP_PRE | XOP_MID | XOP_POST)) != 0) {
         double r[3] = {aP, aE, aN};
         block_sum<3, kXThreads>(r, red_s);
         if (threadIdx.x == 0)
@@ -415,6 +445,35 @@ static XLayout x_layout(void *ws, int n, int p, int dtype) {
 }
 
 size_t x_workspace_bytes(int n, int p, int dtype) { return x_layout(nullptr, n, p, dtype).bytes; }
+
+template <typename T>
+static int launch_pass(int ops, int blocks, size_t smem, hipStream_t st, const XPassArgs &a) {
+    switch (ops) {
+        case XOP_MIX_A:
+            hipLaunchKernelGGL((x_pass_kernel<T, XOP_MIX_A>), dim3(blocks), dim3(kXThreads), smem, st, a);
+            break;
+        case XOP_PRE | XOP_MIX_A:
+            hipLaunchKernelGGL((x_pass_kernel<T, XOP_PRE | XOP_MIX_A>), dim3(blocks), dim3(kXThreads), smem, st, a);
+            break;
+        case XOP_MIX_A | XOP_MID:
+            hipLaunchKernelGGL((x_pass_kernel<T, XOP_MIX_A | XOP_MID>), dim3(blocks), dim3(kXThreads), smem, st, a);
+            break;
+        case XOP_MIX_A | XOP_POST:
+            hipLaunchKernelGGL((x_pass_kernel<T, XOP_MIX_A | XOP_POST>), dim3(blocks), dim3(kXThreads), smem, st, a);
+            break;
+        case XOP_POST:
+            hipLaunchKernelGGL((x_pass_kernel<T, XOP_POST>), dim3(blocks), dim3(kXThreads), smem, st, a);
+            break;
+        case XOP_PRE | XOP_MIX_A | XOP_POST:
+            hipLaunchKernelGGL((x_pass_kernel<T, XOP_PRE | XOP_MIX_A | XOP_POST>), dim3(blocks), dim3(kXThreads), smem,
+                               st, a);
+            break;
+        default:
+            return fail(GQAOA_EINVAL, "internal: X pass operations %d", ops);
+    }
+    GQ_LAUNCH_CHECK();
+    return GQAOA_OK;
+}
 
 // One group of qubits for the streaming passes (n > T).
 struct XGroup {
@@ -570,12 +629,10 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
             }
             a.partials = L.part;
             ProfScope ps(prof, st);
-            if (dtype == GQAOA_C64)
-                hipLaunchKernelGGL(x_pass_kernel<float>, dim3(blocks), dim3(kXThreads), smem, st, a);
-            else
-                hipLaunchKernelGGL(x_pass_kernel<double>, dim3(blocks), dim3(kXThreads), smem, st, a);
+            const int rc = dtype == GQAOA_C64 ? launch_pass<float>(ops, blocks, smem, st, a)
+                                              : launch_pass<double>(ops, blocks, smem, st, a);
             ps.end();
-            GQ_LAUNCH_CHECK();
+            if (rc) return rc;
             return readout_j >= 0 ? finalize(blocks, 3, 0, readout_j) : GQAOA_OK;
         };
         if (p == 0) {
