@@ -35,6 +35,36 @@ def test_cost_table_deterministic_and_two_level():
     assert h1.cpu().tolist()[:2] == [2 ** 12, 2 ** 15 - 2 ** 12]
 
 
+def _all_positive(n):
+    """Every clause (x_a or x_b or x_c) with a < b < c: z = 0 falsifies all of
+    them, so the costs reach far beyond m/8 (the levels are counted outside
+    the kernels' counting window, one by one)."""
+    import itertools
+    return np.array([[2 * a, 2 * b, 2 * c] for a, b, c in itertools.combinations(range(n), 3)], dtype=np.int32)
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_cost_table_levels_far_from_the_mean(n):
+    need_gpu()
+    lits = _all_positive(n)
+    m = lits.shape[0]
+    cost, hist = g.gqaoa_cost_table(n, lits)
+    ref = cost_table(n, lits)
+    assert ref.max() == m
+    np.testing.assert_array_equal(cost.cpu().numpy(), ref.astype(np.uint8))
+    np.testing.assert_array_equal(hist.cpu().numpy(), level_histogram(ref, m))
+
+
+def test_hist_batched_levels_far_from_the_mean():
+    need_gpu()
+    lits = [_all_positive(n) for n in (8, 9, 12)]
+    ns, ms = [8, 9, 12], [l.shape[0] for l in lits]
+    hists = g.gqaoa_hist_batched(ns, ms, lits, hist_stride=max(ms) + 1).cpu().numpy()
+    for i, n in enumerate(ns):
+        ref = level_histogram(cost_table(n, lits[i]), ms[i])
+        np.testing.assert_array_equal(hists[i, :ms[i] + 1], ref)
+
+
 def test_hist_batched_matches_oracle():
     need_gpu()
     insts = inst.batched_scan_instances(3, 24, 4, 14, sat_only=False)
