@@ -125,11 +125,13 @@ def batched_leg(torch, g, inst, steps: int):
         g.gqaoa_scan_batched(ns, ms, hists, grid, grid, plist, out=out)
     torch.cuda.synchronize()
     t_scan = (time.perf_counter() - t0) / steps
-    # histogram step of the batched path (all 4096 instances)
+    # histogram step of the batched path (all 4096 instances; the clauses as one
+    # host array, uploaded and ingested on the device by every call)
+    flat_lits = np.concatenate([np.asarray(it.lits, dtype=np.int32).reshape(-1) for it in insts])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=stride)
+        g.gqaoa_hist_batched(ns, ms, flat_lits, hist_stride=stride)
     torch.cuda.synchronize()
     t_hist = (time.perf_counter() - t0) / steps
     psol = out[0].cpu().numpy()

@@ -133,12 +133,19 @@ def gqaoa_cost_table(n: int, lits, with_hist: bool = True, cost=None, stream=Non
 
 
 def gqaoa_hist_batched(ns, ms, lits_list, hist_stride: int | None = None, stream=None):
-    """Level histograms of many instances: int64 device tensor [I, hist_stride]."""
+    """Level histograms of many instances: int64 device tensor [I, hist_stride].
+    lits_list: one literal array per instance, or all of them already
+    concatenated in instance order (an int32 array of sum(ms) * 3 literals)."""
     torch = _torch()
     lib = load_library()
     ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
     ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
-    flat = np.ascontiguousarray(np.concatenate([_lits(l) for l in lits_list]))
+    if isinstance(lits_list, np.ndarray):
+        flat = _lits(lits_list)
+    else:
+        flat = np.ascontiguousarray(np.concatenate([_lits(l) for l in lits_list]))
+    if flat.size != 3 * int(ms.astype(np.int64).sum()):
+        raise ValueError(f"{flat.size} literals for {int(ms.sum())} clauses")
     stride = int(hist_stride or (int(ms.max()) + 1))
     hists = torch.empty((len(ns), stride), dtype=torch.int64, device="cuda")
     _check(lib.gqaoa_hist_batched(len(ns), _np_ptr(ns), _np_ptr(ms), _np_ptr(flat), _ptr(hists), stride,

@@ -75,6 +75,9 @@ def test_hist_batched_matches_oracle():
         ref = level_histogram(cost_table(it.n, it.lits), it.m)
         np.testing.assert_array_equal(hists[i, :it.m + 1], ref)
         assert not hists[i, it.m + 1:].any()
+    flat = np.concatenate([np.asarray(it.lits, dtype=np.int32).reshape(-1) for it in insts])
+    again = g.gqaoa_hist_batched(ns, ms, flat, hist_stride=80).cpu().numpy()
+    np.testing.assert_array_equal(again, hists)
 
 
 def test_full_size_n28_histogram_and_sampled_costs():
