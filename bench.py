@@ -39,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_EVERY = 8
+PROFILE_EVERY = 7   # coprime with the 64 rounds of a step: the sampled launches cover every round index
 N_VARS, M_CLAUSES, P_ROUNDS = 28, 118, 64
 
 
@@ -337,7 +337,8 @@ def main():
     torch.cuda.synchronize()
     g.gqaoa_profile_reset()
     # HIP events bracket one round pass in PROFILE_EVERY (an event pair around
-    # every pass would add ~1% to the step)
+    # every pass would add ~1% to the step); the bytes of exactly the sampled
+    # launches are counted below
     g.gqaoa_profile_enable(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -358,9 +359,12 @@ def main():
     # roofline of the round pass: algorithmic bytes = 16 B of state + 1 B of cost
     # per amplitude, except round 1, which starts from |s> and reads no state
     avg_round_ms = round_ms / max(round_cnt, 1)
-    bytes_per_step = N * (9 + (P_ROUNDS - 1) * 17)
-    bytes_per_launch = bytes_per_step / P_ROUNDS
-    achieved = bytes_per_launch / (avg_round_ms * 1e-3) / 1e9
+    sampled = range(0, args.steps * P_ROUNDS, PROFILE_EVERY)   # launch L is round (L mod 64) + 1 of its step
+    if len(sampled) != round_cnt:
+        raise RuntimeError(f"expected {len(sampled)} timed round passes, the library recorded {round_cnt}")
+    sampled_bytes = N * sum(9 if L % P_ROUNDS == 0 else 17 for L in sampled)
+    bytes_per_launch = sampled_bytes / max(round_cnt, 1)
+    achieved = sampled_bytes / (round_ms * 1e-3) / 1e9
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
