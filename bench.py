@@ -157,6 +157,31 @@ def batched_leg(torch, g, inst, steps: int):
         ps, _, _ = g.gqaoa_hist_evolve(it.n, it.m, hdev[i], np.full(64, grid[bi]), np.full(64, grid[gi]))
         max_dev = max(max_dev, max(abs(ps[p] - psol[i, q, gi, bi]) for q, p in enumerate(plist)))
     t_h = (time.perf_counter() - t0) / len(cells_h)
+    # statevector work items on a seeded subset: every instance with n <= 14
+    # (its state fits one block's LDS), 16 random grid cells and the 4 cells
+    # where the scan's P_sol peaks (one per p), all in one call
+    small = [i for i, it in enumerate(insts) if it.n <= 14]
+    s_ns = [insts[i].n for i in small]
+    s_ms = [insts[i].m for i in small]
+    s_costs, _, _ = g.gqaoa_cost_batched(s_ns, s_ms, [insts[i].lits for i in small], with_hist=False)
+    item_inst, item_cells = [], []   # cells: (instance, gamma index, beta index) of the scan output
+    for k, i in enumerate(small):
+        peaks = [np.unravel_index(int(np.argmax(psol[i, q])), psol[i, q].shape) for q in range(len(plist))]
+        rnd = [(int(rng.integers(0, 64)), int(rng.integers(0, 64))) for _ in range(16)]
+        for gi, bi in rnd + [(int(a), int(b)) for a, b in peaks]:
+            item_inst.append(k)
+            item_cells.append((i, gi, bi))
+    item_b = [grid[bi] for _, _, bi in item_cells]
+    item_g = [grid[gi] for _, gi, _ in item_cells]
+    g.gqaoa_sv_items(s_ns, s_ms, s_costs, item_inst[:64], item_b[:64], item_g[:64], plist)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv_ps, _ = g.gqaoa_sv_items(s_ns, s_ms, s_costs, item_inst, item_b, item_g, plist)
+    torch.cuda.synchronize()
+    t_items = time.perf_counter() - t0
+    sv_ps = sv_ps.cpu().numpy()
+    scan_at = np.stack([psol[i, :, gi, bi] for i, gi, bi in item_cells])
+    items_dev = float(np.abs(sv_ps - scan_at).max())
     rate = evals / t_scan
     plain_sv = len(plist) / t_sv
     plain_h = len(plist) / t_h
@@ -172,6 +197,12 @@ def batched_leg(torch, g, inst, steps: int):
         "speedup_vs_plain_statevector": rate / plain_sv,
         "speedup_vs_plain_level_space": rate / plain_h,
         "max_abs_psol_diff_vs_plain": max_dev,
+        "statevector_items": {"items": len(item_inst), "instances": len(small), "seconds": t_items,
+                              "instance_angle_evals_per_s": len(item_inst) * len(plist) / t_items,
+                              "speedup_vs_plain_statevector": len(item_inst) * len(plist) / t_items / plain_sv,
+                              "max_abs_psol_diff_vs_scan": items_dev,
+                              "kind": "gqaoa_sv_items: complex64 state in LDS, one block per (instance, angle pair), "
+                                      "n <= 14, 16 random cells + the 4 scan peaks per instance"},
     }
 
 

@@ -80,6 +80,18 @@ int gqaoa_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_hos
                        const int32_t *lits_host, uint64_t *hists_dev, int hist_stride,
                        void *stream);
 
+/* Cost tables of many instances in one launch (as gqaoa_hist_batched, with
+ * n_i in [3, 26]): instance i's table C_i(z), z < 2^n_i, is written to
+ * costs_dev + gqaoa_cost_batched_offset(i, n_host), the tables following
+ * each other in instance order, each starting at a multiple of 64 bytes
+ * (the buffer needs gqaoa_cost_batched_offset(num_inst, n_host) bytes).
+ * hists_dev may be NULL; otherwise it receives the histograms as in
+ * gqaoa_hist_batched. Errors as gqaoa_hist_batched. */
+uint64_t gqaoa_cost_batched_offset(int index, const int32_t *n_host);
+int gqaoa_cost_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                       const int32_t *lits_host, uint8_t *costs_dev, uint64_t *hists_dev,
+                       int hist_stride, void *stream);
+
 /* ---- statevector evolution, Eq. (3) ---------------------------------------
  * For j = 1..p applies exp(-i gamma_j H_P) (phase exp(-i gamma_j C(z)) on z),
  * then exp(-i beta_j H_M) with H_M = |s><s| a projector (Eq. (2)), i.e.
@@ -204,6 +216,26 @@ int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_ho
                         int per_instance_grid, int p_max, const int32_t *p_max_host,
                         float threshold, int32_t *first_p_dev,
                         const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Statevector work items of the batched scan (the check of the level-space
+ * reduction amplitude by amplitude): item k runs the single-angle-pair
+ * protocol of Eq. (5) with (beta_host[k], gamma_host[k]) on instance
+ * item_inst_host[k], whose cost table is in costs_dev at
+ * gqaoa_cost_batched_offset(item_inst_host[k], n_host) (the layout written by
+ * gqaoa_cost_batched), from |s>, complex64 state held in LDS, for
+ * p_list[num_p-1] rounds, recording after each p in p_list (ascending)
+ *   psol_dev  [k*num_p + q] = P_sol at target_host[inst] (NULL: level 0),
+ *   energy_dev[k*num_p + q] = E of Eq. (4) (NULL to skip), both float.
+ * Item instances need n <= GQAOA_SV_ITEMS_MAX_N and an LDS allocation of
+ * 9 * 2^n + 2048 bytes per block on the device (ERANGE otherwise).
+ * Synchronizes the stream. Errors: EINVAL (NULL pointers, non-finite angles,
+ * p_list not ascending), ERANGE (counts, n, m, targets, p values). */
+#define GQAOA_SV_ITEMS_MAX_N 14
+int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                   const int32_t *target_host, const uint8_t *costs_dev, int num_items,
+                   const int32_t *item_inst_host, const double *beta_host,
+                   const double *gamma_host, int num_p, const int32_t *p_list_host,
+                   float *psol_dev, float *energy_dev, void *stream);
 
 /* ---- angle-predictor MLP (bfloat16 MFMA, float32 accumulation) -------------
  * The paper suggests deriving angles from statistics of the density of

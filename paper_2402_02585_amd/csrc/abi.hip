@@ -13,8 +13,9 @@ namespace gqaoa {
 
 // launchers (cost_table.hip, sv.hip, hist.hip, mlp.hip)
 int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist, hipStream_t st);
+uint64_t batched_cost_offset(int i, const int32_t *n_host);
 int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits,
-                        uint64_t *hists, int hist_stride, hipStream_t st);
+                        uint64_t *hists, int hist_stride, uint8_t *costs, hipStream_t st);
 size_t sv_workspace_bytes(int num_inst, int n, int p, int dtype, int ckpt_every, bool grad);
 int run_evolve(int n, int m, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
                int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
@@ -33,6 +34,9 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
              int num_p, const int32_t *p_list, float *psol, float *energy, float threshold, int32_t *first_p,
              const int32_t *pmax_host, const int32_t *tile, void *ws, hipStream_t st);
 size_t x_workspace_bytes(int n, int p, int dtype);
+int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *target_host,
+                 const uint8_t *costs, int num_items, const int32_t *item_inst, const double *beta,
+                 const double *gamma, int num_p, const int32_t *p_list, float *psol, float *energy, hipStream_t st);
 int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const double *gamma, int dtype,
                  int init_uniform, void *psi, int target, double *psol, double *energy, double *norm, void *ws,
                  hipStream_t st);
@@ -145,6 +149,7 @@ int device_info(DeviceInfo *out) {
     DeviceInfo d;
     d.device = dev;
     d.num_cus = prop.multiProcessorCount;
+    d.lds_per_block = prop.sharedMemPerBlock;
     strncpy(d.arch, prop.gcnArchName, sizeof(d.arch) - 1);
     if (strncmp(d.arch, "gfx950", 6) != 0)
         return fail(GQAOA_ENODEV, "device %d is %s; this library is built for gfx950", dev, d.arch);
@@ -205,22 +210,47 @@ int gqaoa_cost_table(int n, int m, const int32_t *lits_host, uint8_t *cost_dev, 
     return launch_cost_table(n, m, lits_host, cost_dev, hist_dev, (hipStream_t)stream);
 }
 
-int gqaoa_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits_host,
-                       uint64_t *hists_dev, int hist_stride, void *stream) {
-    clear_error();
+static int check_batched_instances(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                                   const int32_t *lits_host, int hist_stride, int max_n) {
     if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d outside [1, 2^20]", num_inst);
-    if (!n_host || !m_host || !lits_host || !hists_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    if (!n_host || !m_host || !lits_host) return fail(GQAOA_EINVAL, "NULL argument");
     if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
     size_t off = 0;
     for (int i = 0; i < num_inst; ++i) {
-        if (n_host[i] < GQAOA_MIN_N || n_host[i] > 30) return fail(GQAOA_ERANGE, "instance %d: n=%d outside [3, 30]", i, n_host[i]);
+        if (n_host[i] < GQAOA_MIN_N || n_host[i] > max_n)
+            return fail(GQAOA_ERANGE, "instance %d: n=%d outside [3, %d]", i, n_host[i], max_n);
         if (m_host[i] < 1 || m_host[i] > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "instance %d: m=%d", i, m_host[i]);
         if (m_host[i] + 1 > hist_stride) return fail(GQAOA_ERANGE, "instance %d: m+1=%d > hist_stride", i, m_host[i] + 1);
         int s = check_clauses(n_host[i], m_host[i], lits_host + 3 * off, i);
         if (s) return s;
         off += (size_t)m_host[i];
     }
-    return launch_hist_batched(num_inst, n_host, m_host, lits_host, hists_dev, hist_stride, (hipStream_t)stream);
+    return GQAOA_OK;
+}
+
+int gqaoa_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits_host,
+                       uint64_t *hists_dev, int hist_stride, void *stream) {
+    clear_error();
+    int s = check_batched_instances(num_inst, n_host, m_host, lits_host, hist_stride, 30);
+    if (s) return s;
+    if (!hists_dev) return fail(GQAOA_EINVAL, "NULL hists_dev");
+    return launch_hist_batched(num_inst, n_host, m_host, lits_host, hists_dev, hist_stride, nullptr,
+                               (hipStream_t)stream);
+}
+
+uint64_t gqaoa_cost_batched_offset(int index, const int32_t *n_host) {
+    if (index < 0 || !n_host) return 0;
+    return batched_cost_offset(index, n_host);
+}
+
+int gqaoa_cost_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits_host,
+                       uint8_t *costs_dev, uint64_t *hists_dev, int hist_stride, void *stream) {
+    clear_error();
+    int s = check_batched_instances(num_inst, n_host, m_host, lits_host, hist_stride, 26);
+    if (s) return s;
+    if (!costs_dev) return fail(GQAOA_EINVAL, "NULL costs_dev");
+    return launch_hist_batched(num_inst, n_host, m_host, lits_host, hists_dev, hist_stride, costs_dev,
+                               (hipStream_t)stream);
 }
 
 size_t gqaoa_workspace_bytes(int n, int p, int dtype, int ckpt_every) {
@@ -444,6 +474,36 @@ int gqaoa_draws_to_reject(int num_solutions, const double *q_host, int trials, u
     if (!(tot > 0.0)) return fail(GQAOA_EINVAL, "solution probabilities sum to %g", tot);
     return run_draws_to_reject(num_solutions, q_host, trials, seed, crit, n_min, max_draws, draws_dev,
                                (hipStream_t)stream);
+}
+
+int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *target_host,
+                   const uint8_t *costs_dev, int num_items, const int32_t *item_inst_host, const double *beta_host,
+                   const double *gamma_host, int num_p, const int32_t *p_list_host, float *psol_dev,
+                   float *energy_dev, void *stream) {
+    clear_error();
+    if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d", num_inst);
+    if (num_items < 1 || num_items > (1 << 24)) return fail(GQAOA_ERANGE, "num_items=%d", num_items);
+    if (num_p < 1 || num_p > 16) return fail(GQAOA_ERANGE, "num_p=%d outside [1, 16]", num_p);
+    if (!n_host || !m_host || !costs_dev || !item_inst_host || !beta_host || !gamma_host || !p_list_host || !psol_dev)
+        return fail(GQAOA_EINVAL, "NULL argument");
+    for (int q = 0; q < num_p; ++q) {
+        if (p_list_host[q] < 1 || p_list_host[q] > kMaxP) return fail(GQAOA_ERANGE, "p_list[%d]=%d", q, p_list_host[q]);
+        if (q && p_list_host[q] <= p_list_host[q - 1]) return fail(GQAOA_EINVAL, "p_list is not ascending");
+    }
+    for (int i = 0; i < num_inst; ++i) {
+        if (n_host[i] < GQAOA_MIN_N || n_host[i] > 26) return fail(GQAOA_ERANGE, "instance %d: n=%d", i, n_host[i]);
+        if (m_host[i] < 1 || m_host[i] > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "instance %d: m=%d", i, m_host[i]);
+        const int t = target_host ? target_host[i] : 0;
+        if (t < 0 || t > m_host[i]) return fail(GQAOA_ERANGE, "instance %d: target_level=%d", i, t);
+    }
+    for (int k = 0; k < num_items; ++k) {
+        const int i = item_inst_host[k];
+        if (i < 0 || i >= num_inst) return fail(GQAOA_ERANGE, "item %d: instance %d", k, i);
+        if (n_host[i] > GQAOA_SV_ITEMS_MAX_N) return fail(GQAOA_ERANGE, "item %d: n=%d > %d", k, n_host[i], GQAOA_SV_ITEMS_MAX_N);
+        if (!std::isfinite(beta_host[k]) || !std::isfinite(gamma_host[k])) return fail(GQAOA_EINVAL, "item %d: angles", k);
+    }
+    return run_sv_items(num_inst, n_host, m_host, target_host, costs_dev, num_items, item_inst_host, beta_host,
+                        gamma_host, num_p, p_list_host, psol_dev, energy_dev, (hipStream_t)stream);
 }
 
 size_t gqaoa_mlp_act_bytes(int batch) {

@@ -276,6 +276,7 @@ struct HistInst {
     uint32_t lit_off;   // first clause of the instance in the literal array
     int32_t n, m;
     int32_t win_a0;     // first 32-level block of the counting window
+    uint64_t cost_off;  // byte offset of the instance's cost table (when costs are written)
 };
 struct HistUnit {
     uint32_t inst, word0, nwords, pad;
@@ -283,7 +284,8 @@ struct HistUnit {
 
 __global__ void __launch_bounds__(kCostThreads)
 hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restrict__ units,
-                    const int32_t *__restrict__ lits, unsigned long long *__restrict__ hists, int hist_stride) {
+                    const int32_t *__restrict__ lits, unsigned long long *__restrict__ hists, int hist_stride,
+                    uint8_t *__restrict__ costs) {
     extern __shared__ unsigned char smem[];
     const HistUnit unit = units[blockIdx.x];
     const HistInst in = insts[unit.inst];
@@ -310,13 +312,21 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
         if (t0 * kWave + lane >= unit.nwords) continue;
         if (nbits == 32u) {
             const uint32_t outside = win.add(v);
-            if (outside) {
-                planes_to_bytes(v, t);
-                tally_bits(h, t, outside);
+            if (outside || costs) planes_to_bytes(v, t);
+            if (outside) tally_bits(h, t, outside);
+            if (costs) {
+                typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+                const uint64_t w = (uint64_t)unit.word0 + t0 * kWave + lane;
+                u32x4 *dst = reinterpret_cast<u32x4 *>(costs + in.cost_off + (w << kLowBits));
+                dst[0] = u32x4{t[0], t[1], t[2], t[3]};
+                dst[1] = u32x4{t[4], t[5], t[6], t[7]};
             }
         } else {
             planes_to_bytes(v, t);
             tally_word(h, t, nbits);
+            if (costs)
+                for (uint32_t z = 0; z < nbits; ++z)
+                    costs[in.cost_off + z] = (uint8_t)((t[z >> 2] >> (8 * (z & 3))) & 0xFFu);
         }
     }
     win.flush(h);
@@ -324,7 +334,7 @@ hist_batched_kernel(const HistInst *__restrict__ insts, const HistUnit *__restri
     for (int k = threadIdx.x; k <= in.m; k += kCostThreads) {
         uint32_t s = 0;
         for (int c = 0; c < kHistCopies; ++c) s += lds.hist[c * kHistStride + k];
-        if (s) atomicAdd(hists + (size_t)unit.inst * hist_stride + k, (unsigned long long)s);
+        if (s && hists) atomicAdd(hists + (size_t)unit.inst * hist_stride + k, (unsigned long long)s);
     }
 }
 
@@ -387,8 +397,17 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     return GQAOA_OK;
 }
 
+// Byte offset of each instance's cost table in the concatenated output: the
+// tables follow each other in instance order, each starting at a multiple of
+// 64 bytes.
+uint64_t batched_cost_offset(int i, const int32_t *n_host) {
+    uint64_t off = 0;
+    for (int j = 0; j < i; ++j) off += ((1ull << n_host[j]) + 63) & ~63ull;
+    return off;
+}
+
 int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
-                        const int32_t *lits, uint64_t *hists, int hist_stride, hipStream_t stream) {
+                        const int32_t *lits, uint64_t *hists, int hist_stride, uint8_t *costs, hipStream_t stream) {
     std::vector<HistInst> insts(num_inst);
     std::vector<HistUnit> units;
     constexpr uint32_t kUnitWords = kCostThreads * 4;
@@ -396,10 +415,12 @@ int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_ho
     int max_m = 1;
     for (int i = 0; i < num_inst; ++i) max_m = std::max(max_m, m_host[i]);
     const size_t smem_bytes = cost_lds_bytes((max_m + kGroup - 1) / kGroup * kGroup);
+    uint64_t cost_off = 0;
     for (int i = 0; i < num_inst; ++i) {
         int a0 = 0, nb = 1;
         level_window(m_host[i], &a0, &nb);
-        insts[i] = HistInst{(uint32_t)off, n_host[i], m_host[i], a0};
+        insts[i] = HistInst{(uint32_t)off, n_host[i], m_host[i], a0, cost_off};
+        cost_off += ((1ull << n_host[i]) + 63) & ~63ull;
         off += (size_t)m_host[i];
         const uint64_t nwords = n_host[i] >= kLowBits ? (1ull << (n_host[i] - kLowBits)) : 1;
         for (uint64_t w0 = 0; w0 < nwords; w0 += kUnitWords)
@@ -417,11 +438,11 @@ int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_ho
     GQ_HIP(hipMemcpyAsync(base, insts.data(), b_inst, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipMemcpyAsync(base + o_unit, units.data(), b_unit, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipMemcpyAsync(base + o_lits, lits, b_lits, hipMemcpyHostToDevice, stream));
-    GQ_HIP(hipMemsetAsync(hists, 0, sizeof(uint64_t) * (size_t)num_inst * hist_stride, stream));
+    if (hists) GQ_HIP(hipMemsetAsync(hists, 0, sizeof(uint64_t) * (size_t)num_inst * hist_stride, stream));
     hipLaunchKernelGGL(hist_batched_kernel, dim3((unsigned)units.size()), dim3(kCostThreads), smem_bytes, stream,
                        reinterpret_cast<const HistInst *>(base), reinterpret_cast<const HistUnit *>(base + o_unit),
                        reinterpret_cast<const int32_t *>(base + o_lits),
-                       reinterpret_cast<unsigned long long *>(hists), hist_stride);
+                       reinterpret_cast<unsigned long long *>(hists), hist_stride, costs);
     GQ_LAUNCH_CHECK();
     GQ_HIP(hipFreeAsync(scratch, stream));
     GQ_HIP(hipStreamSynchronize(stream));  // the host tables above end with this call

@@ -50,6 +50,7 @@ void prof_collect();  // after a stream synchronize: fold finished pairs into to
 struct DeviceInfo {
     int device = -1;
     int num_cus = 0;
+    size_t lds_per_block = 0;  // largest LDS allocation one block may use
     char arch[64] = {0};
 };
 int device_info(DeviceInfo *out);

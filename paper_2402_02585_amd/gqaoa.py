@@ -31,6 +31,9 @@ _SIGS = {
     "gqaoa_abi_version": ([], _i32),
     "gqaoa_cost_table": ([_i32, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_hist_batched": ([_i32, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
+    "gqaoa_cost_batched_offset": ([_i32, _vp], _c.c_uint64),
+    "gqaoa_cost_batched": ([_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
+    "gqaoa_sv_items": ([_i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_workspace_bytes": ([_i32, _i32, _i32, _i32], _sz),
     "gqaoa_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_solution_prob": ([_i32, _vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp], _i32),
@@ -140,17 +143,66 @@ def gqaoa_hist_batched(ns, ms, lits_list, hist_stride: int | None = None, stream
     lib = load_library()
     ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
     ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
-    if isinstance(lits_list, np.ndarray):
-        flat = _lits(lits_list)
-    else:
-        flat = np.ascontiguousarray(np.concatenate([_lits(l) for l in lits_list]))
-    if flat.size != 3 * int(ms.astype(np.int64).sum()):
-        raise ValueError(f"{flat.size} literals for {int(ms.sum())} clauses")
+    flat = _flat_lits(lits_list, ms)
     stride = int(hist_stride or (int(ms.max()) + 1))
     hists = torch.empty((len(ns), stride), dtype=torch.int64, device="cuda")
     _check(lib.gqaoa_hist_batched(len(ns), _np_ptr(ns), _np_ptr(ms), _np_ptr(flat), _ptr(hists), stride,
                                   _stream(torch, stream)))
     return hists
+
+
+def _flat_lits(lits_list, ms):
+    if isinstance(lits_list, np.ndarray):
+        flat = _lits(lits_list)
+    else:
+        flat = np.ascontiguousarray(np.concatenate([_lits(l) for l in lits_list]))
+    if flat.size != 3 * int(np.asarray(ms, dtype=np.int64).sum()):
+        raise ValueError(f"{flat.size} literals for {int(np.sum(ms))} clauses")
+    return flat
+
+
+def gqaoa_cost_batched(ns, ms, lits_list, with_hist: bool = True, hist_stride: int | None = None, stream=None):
+    """Cost tables of many instances (n <= 26) in one launch.
+
+    Returns (costs uint8 device tensor, offsets int64 numpy array [I + 1],
+    hists int64 device tensor [I, stride] or None); instance i's table is
+    costs[offsets[i] : offsets[i] + 2^n_i]."""
+    torch = _torch()
+    lib = load_library()
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    flat = _flat_lits(lits_list, ms)
+    offsets = np.array([lib.gqaoa_cost_batched_offset(i, _np_ptr(ns)) for i in range(len(ns) + 1)], dtype=np.int64)
+    costs = torch.empty(max(int(offsets[-1]), 1), dtype=torch.uint8, device="cuda")
+    stride = int(hist_stride or (int(ms.max()) + 1))
+    hists = torch.empty((len(ns), stride), dtype=torch.int64, device="cuda") if with_hist else None
+    _check(lib.gqaoa_cost_batched(len(ns), _np_ptr(ns), _np_ptr(ms), _np_ptr(flat), _ptr(costs), _ptr(hists), stride,
+                                  _stream(torch, stream)))
+    return costs, offsets, hists
+
+
+def gqaoa_sv_items(ns, ms, costs, item_inst, betas, gammas, p_list, targets=None, with_energy: bool = False,
+                   stream=None):
+    """Statevector single-pair items on costs from gqaoa_cost_batched.
+    Returns (psol, energy) float32 device tensors [num_items, num_p] (energy None
+    unless requested)."""
+    torch = _torch()
+    lib = load_library()
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    ii = np.ascontiguousarray(np.asarray(item_inst, dtype=np.int32).ravel())
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).ravel())
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).ravel())
+    if not (ii.size == b.size == g.size):
+        raise ValueError("item_inst, betas and gammas must have one entry per item")
+    pl = np.ascontiguousarray(np.asarray(p_list, dtype=np.int32))
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    psol = torch.empty((ii.size, pl.size), dtype=torch.float32, device="cuda")
+    energy = torch.empty((ii.size, pl.size), dtype=torch.float32, device="cuda") if with_energy else None
+    _check(lib.gqaoa_sv_items(len(ns), _np_ptr(ns), _np_ptr(ms), _np_ptr(tg), _ptr(costs), ii.size, _np_ptr(ii),
+                              _np_ptr(b), _np_ptr(g), pl.size, _np_ptr(pl), _ptr(psol), _ptr(energy),
+                              _stream(torch, stream)))
+    return psol, energy
 
 
 # ---- statevector ----------------------------------------------------------------------

@@ -166,6 +166,30 @@ def test_mlp_argument_checks():
     assert lib.gqaoa_mlp_act_bytes(256) > 256 * 256 * 4
 
 
+def test_batched_cost_and_items_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    ns = np.array([10, 15], dtype=np.int32)
+    ms = np.array([5, 5], dtype=np.int32)
+    lits = np.tile(np.array([0, 2, 4], dtype=np.int32), 10)
+    big = np.array([27], dtype=np.int32)
+    assert lib.gqaoa_cost_batched(1, g._np_ptr(big), g._np_ptr(ms), g._np_ptr(lits), d, None, 6, None) == -2
+    assert lib.gqaoa_cost_batched(2, g._np_ptr(ns), g._np_ptr(ms), g._np_ptr(lits), None, None, 6, None) == -1
+    assert lib.gqaoa_cost_batched_offset(2, g._np_ptr(ns)) == 1024 + 32768
+    b = np.zeros(2)
+    pl = np.array([1, 4], dtype=np.int32)
+    items = np.array([0, 1], dtype=np.int32)     # instance 1 has n = 15 > 14
+    assert lib.gqaoa_sv_items(2, g._np_ptr(ns), g._np_ptr(ms), None, d, 2, g._np_ptr(items), g._np_ptr(b),
+                              g._np_ptr(b), 2, g._np_ptr(pl), d, None, None) == -2
+    items = np.array([0, 2], dtype=np.int32)     # no instance 2
+    assert lib.gqaoa_sv_items(2, g._np_ptr(ns), g._np_ptr(ms), None, d, 2, g._np_ptr(items), g._np_ptr(b),
+                              g._np_ptr(b), 2, g._np_ptr(pl), d, None, None) == -2
+    items = np.array([0, 0], dtype=np.int32)
+    bad = np.array([4, 1], dtype=np.int32)
+    assert lib.gqaoa_sv_items(2, g._np_ptr(ns), g._np_ptr(ms), None, d, 2, g._np_ptr(items), g._np_ptr(b),
+                              g._np_ptr(b), 2, g._np_ptr(bad), d, None, None) == -1
+
+
 def test_profile_interval_checks():
     lib = g.load_library()
     assert lib.gqaoa_profile_enable(-1) == -1
