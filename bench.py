@@ -39,6 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # published; counts packed two-wide FMAs
 PROFILE_EVERY = 7   # coprime with the 64 rounds of a step: the sampled launches cover every round index
 N_VARS, M_CLAUSES, P_ROUNDS = 28, 118, 64
 
@@ -183,10 +184,19 @@ def batched_leg(torch, g, inst, steps: int):
     scan_at = np.stack([psol[i, :, gi, bi] for i, gi, bi in item_cells])
     items_dev = float(np.abs(sv_ps - scan_at).max())
     rate = evals / t_scan
+    # the scan's arithmetic: per occupied level, round and angle pair a complex
+    # phase multiply (6 flops), the weighted sum for the mixer (4) and the
+    # mixer update (2)
+    levels = (hists > 0).sum(axis=1).astype(np.float64)
+    scan_flops = float(levels.sum()) * 64 * 64 * plist[-1] * 12
     plain_sv = len(plist) / t_sv
     plain_h = len(plist) / t_h
     return {
         "metric": "instance-angle evals/s", "value": rate, "ms_per_scan": t_scan * 1e3,
+        "roofline": {"bound": "alu", "kernel": "scan_kernel", "achieved": scan_flops / t_scan / 1e12,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": scan_flops / t_scan / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                     "flops_per_scan": scan_flops, "mean_levels": float(levels.mean())},
         "workload": "4096 satisfiable random 3-SAT, n~U{8..20}, d in {3.0,4.2,5.0}, beta,gamma=linspace(0,pi,64), "
                     "p in {1,4,16,64}, float32",
         "hist_batched_ms": t_hist * 1e3,
