@@ -366,8 +366,9 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     const int hist_len = m + 1;
     const size_t rec_bytes = sizeof(ClauseRec) * vec.size() + sizeof(UniformRec) * (uni.size() + 1);
     const size_t bh_bytes = sizeof(uint32_t) * (size_t)nblocks * hist_len;
-    void *scratch = nullptr;
-    GQ_HIP(hipMallocAsync(&scratch, rec_bytes + bh_bytes + 256, stream));
+    AsyncScratch guard(stream);
+    GQ_HIP(guard.alloc(rec_bytes + bh_bytes + 256));
+    void *scratch = guard.ptr;
     ClauseRec *d_vec = reinterpret_cast<ClauseRec *>(scratch);
     UniformRec *d_uni = reinterpret_cast<UniformRec *>(d_vec + vec.size());
     uint32_t *d_bh = reinterpret_cast<uint32_t *>(
@@ -393,7 +394,6 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
                            reinterpret_cast<unsigned long long *>(hist));
         GQ_LAUNCH_CHECK();
     }
-    GQ_HIP(hipFreeAsync(scratch, stream));
     return GQAOA_OK;
 }
 
@@ -432,8 +432,9 @@ int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_ho
     const size_t b_unit = sizeof(HistUnit) * units.size();
     const size_t b_lits = sizeof(int32_t) * 3 * off;
     const size_t o_unit = al(b_inst), o_lits = o_unit + al(b_unit);
-    void *scratch = nullptr;
-    GQ_HIP(hipMallocAsync(&scratch, o_lits + al(b_lits), stream));
+    AsyncScratch guard(stream);
+    GQ_HIP(guard.alloc(o_lits + al(b_lits)));
+    void *scratch = guard.ptr;
     char *base = reinterpret_cast<char *>(scratch);
     GQ_HIP(hipMemcpyAsync(base, insts.data(), b_inst, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipMemcpyAsync(base + o_unit, units.data(), b_unit, hipMemcpyHostToDevice, stream));
@@ -444,7 +445,6 @@ int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_ho
                        reinterpret_cast<const int32_t *>(base + o_lits),
                        reinterpret_cast<unsigned long long *>(hists), hist_stride, costs);
     GQ_LAUNCH_CHECK();
-    GQ_HIP(hipFreeAsync(scratch, stream));
     GQ_HIP(hipStreamSynchronize(stream));  // the host tables above end with this call
     return GQAOA_OK;
 }

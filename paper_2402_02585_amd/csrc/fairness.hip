@@ -104,12 +104,12 @@ int run_shots_to_all(int K, const double *p, int runs, uint64_t seed, int max_sh
     int s = device_info(&dev);
     if (s) return s;
     const std::vector<double> c = running_cdf(K, p, false);
-    double *d_c = nullptr;
-    GQ_HIP(hipMallocAsync((void **)&d_c, sizeof(double) * K, st));
+    AsyncScratch guard(st);
+    GQ_HIP(guard.alloc(sizeof(double) * K));
+    double *d_c = reinterpret_cast<double *>(guard.ptr);
     GQ_HIP(hipMemcpyAsync(d_c, c.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(shots_all_kernel, dim3((runs + 255) / 256), dim3(256), 0, st, d_c, K, runs, seed, max_shots, out);
     GQ_LAUNCH_CHECK();
-    GQ_HIP(hipFreeAsync(d_c, st));
     GQ_HIP(hipStreamSynchronize(st));  // the host cdf ends here
     return GQAOA_OK;
 }
@@ -120,14 +120,14 @@ int run_draws_to_reject(int K, const double *q, int trials, uint64_t seed, doubl
     int s = device_info(&dev);
     if (s) return s;
     const std::vector<double> c = running_cdf(K, q, true);
-    double *d_c = nullptr;
-    GQ_HIP(hipMallocAsync((void **)&d_c, sizeof(double) * K, st));
+    AsyncScratch guard(st);
+    GQ_HIP(guard.alloc(sizeof(double) * K));
+    double *d_c = reinterpret_cast<double *>(guard.ptr);
     GQ_HIP(hipMemcpyAsync(d_c, c.data(), sizeof(double) * K, hipMemcpyHostToDevice, st));
     const int waves_per_block = 4;
     hipLaunchKernelGGL(reject_kernel, dim3((trials + waves_per_block - 1) / waves_per_block), dim3(waves_per_block * kWave),
                        0, st, d_c, K, trials, seed, crit, n_min, max_draws, out);
     GQ_LAUNCH_CHECK();
-    GQ_HIP(hipFreeAsync(d_c, st));
     GQ_HIP(hipStreamSynchronize(st));
     return GQAOA_OK;
 }

@@ -135,9 +135,9 @@ int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *bet
     }
     const size_t rb = sizeof(HistRound) * rounds.size();
     const size_t ob = sizeof(double) * 3 * (size_t)(p + 1);
-    void *scratch = nullptr;
-    GQ_HIP(hipMallocAsync(&scratch, rb + ob + 256, st));
-    char *base = reinterpret_cast<char *>(scratch);
+    AsyncScratch guard(st);
+    GQ_HIP(guard.alloc(rb + ob + 256));
+    char *base = reinterpret_cast<char *>(guard.ptr);
     double *d_out = reinterpret_cast<double *>(base + ((rb + 255) & ~size_t(255)));
     GQ_HIP(hipMemcpyAsync(base, rounds.data(), rb, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(hist_evolve_kernel, dim3(1), dim3(64), 0, st,
@@ -146,7 +146,6 @@ int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *bet
     GQ_LAUNCH_CHECK();
     std::vector<double> o((size_t)3 * (p + 1));
     GQ_HIP(hipMemcpyAsync(o.data(), d_out, ob, hipMemcpyDeviceToHost, st));
-    GQ_HIP(hipFreeAsync(scratch, st));
     GQ_HIP(hipStreamSynchronize(st));
     for (int j = 0; j <= p; ++j) {
         if (psol) psol[j] = o[3 * j];

@@ -46,6 +46,20 @@ struct ProfScope {
 };
 void prof_collect();  // after a stream synchronize: fold finished pairs into totals
 
+// Stream-ordered scratch owned by one call: freed (stream-ordered) on every
+// return path, after the work enqueued on the stream before the free.
+struct AsyncScratch {
+    void *ptr = nullptr;
+    hipStream_t st;
+    explicit AsyncScratch(hipStream_t s) : st(s) {}
+    AsyncScratch(const AsyncScratch &) = delete;
+    AsyncScratch &operator=(const AsyncScratch &) = delete;
+    hipError_t alloc(size_t bytes) { return hipMallocAsync(&ptr, bytes, st); }
+    ~AsyncScratch() {
+        if (ptr) (void)hipFreeAsync(ptr, st);
+    }
+};
+
 // Device properties the launch shapes depend on (cached per device).
 struct DeviceInfo {
     int device = -1;

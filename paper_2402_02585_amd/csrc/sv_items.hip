@@ -152,9 +152,9 @@ int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, con
     }
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
     const size_t b_items = sizeof(SvItem) * items.size(), b_off = 8 * (size_t)num_inst, b_i = 4 * (size_t)num_inst;
-    void *scratch = nullptr;
-    GQ_HIP(hipMallocAsync(&scratch, al(b_items) + al(b_off) + 2 * al(b_i), st));
-    char *base = reinterpret_cast<char *>(scratch);
+    AsyncScratch guard(st);
+    GQ_HIP(guard.alloc(al(b_items) + al(b_off) + 2 * al(b_i)));
+    char *base = reinterpret_cast<char *>(guard.ptr);
     SvItem *d_items = reinterpret_cast<SvItem *>(base);
     uint64_t *d_off = reinterpret_cast<uint64_t *>(base + al(b_items));
     int32_t *d_m = reinterpret_cast<int32_t *>(base + al(b_items) + al(b_off));
@@ -189,7 +189,6 @@ int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, con
         GQ_LAUNCH_CHECK();
         k0 = k1;
     }
-    GQ_HIP(hipFreeAsync(scratch, st));
     GQ_HIP(hipStreamSynchronize(st));  // the host tables above end with this call
     return GQAOA_OK;
 }
