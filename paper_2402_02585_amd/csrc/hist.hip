@@ -366,21 +366,25 @@ static int launch_bucket(int bucket, const TileChoice &tc, const DeviceInfo &dev
 
 static int tune_bucket(int bucket, const DeviceInfo &dev, const ScanArgs &a, unsigned int *counter,
                        hipStream_t st, TileChoice *out) {
-    const std::string key = std::string(dev.arch) + ":k" + std::to_string(kBuckets[bucket]) + ":t" +
-                            std::to_string(a.ntiles) + ":p" + std::to_string(a.p_list[a.num_p - 1] > 16 ? 64 : 16) +
-                            (a.first_p ? ":x" : "");
+    const std::string plain_key = std::string(dev.arch) + ":k" + std::to_string(kBuckets[bucket]) + ":t" +
+                                  std::to_string(a.ntiles) + ":p" +
+                                  std::to_string(a.p_list[a.num_p - 1] > 16 ? 64 : 16);
+    const std::string key = plain_key + (a.first_p ? ":x" : "");
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
+        if (it == g_tune.end() && a.first_p) it = g_tune.find(plain_key);  // same loop, plus a readout
         if (it != g_tune.end()) {
             *out = it->second;
             return GQAOA_OK;
         }
     }
-    // time a prefix of the queue that fills the device a few times over
+    // time a prefix of the queue that fills the device a few times over; the
+    // crossing form's items can run thousands of rounds, so its prefix is a
+    // single fill of the device
     ScanArgs t = a;
-    t.total_items = std::min<unsigned>(a.total_items, (unsigned)dev.num_cus * 64);
+    t.total_items = std::min<unsigned>(a.total_items, (unsigned)dev.num_cus * (a.first_p ? 8 : 64));
     const int waves_c[] = {1, 2, 4};
     const int bpc_c[] = {2, 4, 8, 16};
     hipEvent_t e0, e1;

@@ -5,8 +5,9 @@ Workload (defaults, the paper's sizes): for every n in [10, 26], ``per_n``
 (100; 50 for n >= 23) satisfiable instances with d ~ U(2, 4.5) and as many
 unsatisfiable ones with d ~ U(4.6, 8) (seeded, duplicate clauses dropped as
 in the paper, m = round(n d)). Angle grid: pi/180 spacing over the
-fundamental domain for n <= 20, a regular 90 x 45 grid (4050 pairs, in place
-of the paper's 4000 sampled pairs) beyond. Targets: level 0 for the satisfiable set (probability P = N_0 /
+fundamental domain for every n (the paper samples 4000 pairs beyond n = 20
+for its energy optimization; for the first-crossing search a 90 x 45 grid
+there leaves a third of the instances unreached, all of them at n > 20). Targets: level 0 for the satisfiable set (probability P = N_0 /
 2^n), the Max-SAT level k_min for the unsatisfiable set (D = N_kmin / 2^n).
 
 Reported:
@@ -71,7 +72,9 @@ def main(argv=None):
     ap.add_argument("--full", type=int, default=12, help="instances of the full G-QAOA subsample")
     ap.add_argument("--full-n-max", type=int, default=14)
     ap.add_argument("--grid", type=int, nargs=2, default=[360, 181], help="grid for n <= 20")
-    ap.add_argument("--grid-large", type=int, nargs=2, default=[90, 45], help="grid for n > 20")
+    ap.add_argument("--grid-large", type=int, nargs=2, default=[360, 181],
+                    help="grid for n > 20 (the paper samples 4000 pairs there; a coarse grid misses the narrow "
+                         "region of angles that reach S at large n)")
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -141,6 +144,10 @@ def main(argv=None):
                             per_n[str(n)] = {"median_p": float(np.median(p_star[mk])),
                                              "median_inv_sqrtP": float(np.median(1 / np.sqrt(P[sel][mk])))}
                     rec["per_n"] = per_n
+            if S == 0.5:
+                # per instance: n, m, d, P (or D), rounds (0: not reached within the cap), cap
+                rec["records"] = [[int(ns[i]), int(ms[i]), round(float(ds[i]), 4), float(P[i]), int(p_star[k]),
+                                   int(cap_s[k])] for k, i in enumerate(sel)]
             entry["per_S"][str(S)] = rec
             log(f"{kind} S={S}: {rec.get('reached')}/{rec['instances']} reached, slope "
                 f"{rec.get('fit_slope_log_p_vs_log_inv_P', float('nan')):.3f}, c {rec.get('median_p_sqrtP', float('nan')):.3f}, "
