@@ -125,7 +125,22 @@ def batched_leg(torch, g, inst, steps: int):
     for _ in range(steps):
         g.gqaoa_scan_batched(ns, ms, hists, grid, grid, plist, out=out)
     torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / steps
+    # the same scan as a captured graph: level tables resident, each step
+    # uploads the grid and replays one graph
+    t0 = time.perf_counter()
+    plan = g.ScanPlan(ns, ms, hists, grid, grid, plist)
+    torch.cuda.synchronize()
+    t_plan_create = time.perf_counter() - t0
+    plan.run(grid, grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(grid, grid)
+    torch.cuda.synchronize()
     t_scan = (time.perf_counter() - t0) / steps
+    graph_equal = bool(torch.equal(plan.psol, out[0]) and torch.equal(plan.energy, out[1]))
+    plan.close()
     # histogram step of the batched path (all 4096 instances; the clauses as one
     # host array, uploaded and ingested on the device by every call)
     flat_lits = np.concatenate([np.asarray(it.lits, dtype=np.int32).reshape(-1) for it in insts])
@@ -164,7 +179,7 @@ def batched_leg(torch, g, inst, steps: int):
     small = [i for i, it in enumerate(insts) if it.n <= 14]
     s_ns = [insts[i].n for i in small]
     s_ms = [insts[i].m for i in small]
-    s_costs, _, _ = g.gqaoa_cost_batched(s_ns, s_ms, [insts[i].lits for i in small], with_hist=False)
+    s_costs, s_offsets, _ = g.gqaoa_cost_batched(s_ns, s_ms, [insts[i].lits for i in small], with_hist=False)
     item_inst, item_cells = [], []   # cells: (instance, gamma index, beta index) of the scan output
     for k, i in enumerate(small):
         peaks = [np.unravel_index(int(np.argmax(psol[i, q])), psol[i, q].shape) for q in range(len(plist))]
@@ -183,6 +198,21 @@ def batched_leg(torch, g, inst, steps: int):
     sv_ps = sv_ps.cpu().numpy()
     scan_at = np.stack([psol[i, :, gi, bi] for i, gi, bi in item_cells])
     items_dev = float(np.abs(sv_ps - scan_at).max())
+    # both paths in one graph: the scan on one branch, the items (on the
+    # scan's own grid cells) on a parallel one
+    cost_off = np.zeros(len(insts), dtype=np.uint64)
+    cost_off[small] = s_offsets[:-1]
+    both = g.ScanPlan(ns, ms, hists, grid, grid, plist, items=np.array(item_cells, dtype=np.int32), costs=s_costs,
+                      cost_off=cost_off)
+    both.run(grid, grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        both.run(grid, grid)
+    torch.cuda.synchronize()
+    t_both = (time.perf_counter() - t0) / 2
+    both_equal = bool(torch.equal(both.psol, out[0]) and np.array_equal(both.item_psol.cpu().numpy(), sv_ps))
+    both.close()
     rate = evals / t_scan
     # the scan's arithmetic: per occupied level, round and angle pair a complex
     # phase multiply (6 flops), the weighted sum for the mixer (4) and the
@@ -193,6 +223,9 @@ def batched_leg(torch, g, inst, steps: int):
     plain_h = len(plist) / t_h
     return {
         "metric": "instance-angle evals/s", "value": rate, "ms_per_scan": t_scan * 1e3,
+        "timed": "graph replays of gqaoa_scan_plan (grid upload + one hipGraphLaunch per scan)",
+        "ms_per_scan_eager_call": t_eager * 1e3, "plan_create_s": t_plan_create,
+        "graph_equals_eager": graph_equal,
         "roofline": {"bound": "alu", "kernel": "scan_kernel", "achieved": scan_flops / t_scan / 1e12,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": scan_flops / t_scan / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
@@ -211,6 +244,7 @@ def batched_leg(torch, g, inst, steps: int):
                               "instance_angle_evals_per_s": len(item_inst) * len(plist) / t_items,
                               "speedup_vs_plain_statevector": len(item_inst) * len(plist) / t_items / plain_sv,
                               "max_abs_psol_diff_vs_scan": items_dev,
+                              "graph_scan_plus_items_ms": t_both * 1e3, "graph_equals_eager": both_equal,
                               "kind": "gqaoa_sv_items: complex64 state in LDS, one block per (instance, angle pair), "
                                       "n <= 14, 16 random cells + the 4 scan peaks per instance"},
     }

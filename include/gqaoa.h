@@ -237,6 +237,59 @@ int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host,
                    const double *gamma_host, int num_p, const int32_t *p_list_host,
                    float *psol_dev, float *energy_dev, void *stream);
 
+/* ---- graph-captured scan plan ----------------------------------------------
+ * The scan of gqaoa_scan_batched (Eq. (5) in the level space of App. C) for
+ * callers that evaluate the same instances over many angle grids (grid
+ * refinement, local searches around optimized angles), with optional
+ * statevector work items on cells of the same grid (the amplitude-by-amplitude
+ * check of gqaoa_sv_items).
+ *
+ * gqaoa_scan_plan_create does the per-instance work once: it compacts and
+ * uploads the occupied levels, chooses every bucket's launch shape (tile as in
+ * gqaoa_scan_batched), and captures all launches in one HIP graph, the scan on
+ * one branch and the items on a parallel one. Arguments num_inst ... tile are
+ * those of gqaoa_scan_batched (no workspace: the plan allocates its device
+ * tables and a pinned staging block, freed by gqaoa_scan_plan_destroy);
+ * betas_host/gammas_host give the first grid. psol_dev/energy_dev (layout of
+ * gqaoa_scan_batched) must stay valid while the plan lives.
+ * Items (num_items in [0, 2^24]; 0 = none, and then the item arguments may be
+ * NULL): items_host[3k..3k+2] = (instance i, gamma index g, beta index b);
+ * item k runs the single-angle-pair protocol with the grid's (beta_b,
+ * gamma_g) of instance i (its own row when per_instance_grid) on the cost
+ * table at costs_dev + cost_off_host[i] (uint8[2^n_i], e.g. written by
+ * gqaoa_cost_batched), and writes item_psol_dev[k*num_p + q] (and
+ * item_energy_dev, NULL to skip) after each p_list[q], the float values of
+ * the scan's cell (i, q, g, b) computed without the level reduction. Item
+ * instances need n <= GQAOA_SV_ITEMS_MAX_N and the LDS of gqaoa_sv_items.
+ * Synchronizes the stream. Errors: those of gqaoa_scan_batched and
+ * gqaoa_sv_items, EINVAL for a NULL plan_out or an item cell outside the
+ * grid, EHIP if the graph cannot be captured.
+ *
+ * gqaoa_scan_plan_run uploads a new grid (same sizes as at creation;
+ * betas_host and gammas_host both NULL: keep the current one) and replays the
+ * graph on `stream`. It does not synchronize: the outputs are complete when
+ * the stream reaches the end of the replay. A run waits (on the device) for
+ * the plan's previous replay, from any stream, and (on the host) for the
+ * previous upload to have read the staging block. A plan is used from one
+ * host thread at a time, on the device current at its creation.
+ * Errors: EINVAL (NULL plan, one of the two grids NULL, non-finite angles,
+ * another device current).
+ *
+ * gqaoa_scan_plan_destroy waits for the plan's last replay and frees it
+ * (NULL is a no-op). */
+typedef struct gqaoa_scan_plan gqaoa_scan_plan;
+int gqaoa_scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                           const uint64_t *hists_host, int hist_stride, const int32_t *target_host,
+                           int nb, const double *betas_host, int ng, const double *gammas_host,
+                           int per_instance_grid, int num_p, const int32_t *p_list_host,
+                           float *psol_dev, float *energy_dev, const int32_t *tile,
+                           int num_items, const int32_t *items_host, const uint8_t *costs_dev,
+                           const uint64_t *cost_off_host, float *item_psol_dev,
+                           float *item_energy_dev, void *stream, gqaoa_scan_plan **plan_out);
+int gqaoa_scan_plan_run(gqaoa_scan_plan *plan, const double *betas_host,
+                        const double *gammas_host, void *stream);
+void gqaoa_scan_plan_destroy(gqaoa_scan_plan *plan);
+
 /* ---- angle-predictor MLP (bfloat16 MFMA, float32 accumulation) -------------
  * The paper suggests deriving angles from statistics of the density of
  * states (Sec. V) and reports clustering of optimized pairs (Sec. III.B).

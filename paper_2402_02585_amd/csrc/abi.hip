@@ -34,6 +34,15 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
              int num_p, const int32_t *p_list, float *psol, float *energy, float threshold, int32_t *first_p,
              const int32_t *pmax_host, const int32_t *tile, void *ws, hipStream_t st);
 size_t x_workspace_bytes(int n, int p, int dtype);
+struct ScanPlan;
+int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
+                     int hist_stride, const int32_t *target_host, int nb, const double *betas, int ng,
+                     const double *gammas, int per_inst, int num_p, const int32_t *p_list, float *psol,
+                     float *energy, const int32_t *tile, int num_items, const int32_t *items,
+                     const uint8_t *costs, const uint64_t *cost_off, float *item_psol, float *item_energy,
+                     hipStream_t st, ScanPlan **out);
+int scan_plan_run(ScanPlan *P, const double *betas, const double *gammas, hipStream_t st);
+void scan_plan_destroy(ScanPlan *P);
 int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *target_host,
                  const uint8_t *costs, int num_items, const int32_t *item_inst, const double *beta,
                  const double *gamma, int num_p, const int32_t *p_list, float *psol, float *energy, hipStream_t st);
@@ -370,13 +379,12 @@ size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng,
 // Checks shared by the two scan entry points (everything but the outputs).
 static int check_scan_args(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
                            int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
-                           const double *gammas_host, int num_p, const int32_t *p_list_host, const int32_t *tile,
-                           const void *ws_dev) {
+                           const double *gammas_host, int num_p, const int32_t *p_list_host, const int32_t *tile) {
     if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d", num_inst);
     if (nb < 1 || nb > 4096 || ng < 1 || ng > 4096) return fail(GQAOA_ERANGE, "grid %d x %d outside [1, 4096]^2", nb, ng);
     if (num_p < 1 || num_p > 16) return fail(GQAOA_ERANGE, "num_p=%d outside [1, 16]", num_p);
     if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
-    if (!n_host || !m_host || !hists_host || !betas_host || !gammas_host || !p_list_host || !ws_dev)
+    if (!n_host || !m_host || !hists_host || !betas_host || !gammas_host || !p_list_host)
         return fail(GQAOA_EINVAL, "NULL argument");
     for (int q = 0; q < num_p; ++q) {
         if (p_list_host[q] < 1 || p_list_host[q] > kMaxP) return fail(GQAOA_ERANGE, "p_list[%d]=%d", q, p_list_host[q]);
@@ -406,9 +414,9 @@ int gqaoa_scan_batched(int num_inst, const int32_t *n_host, const int32_t *m_hos
                        float *energy_dev, const int32_t *tile, void *ws_dev, size_t ws_bytes, void *stream) {
     clear_error();
     int s = check_scan_args(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng,
-                            gammas_host, num_p, p_list_host, tile, ws_dev);
+                            gammas_host, num_p, p_list_host, tile);
     if (s) return s;
-    if (!psol_dev) return fail(GQAOA_EINVAL, "NULL psol_dev");
+    if (!psol_dev || !ws_dev) return fail(GQAOA_EINVAL, "NULL argument");
     const int pig = per_instance_grid ? 1 : 0;
     const size_t need = scan_workspace_bytes(num_inst, hist_stride, nb, ng, num_p, pig);
     if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
@@ -425,8 +433,9 @@ int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_ho
     clear_error();
     const int32_t pl[1] = {p_max};
     int s = check_scan_args(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng,
-                            gammas_host, 1, pl, tile, ws_dev);
+                            gammas_host, 1, pl, tile);
     if (s) return s;
+    if (!ws_dev) return fail(GQAOA_EINVAL, "NULL ws_dev");
     if (p_max_host)
         for (int i = 0; i < num_inst; ++i)
             if (p_max_host[i] < 1 || p_max_host[i] > p_max)
@@ -505,6 +514,57 @@ int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, c
     return run_sv_items(num_inst, n_host, m_host, target_host, costs_dev, num_items, item_inst_host, beta_host,
                         gamma_host, num_p, p_list_host, psol_dev, energy_dev, (hipStream_t)stream);
 }
+
+static bool all_finite(const double *v, size_t n) {
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(v[k])) return false;
+    return true;
+}
+
+int gqaoa_scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
+                           int hist_stride, const int32_t *target_host, int nb, const double *betas_host, int ng,
+                           const double *gammas_host, int per_instance_grid, int num_p, const int32_t *p_list_host,
+                           float *psol_dev, float *energy_dev, const int32_t *tile, int num_items,
+                           const int32_t *items_host, const uint8_t *costs_dev, const uint64_t *cost_off_host,
+                           float *item_psol_dev, float *item_energy_dev, void *stream, gqaoa_scan_plan **plan_out) {
+    clear_error();
+    if (!plan_out) return fail(GQAOA_EINVAL, "NULL plan_out");
+    *plan_out = nullptr;
+    int s = check_scan_args(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng,
+                            gammas_host, num_p, p_list_host, tile);
+    if (s) return s;
+    if (!psol_dev) return fail(GQAOA_EINVAL, "NULL psol_dev");
+    const int pig = per_instance_grid ? 1 : 0;
+    const size_t ga = pig ? (size_t)num_inst : 1;
+    if (!all_finite(betas_host, (size_t)nb * ga) || !all_finite(gammas_host, (size_t)ng * ga))
+        return fail(GQAOA_EINVAL, "non-finite angle in the grid");
+    if (num_items < 0 || num_items > (1 << 24)) return fail(GQAOA_ERANGE, "num_items=%d", num_items);
+    if (num_items) {
+        if (!items_host || !costs_dev || !cost_off_host || !item_psol_dev) return fail(GQAOA_EINVAL, "NULL item argument");
+        for (int k = 0; k < num_items; ++k) {
+            const int i = items_host[3 * k], g = items_host[3 * k + 1], b = items_host[3 * k + 2];
+            if (i < 0 || i >= num_inst) return fail(GQAOA_ERANGE, "item %d: instance %d", k, i);
+            if (g < 0 || g >= ng || b < 0 || b >= nb) return fail(GQAOA_EINVAL, "item %d: cell (%d, %d) outside the grid", k, g, b);
+            if (n_host[i] > GQAOA_SV_ITEMS_MAX_N) return fail(GQAOA_ERANGE, "item %d: n=%d > %d", k, n_host[i], GQAOA_SV_ITEMS_MAX_N);
+        }
+    }
+    ScanPlan *P = nullptr;
+    s = scan_plan_create(num_inst, n_host, m_host, hists_host, hist_stride, target_host, nb, betas_host, ng,
+                         gammas_host, pig, num_p, p_list_host, psol_dev, energy_dev, tile, num_items, items_host,
+                         costs_dev, cost_off_host, item_psol_dev, item_energy_dev, (hipStream_t)stream, &P);
+    if (s) return s;
+    *plan_out = reinterpret_cast<gqaoa_scan_plan *>(P);
+    return GQAOA_OK;
+}
+
+int gqaoa_scan_plan_run(gqaoa_scan_plan *plan, const double *betas_host, const double *gammas_host, void *stream) {
+    clear_error();
+    if (!plan) return fail(GQAOA_EINVAL, "NULL plan");
+    if (!betas_host != !gammas_host) return fail(GQAOA_EINVAL, "one of the two grids is NULL");
+    return scan_plan_run(reinterpret_cast<ScanPlan *>(plan), betas_host, gammas_host, (hipStream_t)stream);
+}
+
+void gqaoa_scan_plan_destroy(gqaoa_scan_plan *plan) { scan_plan_destroy(reinterpret_cast<ScanPlan *>(plan)); }
 
 size_t gqaoa_mlp_act_bytes(int batch) {
     if (batch < 1 || batch > (1 << 20)) return 0;

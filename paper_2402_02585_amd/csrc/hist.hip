@@ -16,7 +16,7 @@
 // bucketed by padded level count (a register-array size per kernel
 // instantiation) and, inside a bucket, ordered by level count descending so
 // the dynamic queue ends with the short items.
-#include "internal.h"
+#include "batch.h"
 
 #include <algorithm>
 #include <chrono>
@@ -156,35 +156,8 @@ int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *bet
 }
 
 // ---- batched single-angle-pair scan, float32 -------------------------------------------
-constexpr int kScanMaxP = 16;
 constexpr int kScanMaxWaves = 4;
 constexpr int kScanHoistMax = 24;  // largest bucket whose phase table is kept in registers
-
-struct ScanSlot {          // one instance inside a bucket, in queue order
-    int32_t inst;          // caller's instance index
-    int32_t lev_off;       // into lev/w
-    int32_t K;             // occupied levels
-    int32_t t_idx;         // position of the target level among them, -1 if unoccupied
-    int32_t pmax;          // rounds to run for this instance
-    int32_t pad[3];
-};
-
-struct ScanArgs {
-    const ScanSlot *slots;
-    const int32_t *lev;
-    const float *w;
-    const double *betas;
-    const double *gammas;
-    float *psol;
-    float *energy;
-    int32_t *first_p;      // crossing mode: [inst][ng][nb] first round with P >= threshold (0: none)
-    float threshold;
-    unsigned int *counter;
-    unsigned int total_items;
-    int nb, ng, ntiles, num_p;
-    int per_inst;          // angle grids are per instance
-    int p_list[kScanMaxP];
-};
 
 // CROSS = false: P_sol (and E) after each p in p_list. CROSS = true: the
 // first round j <= p_list[0] with P >= threshold; a wave stops once every
@@ -322,10 +295,6 @@ int scan_max_levels() { return kScanMaxK; }
 // candidate is timed on the bucket's real work (a prefix of the queue) and
 // the best is cached per (device arch, bucket, beta tiles) for the process;
 // GQAOA_TUNE_CACHE names an optional text file that persists the choices.
-struct TileChoice {
-    int waves, blocks_per_cu;
-};
-
 static std::mutex g_tune_mu;
 static std::map<std::string, TileChoice> g_tune;
 static bool g_tune_loaded = false;
@@ -352,8 +321,8 @@ static void tune_store_locked() {
     fclose(f);
 }
 
-static int launch_bucket(int bucket, const TileChoice &tc, const DeviceInfo &dev, ScanArgs a,
-                         unsigned int *counter, hipStream_t st) {
+int scan_launch_bucket(int bucket, const TileChoice &tc, const DeviceInfo &dev, ScanArgs a, unsigned int *counter,
+                       hipStream_t st) {
     hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counter, 1);
     GQ_LAUNCH_CHECK();
     a.counter = counter;
@@ -395,11 +364,11 @@ static int tune_bucket(int bucket, const DeviceInfo &dev, const ScanArgs &a, uns
     for (int wv : waves_c)
         for (int bpc : bpc_c) {
             TileChoice tc{wv, bpc};
-            int s = launch_bucket(bucket, tc, dev, t, counter, st);  // warm-up
+            int s = scan_launch_bucket(bucket, tc, dev, t, counter, st);  // warm-up
             if (s) return s;
             GQ_HIP(hipEventRecord(e0, st));
             for (int r = 0; r < 3; ++r)
-                if ((s = launch_bucket(bucket, tc, dev, t, counter, st))) return s;
+                if ((s = scan_launch_bucket(bucket, tc, dev, t, counter, st))) return s;
             GQ_HIP(hipEventRecord(e1, st));
             GQ_HIP(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -427,32 +396,48 @@ size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int n
            al(8 * (size_t)ng * ga) + al(4 * kNumBuckets) + 256;
 }
 
-int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
-             int hist_stride, const int32_t *target_host, int nb, const double *betas, int ng,
-             const double *gammas, int per_inst, int num_p, const int32_t *p_list, float *psol, float *energy,
-             float threshold, int32_t *first_p, const int32_t *pmax_host, const int32_t *tile, void *ws,
-             hipStream_t st) {
-    DeviceInfo dev;
-    int s = device_info(&dev);
-    if (s) return s;
+int scan_num_buckets() { return kNumBuckets; }
+
+ScanDev scan_dev_tables(void *ws, int num_inst, int hist_stride, int nb, int ng, int per_inst) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t lv = (size_t)num_inst * std::min(hist_stride, kScanMaxK);
+    const size_t ga = per_inst ? (size_t)num_inst : 1;
+    char *p = reinterpret_cast<char *>(ws);
+    ScanDev d;
+    d.slots = reinterpret_cast<ScanSlot *>(p);
+    p += al(sizeof(ScanSlot) * (size_t)num_inst);
+    d.lev = reinterpret_cast<int32_t *>(p);
+    p += al(4 * lv);
+    d.w = reinterpret_cast<float *>(p);
+    p += al(4 * lv);
+    d.betas = reinterpret_cast<double *>(p);
+    p += al(8 * (size_t)nb * ga);
+    d.gammas = reinterpret_cast<double *>(p);
+    p += al(8 * (size_t)ng * ga);
+    d.counters = reinterpret_cast<unsigned int *>(p);
+    return d;
+}
+
+int scan_host_tables(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
+                     int hist_stride, const int32_t *target_host, const int32_t *pmax_host, int pmax_all,
+                     ScanHost *out) {
     // compact the occupied levels of every instance
-    std::vector<int32_t> K(num_inst), tidx(num_inst);
-    std::vector<int32_t> lev_all;
-    std::vector<float> w_all;
-    std::vector<int32_t> off(num_inst);
+    std::vector<int32_t> K(num_inst), tidx(num_inst), off(num_inst);
+    out->lev.clear();
+    out->w.clear();
     for (int i = 0; i < num_inst; ++i) {
         const uint64_t *h = hists + (size_t)i * hist_stride;
         const int t = target_host ? target_host[i] : 0;
-        off[i] = (int32_t)lev_all.size();
+        off[i] = (int32_t)out->lev.size();
         tidx[i] = -1;
         const double invN = std::ldexp(1.0, -n_host[i]);
         for (int k = 0; k <= m_host[i]; ++k)
             if (h[k]) {
-                if (k == t) tidx[i] = (int32_t)(lev_all.size() - off[i]);
-                lev_all.push_back(k);
-                w_all.push_back((float)((double)h[k] * invN));
+                if (k == t) tidx[i] = (int32_t)(out->lev.size() - off[i]);
+                out->lev.push_back(k);
+                out->w.push_back((float)((double)h[k] * invN));
             }
-        K[i] = (int32_t)lev_all.size() - off[i];
+        K[i] = (int32_t)out->lev.size() - off[i];
         if (K[i] > kScanMaxK) return fail(GQAOA_ERANGE, "instance %d has %d occupied levels (max %d)", i, K[i], kScanMaxK);
     }
     // buckets, each ordered by K descending
@@ -462,42 +447,53 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
         while (kBuckets[bk] < std::max(1, K[i])) ++bk;
         members[bk].push_back(i);
     }
-    std::vector<ScanSlot> slots;
-    std::vector<int> bucket_first(kNumBuckets + 1, 0);
+    out->slots.clear();
+    out->bucket_first.assign(kNumBuckets + 1, 0);
     for (int bk = 0; bk < kNumBuckets; ++bk) {
         auto &mb = members[bk];
         std::stable_sort(mb.begin(), mb.end(), [&](int x, int y) { return K[x] > K[y]; });
-        bucket_first[bk] = (int)slots.size();
+        out->bucket_first[bk] = (int)out->slots.size();
         for (int i : mb)
-            slots.push_back(ScanSlot{i, off[i], K[i], tidx[i], pmax_host ? pmax_host[i] : p_list[num_p - 1], {0, 0, 0}});
+            out->slots.push_back(ScanSlot{i, off[i], K[i], tidx[i], pmax_host ? pmax_host[i] : pmax_all, {0, 0, 0}});
     }
-    bucket_first[kNumBuckets] = (int)slots.size();
-    // device copies
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    char *p = reinterpret_cast<char *>(ws);
-    ScanSlot *d_slots = reinterpret_cast<ScanSlot *>(p);
-    p += al(sizeof(ScanSlot) * slots.size());
-    int32_t *d_lev = reinterpret_cast<int32_t *>(p);
-    p += al(4 * std::max<size_t>(1, lev_all.size()));
-    float *d_w = reinterpret_cast<float *>(p);
-    p += al(4 * std::max<size_t>(1, w_all.size()));
+    out->bucket_first[kNumBuckets] = (int)out->slots.size();
+    return GQAOA_OK;
+}
+
+int scan_choose_tile(int bucket, const DeviceInfo &dev, const ScanArgs &a, unsigned int *counter,
+                     const int32_t *tile, hipStream_t st, TileChoice *out) {
+    if (tile) {
+        *out = TileChoice{tile[0], tile[1]};
+        return GQAOA_OK;
+    }
+    return tune_bucket(bucket, dev, a, counter, st, out);
+}
+
+int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
+             int hist_stride, const int32_t *target_host, int nb, const double *betas, int ng,
+             const double *gammas, int per_inst, int num_p, const int32_t *p_list, float *psol, float *energy,
+             float threshold, int32_t *first_p, const int32_t *pmax_host, const int32_t *tile, void *ws,
+             hipStream_t st) {
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    ScanHost H;
+    if ((s = scan_host_tables(num_inst, n_host, m_host, hists, hist_stride, target_host, pmax_host,
+                              p_list[num_p - 1], &H)))
+        return s;
+    const ScanDev D = scan_dev_tables(ws, num_inst, hist_stride, nb, ng, per_inst);
     const size_t ga = per_inst ? (size_t)num_inst : 1;
-    double *d_b = reinterpret_cast<double *>(p);
-    p += al(8 * (size_t)nb * ga);
-    double *d_g = reinterpret_cast<double *>(p);
-    p += al(8 * (size_t)ng * ga);
-    unsigned int *d_cnt = reinterpret_cast<unsigned int *>(p);
-    GQ_HIP(hipMemcpyAsync(d_slots, slots.data(), sizeof(ScanSlot) * slots.size(), hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemcpyAsync(d_lev, lev_all.data(), 4 * lev_all.size(), hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemcpyAsync(d_w, w_all.data(), 4 * w_all.size(), hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemcpyAsync(d_b, betas, 8 * (size_t)nb * ga, hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemcpyAsync(d_g, gammas, 8 * (size_t)ng * ga, hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(D.slots, H.slots.data(), sizeof(ScanSlot) * H.slots.size(), hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(D.lev, H.lev.data(), 4 * H.lev.size(), hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(D.w, H.w.data(), 4 * H.w.size(), hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(D.betas, betas, 8 * (size_t)nb * ga, hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemcpyAsync(D.gammas, gammas, 8 * (size_t)ng * ga, hipMemcpyHostToDevice, st));
 
     ScanArgs a{};
-    a.lev = d_lev;
-    a.w = d_w;
-    a.betas = d_b;
-    a.gammas = d_g;
+    a.lev = D.lev;
+    a.w = D.w;
+    a.betas = D.betas;
+    a.gammas = D.gammas;
     a.psol = psol;
     a.energy = energy;
     a.first_p = first_p;
@@ -509,19 +505,15 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
     a.per_inst = per_inst;
     for (int q = 0; q < num_p; ++q) a.p_list[q] = p_list[q];
     for (int bk = 0; bk < kNumBuckets; ++bk) {
-        const int nslots = bucket_first[bk + 1] - bucket_first[bk];
+        const int nslots = H.bucket_first[bk + 1] - H.bucket_first[bk];
         if (!nslots) continue;
         ScanArgs ab = a;
-        ab.slots = d_slots + bucket_first[bk];
+        ab.slots = D.slots + H.bucket_first[bk];
         ab.total_items = (unsigned)nslots * (unsigned)ng * (unsigned)ab.ntiles;
-        TileChoice tc{4, 4};
-        if (tile) {
-            tc = TileChoice{tile[0], tile[1]};
-        } else if ((s = tune_bucket(bk, dev, ab, d_cnt + bk, st, &tc))) {
-            return s;
-        }
+        TileChoice tc;
+        if ((s = scan_choose_tile(bk, dev, ab, D.counters + bk, tile, st, &tc))) return s;
         ProfScope ps("scan", st);
-        if ((s = launch_bucket(bk, tc, dev, ab, d_cnt + bk, st))) return s;
+        if ((s = scan_launch_bucket(bk, tc, dev, ab, D.counters + bk, st))) return s;
         ps.end();
     }
     GQ_HIP(hipStreamSynchronize(st));  // host staging vectors end here

@@ -12,7 +12,7 @@
 // phi_j; one block reduction (float64) gives delta_j = (e^{-i beta} - 1) S_j / 2^n.
 // Each thread owns the same amplitudes in every round, so only the reduction
 // needs barriers.
-#include "internal.h"
+#include "batch.h"
 
 #include <algorithm>
 #include <cmath>
@@ -21,27 +21,6 @@
 namespace gqaoa {
 
 constexpr int kItemThreads = 1024;
-constexpr int kItemMaxP = 16;
-
-struct SvItem {
-    int32_t inst;  // caller's instance index
-    int32_t out;   // caller's item index (output row)
-    double beta, gamma;
-};
-
-struct SvItemsArgs {
-    const SvItem *items;
-    int num_items;
-    int n;
-    const uint8_t *costs;
-    const uint64_t *cost_off;  // per instance
-    const int32_t *m;          // per instance
-    const int32_t *target;     // per instance
-    int num_p;
-    int p_list[kItemMaxP];
-    float *psol;    // [items][num_p]
-    float *energy;  // [items][num_p] or null
-};
 
 size_t sv_items_lds_bytes(int n) {
     const size_t N = size_t(1) << n;
@@ -125,29 +104,57 @@ __global__ void __launch_bounds__(kItemThreads) sv_items_kernel(SvItemsArgs a) {
 
 uint64_t batched_cost_offset(int i, const int32_t *n_host);
 
-int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *target_host,
-                 const uint8_t *costs, int num_items, const int32_t *item_inst, const double *beta,
-                 const double *gamma, int num_p, const int32_t *p_list, float *psol, float *energy, hipStream_t st) {
-    DeviceInfo dev;
-    int s = device_info(&dev);
-    if (s) return s;
+int sv_items_order(const int32_t *n_host, int num_items, const int32_t *item_inst, const DeviceInfo &dev,
+                   ItemOrder *out) {
     for (int k = 0; k < num_items; ++k) {
         const size_t need = sv_items_lds_bytes(n_host[item_inst[k]]);
         if (need > dev.lds_per_block)
             return fail(GQAOA_ERANGE, "item %d: n=%d needs %zu bytes of LDS, the device offers %zu per block", k,
                         n_host[item_inst[k]], need, dev.lds_per_block);
     }
+    out->order.resize(num_items);
+    for (int k = 0; k < num_items; ++k) out->order[k] = k;
+    std::stable_sort(out->order.begin(), out->order.end(),
+                     [&](int x, int y) { return n_host[item_inst[x]] < n_host[item_inst[y]]; });
+    out->first.clear();
+    for (int k = 0; k < num_items; ++k)
+        if (k == 0 || n_host[item_inst[out->order[k]]] != n_host[item_inst[out->order[k - 1]]]) out->first.push_back(k);
+    out->first.push_back(num_items);
+    return GQAOA_OK;
+}
+
+int sv_items_allow_lds(int n) {
+    const size_t lds = sv_items_lds_bytes(n);
+    if (lds > 65536)
+        GQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(sv_items_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return GQAOA_OK;
+}
+
+int sv_items_launch(const SvItemsArgs &a, const DeviceInfo &dev, hipStream_t st) {
+    const size_t lds = sv_items_lds_bytes(a.n);
+    const int per_cu = std::max<int>(1, (int)std::min<size_t>(2, dev.lds_per_block / std::max<size_t>(lds, 1)));
+    const int blocks = std::min(a.num_items, dev.num_cus * per_cu);
+    hipLaunchKernelGGL(sv_items_kernel, dim3(blocks), dim3(kItemThreads), lds, st, a);
+    GQ_LAUNCH_CHECK();
+    return GQAOA_OK;
+}
+
+int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *target_host,
+                 const uint8_t *costs, int num_items, const int32_t *item_inst, const double *beta,
+                 const double *gamma, int num_p, const int32_t *p_list, float *psol, float *energy, hipStream_t st) {
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    ItemOrder ord;
+    if ((s = sv_items_order(n_host, num_items, item_inst, dev, &ord))) return s;
     std::vector<uint64_t> off(num_inst);
     for (int i = 0; i < num_inst; ++i) off[i] = batched_cost_offset(i, n_host);
     std::vector<int32_t> tg(num_inst, 0);
     if (target_host) tg.assign(target_host, target_host + num_inst);
-    // items grouped by n (one launch per group, LDS sized for that n)
     std::vector<SvItem> items(num_items);
-    std::vector<int> order(num_items);
-    for (int k = 0; k < num_items; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return n_host[item_inst[x]] < n_host[item_inst[y]]; });
     for (int k = 0; k < num_items; ++k) {
-        const int o = order[k];
+        const int o = ord.order[k];
         items[k] = SvItem{item_inst[o], o, beta[o], gamma[o]};
     }
     auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
@@ -163,14 +170,12 @@ int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, con
     GQ_HIP(hipMemcpyAsync(d_off, off.data(), b_off, hipMemcpyHostToDevice, st));
     GQ_HIP(hipMemcpyAsync(d_m, m_host, b_i, hipMemcpyHostToDevice, st));
     GQ_HIP(hipMemcpyAsync(d_t, tg.data(), b_i, hipMemcpyHostToDevice, st));
-    for (int k0 = 0; k0 < num_items;) {
-        const int n = n_host[items[k0].inst];
-        int k1 = k0;
-        while (k1 < num_items && n_host[items[k1].inst] == n) ++k1;
+    for (size_t g = 0; g + 1 < ord.first.size(); ++g) {
+        const int k0 = ord.first[g], k1 = ord.first[g + 1];
         SvItemsArgs a{};
         a.items = d_items + k0;
         a.num_items = k1 - k0;
-        a.n = n;
+        a.n = n_host[items[k0].inst];
         a.costs = costs;
         a.cost_off = d_off;
         a.m = d_m;
@@ -179,15 +184,7 @@ int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, con
         for (int q = 0; q < num_p; ++q) a.p_list[q] = p_list[q];
         a.psol = psol;
         a.energy = energy;
-        const size_t lds = sv_items_lds_bytes(n);
-        if (lds > 65536)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(sv_items_kernel),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        const int per_cu = std::max<int>(1, (int)std::min<size_t>(2, dev.lds_per_block / std::max<size_t>(lds, 1)));
-        const int blocks = std::min(k1 - k0, dev.num_cus * per_cu);
-        hipLaunchKernelGGL(sv_items_kernel, dim3(blocks), dim3(kItemThreads), lds, st, a);
-        GQ_LAUNCH_CHECK();
-        k0 = k1;
+        if ((s = sv_items_allow_lds(a.n)) || (s = sv_items_launch(a, dev, st))) return s;
     }
     GQ_HIP(hipStreamSynchronize(st));  // the host tables above end with this call
     return GQAOA_OK;

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgqaoa.so")
 
 C64, C128 = 0, 1
+SV_ITEMS_MAX_N = 14          # GQAOA_SV_ITEMS_MAX_N: largest n of a statevector work item (state in LDS)
 MLP_NPARAMS = 160 * 256 + 256 + 256 * 256 + 256 + 256 * 2 + 2
 MLP_OFFSETS = {"W1": (0, (160, 256)), "b1": (40960, (256,)), "W2": (41216, (256, 256)),
                "b2": (106752, (256,)), "W3": (107008, (256, 2)), "b3": (107520, (2,))}
@@ -48,6 +49,10 @@ _SIGS = {
                             _sz, _vp], _i32),
     "gqaoa_scan_crossing": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _f32, _vp, _vp,
                              _vp, _sz, _vp], _i32),
+    "gqaoa_scan_plan_create": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp,
+                                _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_scan_plan_run": ([_vp, _vp, _vp, _vp], _i32),
+    "gqaoa_scan_plan_destroy": ([_vp], None),
     "gqaoa_shots_to_all": ([_i32, _vp, _i32, _c.c_uint64, _i32, _vp, _vp], _i32),
     "gqaoa_draws_to_reject": ([_i32, _vp, _i32, _c.c_uint64, _c.c_double, _i32, _i32, _vp, _vp], _i32),
     "gqaoa_mlp_act_bytes": ([_i32], _sz),
@@ -397,6 +402,78 @@ def gqaoa_scan_crossing(ns, ms, hists, betas, gammas, p_max, threshold: float, t
                                    _ptr(first),
                                    _np_ptr(tl), _ptr(ws), ws.numel(), _stream(torch, stream)))
     return first
+
+
+class ScanPlan:
+    """Graph-captured scan (gqaoa_scan_plan_*): the instances' level tables and
+    launch shapes are fixed at construction, each run() uploads a grid of the
+    same shape and replays one HIP graph. Optional statevector items run on
+    grid cells in the same graph.
+
+    items: int array [K, 3] of (instance, gamma index, beta index); costs and
+    cost_off: the uint8 cost tables and per-instance byte offsets (e.g. from
+    gqaoa_cost_batched; instances without items may have any offset).
+    Outputs live on the plan: psol/energy [I, num_p, ng, nb] and
+    item_psol/item_energy [K, num_p], complete once the run's stream reaches
+    the end of the replay."""
+
+    def __init__(self, ns, ms, hists, betas, gammas, p_list, targets=None, tile=None, with_energy: bool = True,
+                 items=None, costs=None, cost_off=None, stream=None):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self._handle = ctypes.c_void_p()
+        ns, ms, h, I, stride, b, g, per_inst, nb, ng, tg, tl = _scan_common(ns, ms, hists, betas, gammas, targets,
+                                                                            tile)
+        self.shape_b, self.shape_g = b.shape, g.shape
+        pl = np.ascontiguousarray(np.asarray(p_list, dtype=np.int32))
+        self.psol = torch.empty((I, pl.size, ng, nb), dtype=torch.float32, device="cuda")
+        self.energy = torch.empty_like(self.psol) if with_energy else None
+        it = np.zeros((0, 3), dtype=np.int32) if items is None else np.asarray(items, dtype=np.int32).reshape(-1, 3)
+        it = np.ascontiguousarray(it)
+        K = it.shape[0]
+        self.item_psol = torch.empty((K, pl.size), dtype=torch.float32, device="cuda") if K else None
+        self.item_energy = torch.empty((K, pl.size), dtype=torch.float32, device="cuda") if K and with_energy else None
+        co = None
+        if K:
+            co = np.ascontiguousarray(np.asarray(cost_off, dtype=np.uint64).reshape(-1)[:I])
+            if co.size != I:
+                raise ValueError(f"cost_off must have {I} entries")
+        self._keep = (costs,)
+        _check(lib.gqaoa_scan_plan_create(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), nb,
+                                          _np_ptr(b), ng, _np_ptr(g), int(per_inst), pl.size, _np_ptr(pl),
+                                          _ptr(self.psol), _ptr(self.energy), _np_ptr(tl), K,
+                                          _np_ptr(it) if K else None, _ptr(costs) if K else None,
+                                          _np_ptr(co), _ptr(self.item_psol), _ptr(self.item_energy),
+                                          _stream(torch, stream), ctypes.byref(self._handle)))
+
+    def run(self, betas=None, gammas=None, stream=None):
+        """Replay with a new grid (same shapes), or the current one when both are None."""
+        torch = _torch()
+        if (betas is None) != (gammas is None):
+            raise ValueError("give both grids or neither")
+        b = g = None
+        if betas is not None:
+            b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+            g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
+            if b.shape != self.shape_b or g.shape != self.shape_g:
+                raise ValueError(f"grid shapes {b.shape}, {g.shape} differ from the plan's "
+                                 f"{self.shape_b}, {self.shape_g}")
+        if not self._handle:
+            raise GQAOAError(-1, "plan already closed")
+        _check(self._lib.gqaoa_scan_plan_run(self._handle, _np_ptr(b), _np_ptr(g), _stream(torch, stream)))
+        return self.psol, self.energy
+
+    def close(self):
+        if self._handle:
+            self._lib.gqaoa_scan_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- fair-sampling metrics ------------------------------------------------------------

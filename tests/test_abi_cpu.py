@@ -190,6 +190,37 @@ def test_batched_cost_and_items_argument_checks():
                               g._np_ptr(b), 2, g._np_ptr(bad), d, None, None) == -1
 
 
+def test_scan_plan_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    ns = np.array([10, 15], dtype=np.int32)
+    ms = np.array([42, 42], dtype=np.int32)
+    hist = np.zeros((2, 43), dtype=np.uint64)
+    hist[:, :5] = 1
+    b = np.zeros(4)
+    pl = np.array([1, 4], dtype=np.int32)
+    off = np.zeros(2, dtype=np.uint64)
+    out = ctypes.c_void_p()
+
+    def create(items, k, grid=b, plan=ctypes.byref(out), costs=d):
+        return lib.gqaoa_scan_plan_create(2, g._np_ptr(ns), g._np_ptr(ms), g._np_ptr(hist), 43, None, 4,
+                                          g._np_ptr(grid), 4, g._np_ptr(b), 0, 2, g._np_ptr(pl), d, None, None, k,
+                                          g._np_ptr(items), costs, g._np_ptr(off), d, None, None, plan)
+
+    ok = np.array([0, 1, 2], dtype=np.int32)
+    assert create(ok, 1, plan=None) == -1                                   # no place for the plan
+    assert create(np.array([0, 4, 0], dtype=np.int32), 1) == -1             # gamma index outside the grid
+    assert create(np.array([0, 0, -1], dtype=np.int32), 1) == -1            # beta index outside the grid
+    assert create(np.array([2, 0, 0], dtype=np.int32), 1) == -2             # no instance 2
+    assert create(np.array([1, 0, 0], dtype=np.int32), 1) == -2             # n = 15 is past the LDS items
+    assert create(ok, 1, costs=None) == -1                                  # items need cost tables
+    assert create(ok, -1) == -2
+    assert create(ok, 1, grid=np.array([0.0, np.nan, 0.0, 0.0])) == -1      # non-finite angle
+    assert not out.value
+    assert lib.gqaoa_scan_plan_run(None, None, None, None) == -1
+    lib.gqaoa_scan_plan_destroy(None)                                       # a no-op
+
+
 def test_profile_interval_checks():
     lib = g.load_library()
     assert lib.gqaoa_profile_enable(-1) == -1

@@ -1,0 +1,125 @@
+"""GPU: the graph-captured scan plan (gqaoa_scan_plan_*).
+
+A replay runs the same kernels as the eager calls, and each lane's arithmetic
+does not depend on the launch shape or the queue order, so every replay must
+equal the eager gqaoa_scan_batched / gqaoa_sv_items results on the same grid
+bit for bit. Replays are interleaved with other eager work and
+synchronizations, with new grids, with the current grid (no upload) and
+with the first grid again, and the outputs are cleared before each replay so
+a stale value cannot pass. Sampled cells are also checked against the oracle
+(level space, float64) within the scan's float32 tolerance of 1e-4, and the
+statevector items against the scan's cells within 1e-5 (two float32 paths
+of the same exact state).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import log, need_gpu
+from oracle.cost import cost_table, level_histogram
+from oracle.evolve import evolve_hist
+from paper_2402_02585_amd import gqaoa as g
+from paper_2402_02585_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+P_LIST = [1, 3, 8, 20]
+
+
+def _setup(seed, count, n_lo, n_hi):
+    its = inst.batched_scan_instances(seed, count, n_lo, n_hi)
+    ns = [it.n for it in its]
+    ms = [it.m for it in its]
+    H = np.zeros((count, max(ms) + 1), dtype=np.uint64)
+    for i, it in enumerate(its):
+        H[i, :it.m + 1] = level_histogram(cost_table(it.n, it.lits), it.m)
+    return its, ns, ms, H
+
+
+def _items(ns, nb, ng, rng, per=3):
+    rows = []
+    for i, n in enumerate(ns):
+        if n <= g.SV_ITEMS_MAX_N:
+            for _ in range(per):
+                rows.append((i, int(rng.integers(0, ng)), int(rng.integers(0, nb))))
+    return np.array(rows, dtype=np.int32)
+
+
+def _grid(rng, nb, ng, rows=None):
+    shape_b = (nb,) if rows is None else (rows, nb)
+    shape_g = (ng,) if rows is None else (rows, ng)
+    return rng.uniform(0, 2 * np.pi, shape_b), rng.uniform(0, np.pi, shape_g)
+
+
+@pytest.mark.parametrize("per_instance", [False, True])
+def test_plan_replays_equal_eager(per_instance):
+    torch = need_gpu()
+    its, ns, ms, H = _setup(61, 48, 6, 18)
+    nb, ng = 70, 5                                   # two beta tiles, the second ragged
+    rng = np.random.Generator(np.random.PCG64(62 + per_instance))
+    rows = len(its) if per_instance else None
+    grids = [_grid(rng, nb, ng, rows) for _ in range(3)]
+    items = _items(ns, nb, ng, rng)
+    costs, off, _ = g.gqaoa_cost_batched(ns, ms, [it.lits for it in its], with_hist=False)
+    log(f"scan plan per_instance={per_instance}: {len(its)} instances, {items.shape[0]} items")
+    plan = g.ScanPlan(ns, ms, H, grids[0][0], grids[0][1], P_LIST, items=items, costs=costs, cost_off=off[:-1])
+    try:
+        for rep, (k, new) in enumerate([(0, False), (1, True), (1, False), (2, True), (0, True)]):
+            b, gm = grids[k]
+            # other eager work between replays, then the eager reference
+            ref_p, ref_e = g.gqaoa_scan_batched(ns, ms, H, b, gm, P_LIST)
+            ii = items[:, 0]
+            ib = b[ii, items[:, 2]] if per_instance else b[items[:, 2]]
+            ig = gm[ii, items[:, 1]] if per_instance else gm[items[:, 1]]
+            ref_ip, ref_ie = g.gqaoa_sv_items(ns, ms, costs, ii, ib, ig, P_LIST, with_energy=True)
+            torch.cuda.synchronize()
+            for t in (plan.psol, plan.energy, plan.item_psol, plan.item_energy):
+                t.fill_(-1.0)
+            if new:
+                plan.run(b, gm)
+            else:
+                plan.run()
+            torch.cuda.synchronize()
+            log(f"  replay {rep}: grid {k}, upload={new}")
+            assert torch.equal(plan.psol, ref_p), rep
+            assert torch.equal(plan.energy, ref_e), rep
+            assert torch.equal(plan.item_psol, ref_ip), rep
+            assert torch.equal(plan.item_energy, ref_ie), rep
+            ps = plan.psol.cpu().numpy()
+            ip = plan.item_psol.cpu().numpy()
+            scan_at = ps[items[:, 0], :, items[:, 1], items[:, 2]]
+            assert np.abs(ip - scan_at).max() < 1e-5
+            for i in range(0, len(its), 7):
+                bi, gi = int(rng.integers(0, nb)), int(rng.integers(0, ng))
+                bb = b[i, bi] if per_instance else b[bi]
+                gg = gm[i, gi] if per_instance else gm[gi]
+                _, rp, _, _ = evolve_hist(H[i, :ms[i] + 1], np.full(P_LIST[-1], bb), np.full(P_LIST[-1], gg))
+                assert np.abs(ps[i, :, gi, bi] - rp[P_LIST]).max() < 1e-4
+    finally:
+        plan.close()
+
+
+def test_plan_without_items_and_async_runs():
+    """Back-to-back runs with different grids and no host synchronization in
+    between: each run waits for the previous replay before its upload, so the
+    last grid's results come out."""
+    torch = need_gpu()
+    its, ns, ms, H = _setup(63, 30, 8, 16)
+    nb, ng = 64, 4
+    rng = np.random.Generator(np.random.PCG64(64))
+    grids = [_grid(rng, nb, ng) for _ in range(4)]
+    plan = g.ScanPlan(ns, ms, H, grids[0][0], grids[0][1], [2, 9], with_energy=False, tile=[2, 4])
+    try:
+        assert plan.item_psol is None and plan.energy is None
+        for b, gm in grids:
+            plan.run(b, gm)
+        last = g.gqaoa_scan_batched(ns, ms, H, grids[-1][0], grids[-1][1], [2, 9], tile=[2, 4], with_energy=False)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(plan.psol, last)
+        with pytest.raises(ValueError):
+            plan.run(grids[0][0][:10], grids[0][1])
+        with pytest.raises(g.GQAOAError):
+            bad = grids[0][0].copy()
+            bad[3] = np.inf
+            plan.run(bad, grids[0][1])
+    finally:
+        plan.close()
+    plan.close()                                     # closing twice is harmless
