@@ -4,9 +4,9 @@
 //
 // Creating a plan does the per-instance work once: the occupied levels and
 // weights are compacted and uploaded, every bucket's launch shape is chosen
-// (tuned on the real queue), and the launches are captured in one HIP graph:
-// the scan buckets on one branch, the statevector items (states in LDS) on a
-// parallel branch, so both paths go out with a single hipGraphLaunch. A run
+// (tuned on the real queue), and the launches are captured in one HIP graph
+// with one parallel branch per scan bucket and one for the statevector items
+// (states in LDS), so both paths go out with a single hipGraphLaunch. A run
 // then uploads only the angle grid and the items' angles (one copy from
 // pinned staging) and replays the graph. Every queue counter is cleared by a
 // kernel inside the graph, so the graph holds kernel nodes only.
@@ -33,8 +33,10 @@ struct ScanPlan {
     size_t off_b = 0, off_g = 0, off_items = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipStream_t cap = nullptr, side = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> branch;   // one per scan bucket, then one for the items
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;      // one per branch
     hipEvent_t staged = nullptr;       // the last upload has read the staging
     hipEvent_t done = nullptr;         // the last replay has finished
 };
@@ -59,11 +61,11 @@ static void release(ScanPlan *P) {
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->fork) (void)hipEventDestroy(P->fork);
-    if (P->join) (void)hipEventDestroy(P->join);
+    for (hipEvent_t e : P->join) (void)hipEventDestroy(e);
     if (P->staged) (void)hipEventDestroy(P->staged);
     if (P->done) (void)hipEventDestroy(P->done);
     if (P->cap) (void)hipStreamDestroy(P->cap);
-    if (P->side) (void)hipStreamDestroy(P->side);
+    for (hipStream_t b : P->branch) (void)hipStreamDestroy(b);
     if (P->dev) (void)hipFree(P->dev);
     if (P->stage) (void)hipHostFree(P->stage);
     delete P;
@@ -81,24 +83,29 @@ struct PlanGuard {
     }
 };
 
-// Enqueues every launch of the plan: scan buckets on `cap`, items on `side`
-// (forked from and joined back to `cap`).
+// Enqueues every launch of the plan, each scan bucket and the items on a
+// branch of its own, forked from and joined back to `cap`: the buckets are
+// independent, so the tail of one overlaps the others.
 static int enqueue_all(ScanPlan *P, const DeviceInfo &dev, const std::vector<ScanArgs> &bucket_args,
                        const std::vector<int> &bucket_ids, const std::vector<TileChoice> &tiles,
                        unsigned int *counters, const std::vector<SvItemsArgs> &item_args) {
     int s;
-    if (!item_args.empty()) {
-        GQ_HIP(hipEventRecord(P->fork, P->cap));
-        GQ_HIP(hipStreamWaitEvent(P->side, P->fork, 0));
-    }
-    for (size_t q = 0; q < bucket_args.size(); ++q)
-        if ((s = scan_launch_bucket(bucket_ids[q], tiles[q], dev, bucket_args[q], counters + bucket_ids[q], P->cap)))
+    GQ_HIP(hipEventRecord(P->fork, P->cap));
+    for (size_t q = 0; q < bucket_args.size(); ++q) {
+        GQ_HIP(hipStreamWaitEvent(P->branch[q], P->fork, 0));
+        if ((s = scan_launch_bucket(bucket_ids[q], tiles[q], dev, bucket_args[q], counters + bucket_ids[q],
+                                    P->branch[q])))
             return s;
-    for (const SvItemsArgs &a : item_args)
-        if ((s = sv_items_launch(a, dev, P->side))) return s;
+    }
     if (!item_args.empty()) {
-        GQ_HIP(hipEventRecord(P->join, P->side));
-        GQ_HIP(hipStreamWaitEvent(P->cap, P->join, 0));
+        hipStream_t side = P->branch[bucket_args.size()];
+        GQ_HIP(hipStreamWaitEvent(side, P->fork, 0));
+        for (const SvItemsArgs &a : item_args)
+            if ((s = sv_items_launch(a, dev, side))) return s;
+    }
+    for (size_t q = 0; q < P->branch.size(); ++q) {
+        GQ_HIP(hipEventRecord(P->join[q], P->branch[q]));
+        GQ_HIP(hipStreamWaitEvent(P->cap, P->join[q], 0));
     }
     return GQAOA_OK;
 }
@@ -160,11 +167,9 @@ int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host,
     GQ_HIP(hipMalloc(&P->dev, total));
     GQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&P->stage), std::max<size_t>(P->dyn_bytes, 256), hipHostMallocDefault));
     GQ_HIP(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
-    GQ_HIP(hipEventCreateWithFlags(&P->join, hipEventDisableTiming));
     GQ_HIP(hipEventCreateWithFlags(&P->staged, hipEventDisableTiming));
     GQ_HIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
     GQ_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
-    GQ_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
 
     // static tables and the first grid
     std::memcpy(P->stage + P->off_b, betas, 8 * P->n_b);
@@ -232,6 +237,15 @@ int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host,
         item_args.push_back(ia);
     }
     GQ_HIP(hipStreamSynchronize(st));  // uploads and tuning done; host tables end here
+    const size_t nbranch = bucket_args.size() + (item_args.empty() ? 0 : 1);
+    for (size_t q = 0; q < nbranch; ++q) {
+        hipStream_t b = nullptr;
+        hipEvent_t e = nullptr;
+        GQ_HIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+        P->branch.push_back(b);
+        GQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        P->join.push_back(e);
+    }
 
     // capture: one branch per path
     GQ_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
