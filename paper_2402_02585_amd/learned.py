@@ -117,17 +117,22 @@ def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
 
 def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.25, 0.06, 0.015), zoom: int = 16):
     """Best pair after one zoom x zoom window scan per width, each centred on the
-    previous best (one launch per width, all instances). The peak narrows as p
-    grows, hence three shrinking windows."""
+    previous best (one replay of a graph-captured scan per width, all
+    instances). The peak narrows as p grows, hence three shrinking windows."""
     I = len(ns)
     b = np.asarray(betas, dtype=np.float64).copy()
     gm = np.asarray(gammas, dtype=np.float64).copy()
     best = evaluate_pairs(ns, ms, hists, b, gm, p)
+    plan = None                      # one graph-captured scan, replayed per window
     for w in widths:
         offs = np.linspace(-w, w, zoom)
         bgrid = b[:, None] + offs[None, :]
         ggrid = np.clip(gm[:, None] + offs[None, :] / 2, 0.0, math.pi)
-        ps, _ = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], with_energy=False)
+        if plan is None:
+            plan = g.ScanPlan(ns, ms, hists, bgrid, ggrid, [p], with_energy=False)
+            ps, _ = plan.run()
+        else:
+            ps, _ = plan.run(bgrid, ggrid)
         v = ps[:, 0].reshape(I, -1)
         j = v.argmax(dim=1).cpu().numpy()
         vj = v.cpu().numpy()[np.arange(I), j].astype(np.float64)
@@ -135,4 +140,6 @@ def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.25, 0.06, 0.015
         b[better] = bgrid[better, j[better] % zoom]
         gm[better] = ggrid[better, j[better] // zoom]
         best[better] = vj[better]
+    if plan is not None:
+        plan.close()
     return b, gm, best

@@ -9,8 +9,9 @@ seed. Here every evaluation runs on the GPU:
   per angle pair (``gqaoa_hist_evolve``), grid then L-BFGS-B. This is the
   comparator for the batched and learned forms.
 * ``batched_single_pair``: all instances at once - the fundamental-domain grid
-  through one ``gqaoa_scan_batched`` launch, then two rounds of per-instance
-  zoomed grids around each best point (also one launch each).
+  through one ``gqaoa_scan_batched`` call, then two rounds of per-instance
+  zoomed grids around each best point (per p, one graph-captured scan plan
+  replayed at each zoom level).
 * ``full_gqaoa``: all 2p angles by L-BFGS-B with the adjoint gradient
   (``gqaoa_grad``).
 
@@ -108,13 +109,18 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
         gamma[sl] = gg[idx // gb.size]
         del psol, energy, val, flat
     db, dg = gb[1] - gb[0], gg[1] - gg[0]
+    plans = {}                       # per p: a graph-captured scan replayed at every zoom level
     for _ in range(zoom_levels):
         offs = (np.arange(zoom) - (zoom - 1) / 2.0) * (2.0 / zoom)
         for q, p in enumerate(p_list):
             bgrid = beta[:, q:q + 1] + offs[None, :] * db
             ggrid = np.clip(gamma[:, q:q + 1] + offs[None, :] * dg, 0.0, math.pi)
-            ps, en = g.gqaoa_scan_batched(ns, ms, hists, bgrid, ggrid, [p], targets=targets, tile=tile,
-                                          with_energy=want_e)
+            if p not in plans:
+                plans[p] = g.ScanPlan(ns, ms, hists, bgrid, ggrid, [p], targets=targets, tile=tile,
+                                      with_energy=want_e)
+                ps, en = plans[p].run()
+            else:
+                ps, en = plans[p].run(bgrid, ggrid)
             v = (-ps if objective == "psol" else en)[:, 0].reshape(I, -1)
             j = v.argmin(dim=1).cpu().numpy()
             vj = v.cpu().numpy()[np.arange(I), j]
@@ -123,6 +129,8 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
             gamma[better, q] = ggrid[better, j[better] // zoom]
             best_v[better, q] = vj[better]
         db, dg = db * 2.0 / zoom, dg * 2.0 / zoom
+    for pl in plans.values():
+        pl.close()
     # final readout at the chosen pairs
     ps, en = g.gqaoa_scan_batched(ns, ms, hists, beta, gamma, p_list, targets=targets, tile=tile)
     ps = ps.cpu().numpy()
