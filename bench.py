@@ -85,11 +85,15 @@ def host_info():
     return {"cpu_count": os.cpu_count(), "cpu_model": model}
 
 
-def cpu_baseline():
-    """The oracle's statevector evolution (complex128, numpy) on a bounded
-    sample: one seed-2 instance at n = 22, m = 92, p = 64 rounds."""
-    from oracle.cost import cost_table
-    from oracle.evolve import evolve_sv
+def cpu_baseline(legs: bool = True):
+    """The oracle on bounded samples of each workload (one thread each).
+
+    Headline: its statevector evolution (complex128, numpy) of one seed-2
+    instance at n = 22, m = 92, p = 64 rounds. With ``legs``, beside it: the
+    level-space path on 64 instances of the scan workload, the adjoint at the
+    gradient workload's size, the MLP on one batch of 256 and the X mixer."""
+    from oracle.cost import cost_table, level_histogram
+    from oracle.evolve import evolve_hist, evolve_sv
     from paper_2402_02585_amd import instances as inst
 
     n, m, p = 22, 92, 64
@@ -99,9 +103,79 @@ def cpu_baseline():
     t0 = time.perf_counter()
     evolve_sv(n, cost, beta, gamma)
     dt = time.perf_counter() - t0
-    return {"value": (2 ** n) * p / dt, "unit": "amplitude-rounds/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle statevector evolution, n={n} m={m} p={p}, complex128 numpy, one thread, "
-                      f"{dt:.1f} s"}
+    out = {"value": (2 ** n) * p / dt, "unit": "amplitude-rounds/s", "cores": 1, "kind": "oracle",
+           "sample": f"oracle statevector evolution, n={n} m={m} p={p}, complex128 numpy, one thread, "
+                     f"{dt:.1f} s"}
+    if not legs:
+        return out
+    out["legs"] = {}
+    # scan workload: cost tables + histograms of its first 64 instances, then
+    # one 64-round level-space run (4 readouts) at 8 grid cells per instance
+    its = inst.batched_scan_instances(3, 64, 8, 20)
+    t0 = time.perf_counter()
+    hists = [level_histogram(cost_table(x.n, x.lits), x.m) for x in its]
+    t_hist = time.perf_counter() - t0
+    grid = np.linspace(0.0, math.pi, 64)
+    rng = np.random.Generator(np.random.PCG64(35))
+    cells = [(h, grid[rng.integers(0, 64)], grid[rng.integers(0, 64)]) for h in hists for _ in range(8)]
+    t0 = time.perf_counter()
+    for h, b, gm in cells:
+        evolve_hist(h, np.full(64, b), np.full(64, gm))
+    t_scan = time.perf_counter() - t0
+    out["legs"]["batched"] = {
+        "value": len(cells) * 4 / t_scan, "unit": "instance-angle evals/s",
+        "histograms_clause_evals_per_s": sum(x.m * 2 ** x.n for x in its) / t_hist,
+        "sample": f"oracle level-space evolution, 64 instances of the scan workload x 8 grid cells, p = 64 with "
+                  f"4 readouts ({t_scan:.1f} s); their cost tables and histograms ({t_hist:.1f} s)"}
+    # adjoint workload size: one statevector gradient (n = 20, p = 32) and
+    # level-space gradients of 4 instances
+    from oracle.grad import grad_hist, grad_sv
+    n, m, p = 20, 85, 32
+    lits = []
+    for _, l in inst.sat_stream(4, n, m):
+        if inst.dpll_satisfiable(n, l):
+            lits.append(l)
+        if len(lits) == 4:
+            break
+    costs = [cost_table(n, l) for l in lits]
+    angles = [inst.uniform_angles(100 + i, p) for i in range(4)]
+    t0 = time.perf_counter()
+    grad_sv(n, costs[0], angles[0][0], angles[0][1])
+    t_sv = time.perf_counter() - t0
+    hs = [level_histogram(c, m) for c in costs]
+    t0 = time.perf_counter()
+    for h, (b, gm) in zip(hs, angles):
+        grad_hist(h, b, gm)
+    t_h = (time.perf_counter() - t0) / len(hs)
+    out["legs"]["adjoint"] = {
+        "statevector_gradients_per_s": 1.0 / t_sv, "statevector_amplitude_rounds_per_s": (1 << n) * p / t_sv,
+        "level_space_gradients_per_s": 1.0 / t_h,
+        "sample": f"oracle reverse sweep, n={n} m={m} p={p}: one statevector gradient ({t_sv:.1f} s), "
+                  f"level-space gradients of 4 instances"}
+    # MLP: one forward + backward of a batch of 256
+    from oracle import mlp as omlp
+    prm = omlp.init_params(5)
+    x = np.random.Generator(np.random.PCG64(36)).uniform(0.0, 0.2, (256, omlp.D_IN))
+    t0 = time.perf_counter()
+    o, cache = omlp.forward(prm, x)
+    _, dout = omlp.loss_and_dout(o, np.full(256, 1.0), np.full(256, 0.5))
+    omlp.backward(prm, cache, dout)
+    t_mlp = time.perf_counter() - t0
+    out["legs"]["mlp"] = {"training_samples_per_s": 256 / t_mlp,
+                          "sample": "oracle MLP forward + loss + backward, one batch of 256 (float64, bfloat16 "
+                                    "storage emulated)"}
+    # X mixer: the comparator's statevector rounds
+    from oracle.xqaoa import evolve_x
+    n, m, p = 20, 84, 4
+    itx = inst.first_satisfiable(2, n, m)
+    bx, gx = inst.uniform_angles(3, p)
+    cx = cost_table(n, itx.lits)
+    t0 = time.perf_counter()
+    evolve_x(n, cx, bx, gx)
+    t_x = time.perf_counter() - t0
+    out["legs"]["xqaoa"] = {"value": (1 << n) * p / t_x, "unit": "amplitude-rounds/s",
+                            "sample": f"oracle X-mixer evolution, n={n} m={m} p={p}, complex128 ({t_x:.1f} s)"}
+    return out
 
 
 def batched_leg(torch, g, inst, steps: int):
