@@ -407,6 +407,77 @@ def xqaoa_leg(torch, g, inst, it, reps: int = 3):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_leg(torch, g):
+    """Angle MLP (bfloat16 MFMA): inference over 65,536 instances' features
+    and training steps (forward, loss, backward, Adam) at batch 512."""
+    flops_fwd = 2 * (131 * 256 + 256 * 256 + 256 * 2)       # per sample, the network's own sizes
+    rng = np.random.Generator(np.random.PCG64(37))
+    params = torch.from_numpy(rng.normal(0.0, 0.05, g.MLP_NPARAMS).astype(np.float32)).cuda()
+    B = 65536
+    x = torch.from_numpy(rng.uniform(0.0, 0.2, (B, 131)).astype(np.float32)).cuda()
+    out = torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    act = torch.empty(g.gqaoa_mlp_act_bytes(B), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(g.gqaoa_mlp_infer_bytes(B), dtype=torch.uint8, device="cuda")
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_fwd = timed(lambda: g.gqaoa_mlp_forward(params, x, out=out, act=act))
+    t_inf = timed(lambda: g.gqaoa_mlp_infer(params, x, out=out, workspace=ws))
+    # HBM bytes the inference kernels must move: x (float32) in, h1 (bfloat16) out and back in, outputs out
+    inf_bytes = B * (131 * 4 + 2 * 256 * 2 + 2 * 4)
+    # training steps at batch 512
+    b = 512
+    xb = x[:b].contiguous()
+    yb = torch.from_numpy(np.stack([rng.uniform(0, 2 * math.pi, b), rng.uniform(0, math.pi, b)], axis=1)
+                          .astype(np.float32)).cuda()
+    grads = torch.empty(g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    state = torch.zeros(2 * g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    ob = torch.empty((b, 2), dtype=torch.float32, device="cuda")
+    actb = torch.empty(g.gqaoa_mlp_act_bytes(b), dtype=torch.uint8, device="cuda")
+
+    def step(k):
+        g.gqaoa_mlp_forward(params, xb, out=ob, act=actb)
+        dout, _ = g.gqaoa_mlp_loss(ob, yb)
+        g.gqaoa_mlp_backward(params, actb, dout, grads=grads)
+        g.gqaoa_mlp_adam(params, grads, state, k)
+
+    step(1)
+    torch.cuda.synchronize()
+    steps = 200
+    e0.record()
+    for k in range(steps):
+        step(2 + k)
+    e1.record()
+    torch.cuda.synchronize()
+    t_step = e0.elapsed_time(e1) / steps * 1e-3
+    inf_tflops = B * flops_fwd / t_inf / 1e12
+    return {
+        "workload": "angle MLP 131-256-256-2, bfloat16 weights and activations, float32 accumulation; "
+                    "inference batch 65536, training batch 512",
+        "inference": {"ms_per_batch": t_inf * 1e3, "instances_per_s": B / t_inf, "TFLOPs": inf_tflops,
+                      "frac_of_bf16_mfma_peak": inf_tflops / MFMA_BF16_PEAK_TFLOPS,
+                      "hbm_GBps": inf_bytes / t_inf / 1e9, "kind": "gqaoa_mlp_infer (weights in LDS, two launches)",
+                      "training_forward_ms": t_fwd * 1e3},
+        "training": {"ms_per_step": t_step * 1e3, "samples_per_s": b / t_step,
+                     "TFLOPs": 3 * b * flops_fwd / t_step / 1e12},
+        "note": "65,536 x 2e5 flops is about 5 us of MFMA work at peak and the inference moves about 100 MB; "
+                "training steps at batch 512 are launch-bound (13 launches per step)",
+    }
+
+
 def rounds_leg(torch, g, inst):
     """Rounds-to-target search (single angle pair, S = 50%) for 512
     satisfiable instances, n in 12..20, d ~ U(2, 4.5), the pi/180 grid."""
@@ -441,6 +512,7 @@ def main():
     ap.add_argument("--skip-adjoint", action="store_true", help="omit the adjoint-gradient leg")
     ap.add_argument("--skip-x", action="store_true", help="omit the X-QAOA leg")
     ap.add_argument("--skip-rounds", action="store_true", help="omit the rounds-to-target leg")
+    ap.add_argument("--skip-mlp", action="store_true", help="omit the angle-MLP leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
@@ -547,6 +619,8 @@ def main():
         out["xqaoa"] = xqaoa_leg(torch, g, inst, it)
     if not args.skip_rounds:
         out["rounds_to_target"] = rounds_leg(torch, g, inst)
+    if not args.skip_mlp:
+        out["mlp"] = mlp_leg(torch, g)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

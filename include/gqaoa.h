@@ -311,6 +311,15 @@ void gqaoa_scan_plan_destroy(gqaoa_scan_plan *plan);
 size_t gqaoa_mlp_act_bytes(int batch);
 int gqaoa_mlp_forward(const float *params_dev, int batch, const float *x_dev, float *out_dev,
                       void *act_dev, void *stream);
+/* Inference only (no activation cache, no gradients): the same outputs as
+ * gqaoa_mlp_forward (identical bfloat16 activations; the output layer's sum
+ * may round differently in the last float32 place), from two launches with
+ * the weights held in LDS. ws_dev: gqaoa_mlp_infer_bytes(batch) bytes for
+ * the bfloat16 first hidden layer. Errors: ERANGE (batch), EINVAL (NULL
+ * pointers), EWORKSPACE. */
+size_t gqaoa_mlp_infer_bytes(int batch);
+int gqaoa_mlp_infer(const float *params_dev, int batch, const float *x_dev, float *out_dev,
+                    void *ws_dev, size_t ws_bytes, void *stream);
 int gqaoa_mlp_backward(const float *params_dev, int batch, const void *act_dev,
                        const float *dout_dev, float *grads_dev, void *stream);
 int gqaoa_mlp_adam(float *params_dev, const float *grads_dev, float *state_dev, int step,

@@ -53,6 +53,8 @@ int run_shots_to_all(int K, const double *p, int runs, uint64_t seed, int max_sh
 int run_draws_to_reject(int K, const double *q, int trials, uint64_t seed, double crit, int n_min, int max_draws,
                         int32_t *out, hipStream_t st);
 size_t mlp_act_bytes(int batch);
+size_t mlp_infer_bytes(int batch);
+int run_mlp_infer(const float *prm, int batch, const float *x, float *out, void *ws, hipStream_t st);
 int run_mlp_forward(const float *prm, int batch, const float *x, float *out, void *act, hipStream_t st);
 int run_mlp_backward(const float *prm, int batch, const void *act, const float *dout, float *grads,
                      hipStream_t st);
@@ -569,6 +571,20 @@ void gqaoa_scan_plan_destroy(gqaoa_scan_plan *plan) { scan_plan_destroy(reinterp
 size_t gqaoa_mlp_act_bytes(int batch) {
     if (batch < 1 || batch > (1 << 20)) return 0;
     return mlp_act_bytes(batch);
+}
+
+size_t gqaoa_mlp_infer_bytes(int batch) {
+    if (batch < 1 || batch > (1 << 20)) return 0;
+    return mlp_infer_bytes(batch);
+}
+
+int gqaoa_mlp_infer(const float *params_dev, int batch, const float *x_dev, float *out_dev, void *ws_dev,
+                    size_t ws_bytes, void *stream) {
+    clear_error();
+    if (batch < 1 || batch > (1 << 20)) return fail(GQAOA_ERANGE, "batch=%d", batch);
+    if (!params_dev || !x_dev || !out_dev || !ws_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    if (ws_bytes < mlp_infer_bytes(batch)) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, mlp_infer_bytes(batch));
+    return run_mlp_infer(params_dev, batch, x_dev, out_dev, ws_dev, (hipStream_t)stream);
 }
 
 int gqaoa_mlp_forward(const float *params_dev, int batch, const float *x_dev, float *out_dev, void *act_dev,

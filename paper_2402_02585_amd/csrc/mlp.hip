@@ -18,6 +18,7 @@
 // staging loads.
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace gqaoa {
@@ -423,6 +424,202 @@ int run_mlp_features(int batch, const uint64_t *hists, int hist_stride, const in
     const size_t nx = (size_t)batch * kDIn;
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st,
                        reinterpret_cast<const unsigned long long *>(hists), hist_stride, n, m, p, batch, x);
+    GQ_LAUNCH_CHECK();
+    return GQAOA_OK;
+}
+
+// ---- inference: weights stationary in LDS ----------------------------------------------
+// A small kernel packs the LDS images of W1^T and W2^T (bfloat16) into the
+// workspace; then two persistent kernels of 512 threads (8 waves) run over
+// tiles of 128 rows, each block copying its weight image with 16-byte loads; a
+// wave owns 16 rows and all 256 hidden units (16 MFMA tiles, 64 accumulator
+// registers). Kernel 1 keeps W1^T (bfloat16) in LDS, stages the tile's x rows
+// (contiguous in memory) through LDS and writes h1 = bf16(gelu(x W1 + b1)).
+// Kernel 2 keeps W2^T in LDS, loads h1 fragments straight into the MFMA
+// operand layout and folds the output layer into its epilogue, so h2 never
+// leaves registers. The MFMA k-order equals the training GEMM's, so h1 and
+// h2 are bit-identical to the training forward; only the output layer's
+// 256-term sum is taken in another order.
+constexpr int kInfThreads = 512, kInfRows = 128, kWPad = 8;
+constexpr int kW1Ld = kDInPad + kWPad, kW2Ld = kDH + kWPad, kXLd = kDInPad + kWPad;
+
+constexpr size_t kW1Image = (size_t)kDH * kW1Ld * 2, kW2Image = (size_t)kDH * kW2Ld * 2;  // bytes
+
+// workspace: [W1^T LDS image | W2^T LDS image | h1 (bfloat16 [batch][256])]
+size_t mlp_infer_bytes(int batch) { return al256(kW1Image) + al256(kW2Image) + al256((size_t)batch * kDH * 2); }
+
+// The LDS images of both weight matrices, bfloat16, transposed ([n][k]) and
+// padded, so every block of the inference kernels loads them with 16-byte
+// copies.
+__global__ void mlp_pack_images_kernel(const float *__restrict__ prm, uint16_t *__restrict__ w1t,
+                                       uint16_t *__restrict__ w2t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kDH * kW1Ld) {
+        const int n = i / kW1Ld, k = i % kW1Ld;
+        w1t[i] = k < kDIn ? f2bf(prm[kOffW1 + (size_t)k * kDH + n]) : (uint16_t)0;
+    }
+    if (i < kDH * kW2Ld) {
+        const int n = i / kW2Ld, k = i % kW2Ld;
+        w2t[i] = k < kDH ? f2bf(prm[kOffW2 + (size_t)k * kDH + n]) : (uint16_t)0;
+    }
+}
+
+// 16-byte copy of an LDS image (bytes a multiple of 16) by a whole block.
+__device__ __forceinline__ void load_image(uint16_t *dst, const uint16_t *__restrict__ src, size_t bytes) {
+    const uint4 *s = reinterpret_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(dst);
+    for (size_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+__global__ void __launch_bounds__(kInfThreads) mlp_infer_l1_kernel(const float *__restrict__ prm,
+                                                                    const uint16_t *__restrict__ w1t,
+                                                                    const float *__restrict__ x, int batch,
+                                                                    int x_aligned, uint16_t *__restrict__ h1) {
+    __shared__ __attribute__((aligned(16))) uint16_t w[kDH * kW1Ld];        // W1^T: [n][k]
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kInfRows * kXLd];   // the tile's inputs: [row][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    load_image(w, w1t, kW1Image);
+    const int r16 = lane & 15, kg = (lane >> 4) * 8;
+    float b1[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) b1[t] = prm[kOffB1 + t * 16 + r16];
+    const int ntiles = (batch + kInfRows - 1) / kInfRows;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int row0 = tile * kInfRows;
+        const int rows = min(kInfRows, batch - row0);
+        __syncthreads();  // the previous tile's reads of xs (and, first time, the W1 staging) are done
+        // the tile's rows are contiguous and, when x is 16-byte aligned, start
+        // 16-byte aligned (row0 is a multiple of 4): float4 loads over the
+        // valid part, zeros past the batch
+        const float *src = x + (size_t)row0 * kDIn;
+        const int nvalid = rows * kDIn;
+        for (int j = tid; j < (kInfRows * kDIn) / 4; j += kInfThreads) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (x_aligned && 4 * j + 3 < nvalid) {
+                v = reinterpret_cast<const float4 *>(src)[j];
+            } else {
+                if (4 * j < nvalid) v.x = src[4 * j];
+                if (4 * j + 1 < nvalid) v.y = src[4 * j + 1];
+                if (4 * j + 2 < nvalid) v.z = src[4 * j + 2];
+                if (4 * j + 3 < nvalid) v.w = src[4 * j + 3];
+            }
+            const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * j + q, r = i / kDIn, k = i % kDIn;
+                xs[r * kXLd + k] = f2bf(e[q]);
+            }
+        }
+        for (int i = tid; i < kInfRows * (kDInPad - kDIn); i += kInfThreads) {
+            const int r = i / (kDInPad - kDIn), k = kDIn + i % (kDInPad - kDIn);
+            xs[r * kXLd + k] = 0;
+        }
+        __syncthreads();
+        f32x4 acc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < kDInPad / 32; ++ks) {
+            const u16x8 av = *reinterpret_cast<const u16x8 *>(&xs[(wave * 16 + r16) * kXLd + ks * 32 + kg]);
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const u16x8 bv = *reinterpret_cast<const u16x8 *>(&w[(t * 16 + r16) * kW1Ld + ks * 32 + kg]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                 __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
+            }
+        }
+        // lane holds C[4*(lane/16) + r][lane % 16] of each 16x16 tile
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = row0 + wave * 16 + 4 * (lane >> 4) + r;
+            if (row >= batch) continue;
+            uint16_t *dst = h1 + (size_t)row * kDH + r16;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) dst[t * 16] = f2bf(gelu(acc[t][r] + b1[t]));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kInfThreads) mlp_infer_l23_kernel(const float *__restrict__ prm,
+                                                                     const uint16_t *__restrict__ w2t,
+                                                                     const uint16_t *__restrict__ h1, int batch,
+                                                                     float *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) uint16_t w[kDH * kW2Ld];        // W2^T: [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    load_image(w, w2t, kW2Image);
+    const int r16 = lane & 15, kg = (lane >> 4) * 8;
+    float b2[16], w30[16], w31[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int n = t * 16 + r16;
+        b2[t] = prm[kOffB2 + n];
+        w30[t] = bf2f(f2bf(prm[kOffW3 + (size_t)n * kDOut]));
+        w31[t] = bf2f(f2bf(prm[kOffW3 + (size_t)n * kDOut + 1]));
+    }
+    const float b30 = prm[kOffB3], b31 = prm[kOffB3 + 1];
+    __syncthreads();
+    const int ntiles = (batch + kInfRows - 1) / kInfRows;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int row0 = tile * kInfRows;
+        const int arow = row0 + wave * 16 + r16;  // the A-operand row of this lane
+        const bool live = arow < batch;
+        const uint16_t *src = h1 + (size_t)(live ? arow : 0) * kDH + kg;
+        f32x4 acc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int ks = 0; ks < kDH / 32; ++ks) {
+            u16x8 av = *reinterpret_cast<const u16x8 *>(src + ks * 32);
+            if (!live) av = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const u16x8 bv = *reinterpret_cast<const u16x8 *>(&w[(t * 16 + r16) * kW2Ld + ks * 32 + kg]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                                 __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const float h = bf2f(f2bf(gelu(acc[t][r] + b2[t])));
+                s0 += h * w30[t];
+                s1 += h * w31[t];
+            }
+            // the 16 lanes of a group hold the same rows, different columns
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                s0 += __shfl_xor(s0, off, kWave);
+                s1 += __shfl_xor(s1, off, kWave);
+            }
+            const int row = row0 + wave * 16 + 4 * (lane >> 4) + r;
+            if (r16 == 0 && row < batch) {
+                out[(size_t)row * kDOut] = s0 + b30;
+                out[(size_t)row * kDOut + 1] = s1 + b31;
+            }
+        }
+    }
+}
+
+int run_mlp_infer(const float *prm, int batch, const float *x, float *out, void *ws, hipStream_t st) {
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    char *base = reinterpret_cast<char *>(ws);
+    uint16_t *w1t = reinterpret_cast<uint16_t *>(base);
+    uint16_t *w2t = reinterpret_cast<uint16_t *>(base + al256(kW1Image));
+    uint16_t *h1 = reinterpret_cast<uint16_t *>(base + al256(kW1Image) + al256(kW2Image));
+    const int img = std::max(kDH * kW1Ld, kDH * kW2Ld);
+    hipLaunchKernelGGL(mlp_pack_images_kernel, dim3((img + 255) / 256), dim3(256), 0, st, prm, w1t, w2t);
+    GQ_LAUNCH_CHECK();
+    const int ntiles = (batch + kInfRows - 1) / kInfRows;
+    const int blocks = std::min(ntiles, dev.num_cus);
+    const int x_aligned = (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+    hipLaunchKernelGGL(mlp_infer_l1_kernel, dim3(blocks), dim3(kInfThreads), 0, st, prm, w1t, x, batch, x_aligned,
+                       h1);
+    GQ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(mlp_infer_l23_kernel, dim3(blocks), dim3(kInfThreads), 0, st, prm, w2t, h1, batch, out);
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
 }

@@ -57,6 +57,8 @@ _SIGS = {
     "gqaoa_draws_to_reject": ([_i32, _vp, _i32, _c.c_uint64, _c.c_double, _i32, _i32, _vp, _vp], _i32),
     "gqaoa_mlp_act_bytes": ([_i32], _sz),
     "gqaoa_mlp_forward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_mlp_infer_bytes": ([_i32], _sz),
+    "gqaoa_mlp_infer": ([_vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_mlp_backward": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_mlp_adam": ([_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
     "gqaoa_mlp_loss": ([_i32, _vp, _vp, _vp, _vp, _vp], _i32),
@@ -512,6 +514,23 @@ def gqaoa_mlp_forward(params, x, out=None, act=None, stream=None):
     act = act if act is not None else _workspace(torch, lib.gqaoa_mlp_act_bytes(B))
     _check(lib.gqaoa_mlp_forward(_ptr(params), B, _ptr(x), _ptr(out), _ptr(act), _stream(torch, stream)))
     return out, act
+
+
+def gqaoa_mlp_infer_bytes(batch: int) -> int:
+    return int(load_library().gqaoa_mlp_infer_bytes(batch))
+
+
+def gqaoa_mlp_infer(params, x, out=None, workspace=None, stream=None):
+    """Inference only: params float32 [MLP_NPARAMS], x float32 [B, 131] -> out [B, 2]."""
+    torch = _torch()
+    lib = load_library()
+    B = x.shape[0]
+    if tuple(x.shape) != (B, 131) or x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be contiguous float32 [B, 131]")
+    out = out if out is not None else torch.empty((B, 2), dtype=torch.float32, device="cuda")
+    ws = workspace if workspace is not None else _workspace(torch, lib.gqaoa_mlp_infer_bytes(B))
+    _check(lib.gqaoa_mlp_infer(_ptr(params), B, _ptr(x), _ptr(out), _ptr(ws), ws.numel(), _stream(torch, stream)))
+    return out
 
 
 def gqaoa_mlp_backward(params, act, dout, grads=None, stream=None):

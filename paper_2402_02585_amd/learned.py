@@ -45,8 +45,8 @@ class AngleMLP:
         self.step = 0
 
     def outputs(self, x):
-        out, _ = g.gqaoa_mlp_forward(self.params, x)
-        return out
+        """Raw outputs [B, 2] by the inference kernels (no activation cache)."""
+        return g.gqaoa_mlp_infer(self.params, x.contiguous())
 
     def angles(self, x):
         """(beta, gamma) numpy arrays: beta = 2 pi sigmoid(o0), gamma = pi sigmoid(o1)."""

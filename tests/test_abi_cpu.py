@@ -164,6 +164,11 @@ def test_mlp_argument_checks():
     assert lib.gqaoa_mlp_adam(d, d, d, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -2
     assert lib.gqaoa_mlp_adam(d, d, d, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -2
     assert lib.gqaoa_mlp_act_bytes(256) > 256 * 256 * 4
+    need = lib.gqaoa_mlp_infer_bytes(1000)
+    assert need >= 1000 * 256 * 2 and lib.gqaoa_mlp_infer_bytes(0) == 0
+    assert lib.gqaoa_mlp_infer(d, 0, d, d, d, need, None) == -2
+    assert lib.gqaoa_mlp_infer(d, 1000, None, d, d, need, None) == -1
+    assert lib.gqaoa_mlp_infer(d, 1000, d, d, d, need - 1, None) == -3
 
 
 def test_batched_cost_and_items_argument_checks():

@@ -69,6 +69,35 @@ def test_forward_backward_vs_oracle(B):
     assert not _unpack(grads, "W1")[131:].any() if _unpack(grads, "W1").shape[0] > 131 else True
 
 
+@pytest.mark.parametrize("B", [1, 37, 128, 129, 1000, 65536])
+def test_inference_matches_forward_and_oracle(B):
+    """The weights-stationary inference kernels against the training forward
+    (same bfloat16 activations: outputs within float32 rounding of the output
+    layer's 256-term sum) and, on small batches, against the oracle at the
+    forward's bar. Ragged batches leave a partial 128-row tile."""
+    torch = need_gpu()
+    params = _params32(7 + B)
+    rng = np.random.Generator(np.random.PCG64(100 + B))
+    x = (np.abs(rng.normal(size=(B, 131))) * 0.2).astype(np.float32)
+    prm = torch.tensor(_pack(params), device="cuda")
+    xd = torch.tensor(x, device="cuda")
+    out = torch.full((B + 1, 2), -7.0, device="cuda")      # one guard row past the batch
+    o_inf = g.gqaoa_mlp_infer(prm, xd, out=out[:B])
+    o_fwd, _ = g.gqaoa_mlp_forward(prm, xd)
+    a, b = o_inf.cpu().numpy(), o_fwd.cpu().numpy()
+    assert np.all(np.abs(a - b) <= 2e-6 * np.abs(b) + 1e-6), np.abs(a - b).max()
+    assert (out[B].cpu().numpy() == -7.0).all()
+    if B <= 1000:
+        o_ref, _ = ref.forward(params, x.astype(np.float64))
+        assert np.all(np.abs(a - o_ref) <= 1e-2 * np.abs(o_ref) + 1e-3), np.abs(a - o_ref).max()
+        # the same rows from a buffer whose first row is not 16-byte aligned
+        flat = torch.zeros(B * 131 + 1, dtype=torch.float32, device="cuda")
+        flat[1:] = xd.reshape(-1)
+        xm = flat[1:].view(B, 131)
+        assert xm.data_ptr() % 16 != 0
+        assert torch.equal(g.gqaoa_mlp_infer(prm, xm), o_inf)
+
+
 def test_adam_matches_oracle():
     torch = need_gpu()
     rng = np.random.Generator(np.random.PCG64(3))
