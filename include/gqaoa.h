@@ -222,12 +222,11 @@ int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_ho
  * protocol of Eq. (5) with (beta_host[k], gamma_host[k]) on instance
  * item_inst_host[k], whose cost table is in costs_dev at
  * gqaoa_cost_batched_offset(item_inst_host[k], n_host) (the layout written by
- * gqaoa_cost_batched), from |s>, complex64 state held in LDS, for
+ * gqaoa_cost_batched), from |s>, complex64 state held in registers, for
  * p_list[num_p-1] rounds, recording after each p in p_list (ascending)
  *   psol_dev  [k*num_p + q] = P_sol at target_host[inst] (NULL: level 0),
  *   energy_dev[k*num_p + q] = E of Eq. (4) (NULL to skip), both float.
- * Item instances need n <= GQAOA_SV_ITEMS_MAX_N and an LDS allocation of
- * 9 * 2^n + 2048 bytes per block on the device (ERANGE otherwise).
+ * Item instances need n <= GQAOA_SV_ITEMS_MAX_N (ERANGE otherwise).
  * Synchronizes the stream. Errors: EINVAL (NULL pointers, non-finite angles,
  * p_list not ascending), ERANGE (counts, n, m, targets, p values). */
 #define GQAOA_SV_ITEMS_MAX_N 14
@@ -260,7 +259,7 @@ int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host,
  * gqaoa_cost_batched), and writes item_psol_dev[k*num_p + q] (and
  * item_energy_dev, NULL to skip) after each p_list[q], the float values of
  * the scan's cell (i, q, g, b) computed without the level reduction. Item
- * instances need n <= GQAOA_SV_ITEMS_MAX_N and the LDS of gqaoa_sv_items.
+ * instances need n <= GQAOA_SV_ITEMS_MAX_N.
  * Synchronizes the stream. Errors: those of gqaoa_scan_batched and
  * gqaoa_sv_items, EINVAL for a NULL plan_out or an item cell outside the
  * grid, EHIP if the graph cannot be captured.

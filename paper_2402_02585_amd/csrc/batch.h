@@ -104,12 +104,8 @@ struct ItemOrder {
     std::vector<int> first;   // group boundaries, first.back() == num_items
 };
 
-size_t sv_items_lds_bytes(int n);
 int sv_items_order(const int32_t *n_host, int num_items, const int32_t *item_inst, const DeviceInfo &dev,
                    ItemOrder *out);
-// Raises the kernel's dynamic LDS limit for items of size n (before a
-// launch, outside graph capture).
-int sv_items_allow_lds(int n);
 // Launches one group: a.items points at the group's first item, a.n is the
 // group's n.
 int sv_items_launch(const SvItemsArgs &a, const DeviceInfo &dev, hipStream_t st);

@@ -5,8 +5,8 @@
 // Creating a plan does the per-instance work once: the occupied levels and
 // weights are compacted and uploaded, every bucket's launch shape is chosen
 // (tuned on the real queue), and the launches are captured in one HIP graph
-// with one parallel branch per scan bucket and one for the statevector items
-// (states in LDS), so both paths go out with a single hipGraphLaunch. A run
+// with one parallel branch per scan bucket and one per group of statevector
+// items (one group per n), so both paths go out with a single hipGraphLaunch. A run
 // then uploads only the angle grid and the items' angles (one copy from
 // pinned staging) and replays the graph. Every queue counter is cleared by a
 // kernel inside the graph, so the graph holds kernel nodes only.
@@ -34,7 +34,7 @@ struct ScanPlan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
-    std::vector<hipStream_t> branch;   // one per scan bucket, then one for the items
+    std::vector<hipStream_t> branch;   // one per scan bucket, then one per item group
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;      // one per branch
     hipEvent_t staged = nullptr;       // the last upload has read the staging
@@ -83,9 +83,9 @@ struct PlanGuard {
     }
 };
 
-// Enqueues every launch of the plan, each scan bucket and the items on a
-// branch of its own, forked from and joined back to `cap`: the buckets are
-// independent, so the tail of one overlaps the others.
+// Enqueues every launch of the plan, each scan bucket and each group of
+// items (one n) on a branch of its own, forked from and joined back to
+// `cap`: they are independent, so the tail of one overlaps the others.
 static int enqueue_all(ScanPlan *P, const DeviceInfo &dev, const std::vector<ScanArgs> &bucket_args,
                        const std::vector<int> &bucket_ids, const std::vector<TileChoice> &tiles,
                        unsigned int *counters, const std::vector<SvItemsArgs> &item_args) {
@@ -97,11 +97,10 @@ static int enqueue_all(ScanPlan *P, const DeviceInfo &dev, const std::vector<Sca
                                     P->branch[q])))
             return s;
     }
-    if (!item_args.empty()) {
-        hipStream_t side = P->branch[bucket_args.size()];
+    for (size_t q = 0; q < item_args.size(); ++q) {
+        hipStream_t side = P->branch[bucket_args.size() + q];
         GQ_HIP(hipStreamWaitEvent(side, P->fork, 0));
-        for (const SvItemsArgs &a : item_args)
-            if ((s = sv_items_launch(a, dev, side))) return s;
+        if ((s = sv_items_launch(item_args[q], dev, side))) return s;
     }
     for (size_t q = 0; q < P->branch.size(); ++q) {
         GQ_HIP(hipEventRecord(P->join[q], P->branch[q]));
@@ -233,11 +232,10 @@ int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host,
         for (int q = 0; q < num_p; ++q) ia.p_list[q] = p_list[q];
         ia.psol = item_psol;
         ia.energy = item_energy;
-        if ((s = sv_items_allow_lds(ia.n))) return s;
         item_args.push_back(ia);
     }
     GQ_HIP(hipStreamSynchronize(st));  // uploads and tuning done; host tables end here
-    const size_t nbranch = bucket_args.size() + (item_args.empty() ? 0 : 1);
+    const size_t nbranch = bucket_args.size() + item_args.size();
     for (size_t q = 0; q < nbranch; ++q) {
         hipStream_t b = nullptr;
         hipEvent_t e = nullptr;

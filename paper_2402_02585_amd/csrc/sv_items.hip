@@ -1,17 +1,19 @@
-// Statevector evaluation of single-angle-pair work items of small instances,
-// each state held in LDS: the independent statevector check of the batched
-// level-space scan (Eq. (5) evolved amplitude by amplitude instead of level
-// by level).
+// Statevector evaluation of single-angle-pair work items of small instances:
+// the independent statevector check of the batched level-space scan (Eq. (5)
+// evolved amplitude by amplitude instead of level by level).
 //
-// One block of 1024 threads per item (instance, beta, gamma). The instance's
-// cost table (from gqaoa_cost_batched) and the phase table e^{-i gamma k} are
-// staged in LDS beside the complex64 state. Round j is one sweep over the
-// state: it forms psi_{j-1} = phi_{j-1} + delta_{j-1} (the Grover mixer of
-// the previous round applied lazily, as in the streaming round pass), reads
-// out P_sol and E when j-1 is a requested round, applies the phase and sums
-// phi_j; one block reduction (float64) gives delta_j = (e^{-i beta} - 1) S_j / 2^n.
-// Each thread owns the same amplitudes in every round, so only the reduction
-// needs barriers.
+// One block per item (instance, beta, gamma), sized to the state, each
+// thread owning the same PER consecutive amplitudes in every round. Under the
+// single-angle-pair protocol the phase table e^{-i gamma k} is the same in
+// every round: it sits in LDS, the thread's amplitudes and their costs (four
+// to a register) stay in registers. Round j is one sweep over the thread's
+// amplitudes: it forms
+// psi_{j-1} = phi_{j-1} + delta_{j-1} (the Grover mixer of the previous round
+// applied lazily, as in the streaming round pass), reads out P_sol and E
+// when j-1 is a requested round, applies the phase and sums phi_j; one
+// reduction (float64) gives delta_j = (e^{-i beta} - 1) S_j / 2^n. The
+// reduction is the only exchange between threads (wave shuffles alone for a
+// one-wave block).
 #include "batch.h"
 
 #include <algorithm>
@@ -20,21 +22,46 @@
 
 namespace gqaoa {
 
-constexpr int kItemThreads = 1024;
+// Shape of a block for items of size n: one wave of PER = max(1, 2^n / 64)
+// amplitudes per lane up to n = 11 (its sums are pure wave reductions), then
+// 2^n / 32 threads of 32 amplitudes (fewer waves per item, so less
+// reduction work per amplitude).
+static int item_threads(int n) { return n <= 11 ? 64 : (1 << (n - 5)); }
 
-size_t sv_items_lds_bytes(int n) {
-    const size_t N = size_t(1) << n;
-    return 8 * N + ((N + 7) & ~size_t(7)) + 8 * 256;
+// PER cost bytes from p into cpk (byte i of the run in byte i % 4 of word i / 4).
+template <int PER>
+__device__ __forceinline__ void load_costs(const uint8_t *__restrict__ p, uint32_t (&cpk)[(PER + 3) / 4]) {
+    static_assert(PER == 1 || PER == 2 || PER == 4 || PER == 8 || PER % 16 == 0, "cost run length");
+    if constexpr (PER >= 4) {
+        if ((reinterpret_cast<uintptr_t>(p) & (PER >= 16 ? 15 : PER - 1)) == 0) {
+            if constexpr (PER >= 16) {
+#pragma unroll
+                for (int u = 0; u < PER / 16; ++u) {
+                    const uint4 v = reinterpret_cast<const uint4 *>(p)[u];
+                    cpk[4 * u] = v.x;
+                    cpk[4 * u + 1] = v.y;
+                    cpk[4 * u + 2] = v.z;
+                    cpk[4 * u + 3] = v.w;
+                }
+            } else if constexpr (PER == 8) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(p);
+                cpk[0] = v.x;
+                cpk[1] = v.y;
+            } else {
+                cpk[0] = *reinterpret_cast<const uint32_t *>(p);
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) cpk[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
 }
 
-__global__ void __launch_bounds__(kItemThreads) sv_items_kernel(SvItemsArgs a) {
-    extern __shared__ unsigned char smem[];
-    __shared__ double red_s[4 * kItemThreads / kWave];
-    __shared__ double bc_s[4];
+template <int THREADS, int PER>
+__global__ void __launch_bounds__(THREADS) sv_items_kernel(SvItemsArgs a) {
+    __shared__ float2 lut[256];
+    __shared__ double red_s[2][THREADS / kWave][4];  // per-wave sums, double-buffered by round parity
     const uint32_t N = 1u << a.n;
-    float2 *psi = reinterpret_cast<float2 *>(smem);
-    uint8_t *c = smem + 8 * (size_t)N;
-    float2 *lut = reinterpret_cast<float2 *>(smem + 8 * (size_t)N + ((N + 7) & ~7u));
     const int tid = threadIdx.x;
     const double invN = ldexp(1.0, -a.n);
     const float amp0 = (float)sqrt(invN);  // |s> = 2^(-n/2) on every z
@@ -42,10 +69,9 @@ __global__ void __launch_bounds__(kItemThreads) sv_items_kernel(SvItemsArgs a) {
     for (int item = blockIdx.x; item < a.num_items; item += gridDim.x) {
         const SvItem it = a.items[item];
         const uint8_t *src = a.costs + a.cost_off[it.inst];
-        for (uint32_t z = tid; z < N; z += kItemThreads) c[z] = src[z];
         const int m = a.m[it.inst];
         const uint32_t target = (uint32_t)a.target[it.inst];
-        for (int k = tid; k <= m; k += kItemThreads) {
+        for (int k = tid; k <= m; k += THREADS) {
             double s, co;
             sincos(fmod(it.gamma * (double)k, 2.0 * M_PI), &s, &co);
             lut[k] = float2{(float)co, (float)-s};
@@ -54,51 +80,109 @@ __global__ void __launch_bounds__(kItemThreads) sv_items_kernel(SvItemsArgs a) {
         sincos(it.beta, &sb, &cb);
         const double mr = cb - 1.0, mi = -sb;
         __syncthreads();
+        // this thread's amplitudes z = tid PER + i (a contiguous run): the
+        // state in registers, the costs packed four to a register (one
+        // vector load when aligned); the phase factor e^{-i gamma C(z)} is
+        // read from the LDS table each round. Only the one-amplitude shape
+        // (n <= 6) has lanes without amplitudes.
+        const bool owns = (uint32_t)tid * PER < N;
+        float2 xv[PER];
+        uint32_t cpk[(PER + 3) / 4];
+#pragma unroll
+        for (int w = 0; w < (PER + 3) / 4; ++w) cpk[w] = 0u;
+        if (owns) load_costs<PER>(src + (size_t)tid * PER, cpk);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) xv[i] = float2{amp0, 0.f};
         float dr = 0.f, di = 0.f;
         int q = 0;
         for (int j = 1; j <= pmax + 1; ++j) {
             const bool rd = q < a.num_p && a.p_list[q] == j - 1;
             const bool ph = j <= pmax;
             float sr = 0.f, si = 0.f, sp = 0.f, se = 0.f;
-            for (uint32_t z = tid; z < N; z += kItemThreads) {
-                float2 x = j == 1 ? float2{amp0, 0.f} : psi[z];
-                if (j > 1) {
-                    x.x += dr;
-                    x.y += di;
-                }
-                const uint32_t cz = c[z];
-                if (rd) {
-                    const float pr = x.x * x.x + x.y * x.y;
-                    sp += cz == target ? pr : 0.f;
-                    se += (float)cz * pr;
-                }
-                if (ph) {
-                    const float2 e = lut[cz];
-                    const float2 f{e.x * x.x - e.y * x.y, e.x * x.y + e.y * x.x};
-                    psi[z] = f;
-                    sr += f.x;
-                    si += f.y;
-                }
+            if (owns) {
+                if (j > 1)  // psi_{j-1} = phi_{j-1} + delta_{j-1}: the previous mixer, applied lazily
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) {
+                        xv[i].x += dr;
+                        xv[i].y += di;
+                    }
+                if (rd)
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) {
+                        const uint32_t cz = (cpk[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                        const float pr = xv[i].x * xv[i].x + xv[i].y * xv[i].y;
+                        sp += cz == target ? pr : 0.f;
+                        se += (float)cz * pr;
+                    }
+                if (ph)
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) {
+                        const uint32_t cz = (cpk[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                        const float2 e = lut[cz], x = xv[i];
+                        const float2 f{e.x * x.x - e.y * x.y, e.x * x.y + e.y * x.x};
+                        xv[i] = f;
+                        sr += f.x;
+                        si += f.y;
+                    }
             }
+            // S every round; P_sol and E only in the readout rounds
             double r[4] = {sr, si, sp, se};
-            block_sum<4, kItemThreads>(r, red_s);
-            if (tid == 0)
-                for (int k = 0; k < 4; ++k) bc_s[k] = r[k];
-            __syncthreads();
+            const int nq = rd ? 4 : 2;
+            if constexpr (THREADS == kWave) {
+                // xor-butterfly sums: every lane ends with the same totals
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < nq) r[k] = wave_sum(r[k]);
+            } else {
+                // wave sums, then a wave sum of the per-wave sums (the same
+                // fixed order in every wave, so identical totals in every
+                // thread). A buffer is rewritten two rounds later, after the
+                // next round's barrier, which every thread passes only once
+                // it has read this round's sums.
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < nq) r[k] = wave_sum(r[k]);
+                double(*buf)[4] = red_s[j & 1];
+                const int lane = tid & (kWave - 1);
+                if (lane == 0)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (k < nq) buf[tid / kWave][k] = r[k];
+                __syncthreads();
+                // lane w < waves takes wave w's sums, then one more wave sum
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (k < nq) r[k] = wave_sum(lane < THREADS / kWave ? buf[lane][k] : 0.0);
+            }
             if (rd) {
                 if (tid == 0) {
-                    a.psol[(size_t)it.out * a.num_p + q] = (float)bc_s[2];
-                    if (a.energy) a.energy[(size_t)it.out * a.num_p + q] = (float)bc_s[3];
+                    a.psol[(size_t)it.out * a.num_p + q] = (float)r[2];
+                    if (a.energy) a.energy[(size_t)it.out * a.num_p + q] = (float)r[3];
                 }
                 ++q;
             }
             if (ph) {
-                const double Sr = bc_s[0] * invN, Si = bc_s[1] * invN;
+                const double Sr = r[0] * invN, Si = r[1] * invN;
                 dr = (float)(mr * Sr - mi * Si);
                 di = (float)(mr * Si + mi * Sr);
             }
-            __syncthreads();  // bc_s is rewritten by the next reduction
         }
+        __syncthreads();  // every thread has read lut before the next item rewrites it
+    }
+}
+
+typedef void (*ItemsFn)(SvItemsArgs);
+static ItemsFn items_fn(int n) {
+    switch (n <= 6 ? 6 : n) {
+        case 6: return sv_items_kernel<64, 1>;
+        case 7: return sv_items_kernel<64, 2>;
+        case 8: return sv_items_kernel<64, 4>;
+        case 9: return sv_items_kernel<64, 8>;
+        case 10: return sv_items_kernel<64, 16>;
+        case 11: return sv_items_kernel<64, 32>;
+        case 12: return sv_items_kernel<128, 32>;
+        case 13: return sv_items_kernel<256, 32>;
+        default: return sv_items_kernel<512, 32>;
     }
 }
 
@@ -106,12 +190,10 @@ uint64_t batched_cost_offset(int i, const int32_t *n_host);
 
 int sv_items_order(const int32_t *n_host, int num_items, const int32_t *item_inst, const DeviceInfo &dev,
                    ItemOrder *out) {
-    for (int k = 0; k < num_items; ++k) {
-        const size_t need = sv_items_lds_bytes(n_host[item_inst[k]]);
-        if (need > dev.lds_per_block)
-            return fail(GQAOA_ERANGE, "item %d: n=%d needs %zu bytes of LDS, the device offers %zu per block", k,
-                        n_host[item_inst[k]], need, dev.lds_per_block);
-    }
+    (void)dev;
+    for (int k = 0; k < num_items; ++k)
+        if (n_host[item_inst[k]] > GQAOA_SV_ITEMS_MAX_N)
+            return fail(GQAOA_ERANGE, "item %d: n=%d > %d", k, n_host[item_inst[k]], GQAOA_SV_ITEMS_MAX_N);
     out->order.resize(num_items);
     for (int k = 0; k < num_items; ++k) out->order[k] = k;
     std::stable_sort(out->order.begin(), out->order.end(),
@@ -123,19 +205,15 @@ int sv_items_order(const int32_t *n_host, int num_items, const int32_t *item_ins
     return GQAOA_OK;
 }
 
-int sv_items_allow_lds(int n) {
-    const size_t lds = sv_items_lds_bytes(n);
-    if (lds > 65536)
-        GQ_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(sv_items_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    return GQAOA_OK;
-}
-
 int sv_items_launch(const SvItemsArgs &a, const DeviceInfo &dev, hipStream_t st) {
-    const size_t lds = sv_items_lds_bytes(a.n);
-    const int per_cu = std::max<int>(1, (int)std::min<size_t>(2, dev.lds_per_block / std::max<size_t>(lds, 1)));
-    const int blocks = std::min(a.num_items, dev.num_cus * per_cu);
-    hipLaunchKernelGGL(sv_items_kernel, dim3(blocks), dim3(kItemThreads), lds, st, a);
+    const int threads = item_threads(a.n);
+    const ItemsFn fn = items_fn(a.n);
+    // exactly the blocks that are resident at once (each takes items in a
+    // grid-stride loop, so a second wave of blocks would only wait)
+    int per_cu = 0;
+    GQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), threads, 0));
+    const int blocks = std::min(a.num_items, dev.num_cus * std::max(1, per_cu));
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), 0, st, a);
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
 }
@@ -184,7 +262,7 @@ int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, con
         for (int q = 0; q < num_p; ++q) a.p_list[q] = p_list[q];
         a.psol = psol;
         a.energy = energy;
-        if ((s = sv_items_allow_lds(a.n)) || (s = sv_items_launch(a, dev, st))) return s;
+        if ((s = sv_items_launch(a, dev, st))) return s;
     }
     GQ_HIP(hipStreamSynchronize(st));  // the host tables above end with this call
     return GQAOA_OK;

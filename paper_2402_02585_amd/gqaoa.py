@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgqaoa.so")
 
 C64, C128 = 0, 1
-SV_ITEMS_MAX_N = 14          # GQAOA_SV_ITEMS_MAX_N: largest n of a statevector work item (state in LDS)
+SV_ITEMS_MAX_N = 14          # GQAOA_SV_ITEMS_MAX_N: largest n of a statevector work item (state in registers)
 MLP_NPARAMS = 160 * 256 + 256 + 256 * 256 + 256 + 256 * 2 + 2
 MLP_OFFSETS = {"W1": (0, (160, 256)), "b1": (40960, (256,)), "W2": (41216, (256, 256)),
                "b2": (106752, (256,)), "W3": (107008, (256, 2)), "b3": (107520, (2,))}

@@ -1,8 +1,9 @@
 """Batched cost tables and the statevector work items of the batched scan,
 against the oracle: tables bit-exact (every size class, n < 5 included);
 item P_sol and E against the oracle's complex128 statevector evolution
-(float32 state in LDS, 1e-5), including Max-SAT targets and the n = 14 LDS
-limit; and the level-space scan of the same items within 1e-5."""
+(float32 state, 1e-5), including Max-SAT targets, every block shape (n = 3
+to 14) and the n = 14 limit; and the level-space scan of the same items
+within 1e-5."""
 import numpy as np
 import pytest
 
@@ -76,9 +77,32 @@ def test_items_match_oracle_statevector(unsat):
         assert np.abs(sp.cpu().numpy().reshape(len(pool), -1) - ps[sel]).max() < 1e-5
 
 
-def test_items_at_the_lds_limit():
-    """n = 14: a 128 KiB state, the 16 KiB cost table and the phase table in
-    one block's LDS."""
+def test_items_every_block_shape():
+    """One instance for every n from 3 to 14: one-wave blocks with 1 to 16
+    amplitudes per lane (n <= 6 leaves lanes without amplitudes) and blocks
+    of 128 to 1024 threads, against the oracle's statevector."""
+    need_gpu()
+    its = _set(50, list(range(3, 15)))
+    ns = [n for n, _ in its]
+    ms = [l.shape[0] for _, l in its]
+    costs, _, _ = g.gqaoa_cost_batched(ns, ms, [l for _, l in its], with_hist=False)
+    rng = np.random.Generator(np.random.PCG64(51))
+    item_inst = np.repeat(np.arange(len(its)), 3)
+    beta = rng.uniform(0, 2 * np.pi, item_inst.size)
+    gamma = rng.uniform(0, np.pi, item_inst.size)
+    refc = [cost_table(n, l) for n, l in its]
+    targets = [min_level(level_histogram(c, m)) for c, m in zip(refc, ms)]
+    log(f"sv items n=3..14: {item_inst.size} items")
+    ps, en = g.gqaoa_sv_items(ns, ms, costs, item_inst, beta, gamma, P_LIST, targets=targets, with_energy=True)
+    ps, en = ps.cpu().numpy(), en.cpu().numpy()
+    for k, i in enumerate(item_inst):
+        _, rp, re, _ = evolve_sv(ns[i], refc[i], np.full(64, beta[k]), np.full(64, gamma[k]), target=targets[i])
+        assert np.abs(ps[k] - rp[P_LIST]).max() < 1e-5, (ns[i], ps[k], rp[P_LIST])
+        assert np.abs(en[k] - re[P_LIST]).max() / ms[i] < 1e-5, ns[i]
+
+
+def test_items_at_the_size_limit():
+    """n = 14, the largest item: 1024 threads of 16 register-held amplitudes."""
     need_gpu()
     n, m = 14, 59
     lits = rand_lits(n, m, 46)
