@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from gpu_common import log, need_gpu
-from oracle.cost import cost_table, level_histogram
+from oracle.cost import cost_table, level_histogram, min_level
 from oracle.evolve import evolve_hist
 from paper_2402_02585_amd import gqaoa as g
 from paper_2402_02585_amd import instances as inst
@@ -123,3 +123,38 @@ def test_plan_without_items_and_async_runs():
     finally:
         plan.close()
     plan.close()                                     # closing twice is harmless
+
+
+def test_plan_maxsat_targets():
+    """Unsatisfiable instances with the target at k_min (Max-SAT): the plan's
+    scan and items read out the target level, as the eager calls do."""
+    torch = need_gpu()
+    its = inst.batched_scan_instances(65, 24, 6, 14, want="unsat", density_range=(4.6, 8.0), dup="drop")
+    ns = [it.n for it in its]
+    ms = [it.m for it in its]
+    H = np.zeros((len(its), max(ms) + 1), dtype=np.uint64)
+    for i, it in enumerate(its):
+        H[i, :it.m + 1] = level_histogram(cost_table(it.n, it.lits), it.m)
+    tg = [min_level(H[i, :ms[i] + 1]) for i in range(len(its))]
+    assert min(tg) > 0
+    rng = np.random.Generator(np.random.PCG64(66))
+    nb, ng = 33, 6
+    b, gm = _grid(rng, nb, ng)
+    items = _items(ns, nb, ng, rng, per=2)
+    costs, off, _ = g.gqaoa_cost_batched(ns, ms, [it.lits for it in its], with_hist=False)
+    plan = g.ScanPlan(ns, ms, H, b, gm, P_LIST, targets=tg, items=items, costs=costs, cost_off=off[:-1])
+    try:
+        plan.run()
+        ref_p, ref_e = g.gqaoa_scan_batched(ns, ms, H, b, gm, P_LIST, targets=tg)
+        ii = items[:, 0]
+        ref_ip, _ = g.gqaoa_sv_items(ns, ms, costs, ii, b[items[:, 2]], gm[items[:, 1]], P_LIST, targets=tg)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.psol, ref_p) and torch.equal(plan.energy, ref_e)
+        assert torch.equal(plan.item_psol, ref_ip)
+        ps = plan.psol.cpu().numpy()
+        for i in range(0, len(its), 5):
+            _, rp, _, _ = evolve_hist(H[i, :ms[i] + 1], np.full(P_LIST[-1], b[3]), np.full(P_LIST[-1], gm[2]),
+                                      target=tg[i])
+            assert np.abs(ps[i, :, 2, 3] - rp[P_LIST]).max() < 1e-4
+    finally:
+        plan.close()
