@@ -407,6 +407,37 @@ def xqaoa_leg(torch, g, inst, it, reps: int = 3):
     }
 
 
+def small_n_leg(torch, g, inst, calls: int = 200):
+    """Launch-bound statevector calls: one instance evolved again and again
+    with new angles, through the eager gqaoa_evolve and through a
+    graph-captured plan (one hipGraphLaunch per call)."""
+    out = {}
+    for n, m, p, dt, name in ((10, 42, 20, g.C128, "n10_p20_c128"), (14, 59, 64, g.C64, "n14_p64_c64")):
+        it = inst.first_satisfiable(1, n, m)
+        cost, _ = g.gqaoa_cost_table(n, it.lits)
+        angles = [inst.uniform_angles(200 + k, p) for k in range(calls)]
+        psi = torch.empty(1 << n, dtype=torch.complex64 if dt == g.C64 else torch.complex128, device="cuda")
+        ws = torch.empty(g.gqaoa_workspace_bytes(n, p, dt), dtype=torch.uint8, device="cuda")
+        g.gqaoa_evolve(n, m, cost, *angles[0], dtype=dt, psi=psi, workspace=ws)
+        t0 = time.perf_counter()
+        for b, gm in angles:
+            ps_e = g.gqaoa_evolve(n, m, cost, b, gm, dtype=dt, psi=psi, workspace=ws)[1]
+        t_e = (time.perf_counter() - t0) / calls
+        plan = g.EvolvePlan(n, m, cost, p, dtype=dt)
+        plan.run(*angles[0])
+        t0 = time.perf_counter()
+        for b, gm in angles:
+            ps_g = plan.run(b, gm)[0]
+        t_g = (time.perf_counter() - t0) / calls
+        plan.close()
+        out[name] = {"eager_ms_per_call": t_e * 1e3, "graph_ms_per_call": t_g * 1e3, "speedup": t_e / t_g,
+                     "last_call_max_abs_psol_diff": float(np.abs(ps_g - ps_e).max()),
+                     "round_ms_graph": t_g * 1e3 / p}
+    out["workload"] = ("one satisfiable instance (seed 1) per size, a new set of p independent angle pairs per call "
+                       f"({calls} calls), readouts returned to the host every call")
+    return out
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -513,6 +544,7 @@ def main():
     ap.add_argument("--skip-x", action="store_true", help="omit the X-QAOA leg")
     ap.add_argument("--skip-rounds", action="store_true", help="omit the rounds-to-target leg")
     ap.add_argument("--skip-mlp", action="store_true", help="omit the angle-MLP leg")
+    ap.add_argument("--skip-small", action="store_true", help="omit the small-n eager vs graph leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
@@ -621,6 +653,8 @@ def main():
         out["rounds_to_target"] = rounds_leg(torch, g, inst)
     if not args.skip_mlp:
         out["mlp"] = mlp_leg(torch, g)
+    if not args.skip_small:
+        out["small_n_graph"] = small_n_leg(torch, g, inst)
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

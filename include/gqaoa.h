@@ -128,6 +128,29 @@ int gqaoa_evolve_x(int n, int m, const uint8_t *cost_dev, int p, const double *b
                    int target_level, double *psol_host, double *energy_host,
                    double *norm_host, void *ws_dev, size_t ws_bytes, void *stream);
 
+/* Graph-captured form of gqaoa_evolve for callers that evolve one instance
+ * many times with new angles (angle searches, where at small n each round is
+ * a few microseconds and launch overhead dominates): create captures the
+ * whole call (device-side angle tables, p >= 1 rounds, final readout) into
+ * one HIP graph; each run uploads the 2p angles, replays it and returns the
+ * readouts as gqaoa_evolve does (synchronizes the stream). Arguments of
+ * create as gqaoa_evolve (workspace: gqaoa_workspace_bytes(n, p, dtype, 0));
+ * cost_dev, psi_dev and ws_dev must stay valid while the plan lives. With
+ * init_uniform = 1 every run starts from |s>; with 0, from psi's contents,
+ * which a run overwrites with its final state. Runs of one plan come from
+ * one host thread at a time. The results equal gqaoa_evolve's up to the last
+ * bit of the phase tables (device vs host float64 sin/cos).
+ * Errors: as gqaoa_evolve, ERANGE for p < 1, EINVAL for a NULL plan_out or
+ * angles, non-finite angles, or another device current at a run. */
+typedef struct gqaoa_evolve_plan gqaoa_evolve_plan;
+int gqaoa_evolve_plan_create(int n, int m, const uint8_t *cost_dev, int p, int dtype,
+                             int init_uniform, void *psi_dev, int target_level, void *ws_dev,
+                             size_t ws_bytes, void *stream, gqaoa_evolve_plan **plan_out);
+int gqaoa_evolve_plan_run(gqaoa_evolve_plan *plan, const double *beta_host,
+                          const double *gamma_host, double *psol_host, double *energy_host,
+                          double *norm_host, void *stream);
+void gqaoa_evolve_plan_destroy(gqaoa_evolve_plan *plan);
+
 /* Solution probability of a given state (the readout of Sec. III, P_sol):
  * *out_host = sum over z with C(z) = target_level of |psi_z|^2.
  * ws: gqaoa_workspace_bytes(n, 0, dtype, 0) bytes. */

@@ -34,6 +34,12 @@ int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const u
              int num_p, const int32_t *p_list, float *psol, float *energy, float threshold, int32_t *first_p,
              const int32_t *pmax_host, const int32_t *tile, void *ws, hipStream_t st);
 size_t x_workspace_bytes(int n, int p, int dtype);
+struct EvolvePlan;
+int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int init_uniform, void *psi, int target,
+                       void *ws, hipStream_t st, EvolvePlan **out);
+int evolve_plan_run(EvolvePlan *E, const double *beta, const double *gamma, double *psol, double *energy,
+                    double *norm, hipStream_t st);
+void evolve_plan_destroy(EvolvePlan *E);
 struct ScanPlan;
 int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
                      int hist_stride, const int32_t *target_host, int nb, const double *betas, int ng,
@@ -104,6 +110,8 @@ bool prof_on() { return g_prof_on; }
 
 ProfScope::ProfScope(const char *name, hipStream_t st) : name_(name), st_(st) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;  // no event nodes in captured graphs
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         bool sample = true;
@@ -286,6 +294,38 @@ int gqaoa_evolve(int n, int m, const uint8_t *cost_dev, int p, const double *bet
     return run_evolve(n, m, cost_dev, p, beta_host, gamma_host, dtype, init_uniform, psi_dev, target_level, psol_host,
                       energy_host, norm_host, ws_dev, (hipStream_t)stream);
 }
+
+int gqaoa_evolve_plan_create(int n, int m, const uint8_t *cost_dev, int p, int dtype, int init_uniform,
+                             void *psi_dev, int target_level, void *ws_dev, size_t ws_bytes, void *stream,
+                             gqaoa_evolve_plan **plan_out) {
+    clear_error();
+    if (!plan_out) return fail(GQAOA_EINVAL, "NULL plan_out");
+    *plan_out = nullptr;
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (m < 1 || m > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "m=%d outside [1, 255]", m);
+    if (p < 1 || p > kMaxP) return fail(GQAOA_ERANGE, "p=%d outside [1, %d]", p, kMaxP);
+    if (target_level < 0 || target_level > m) return fail(GQAOA_ERANGE, "target_level=%d outside [0, m]", target_level);
+    if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
+    if (!cost_dev || !psi_dev || !ws_dev) return fail(GQAOA_EINVAL, "NULL cost_dev, psi_dev or ws_dev");
+    const size_t need = sv_workspace_bytes(1, n, p, dtype, 0, false);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    EvolvePlan *E = nullptr;
+    int s = evolve_plan_create(n, m, cost_dev, p, dtype, init_uniform ? 1 : 0, psi_dev, target_level, ws_dev,
+                               (hipStream_t)stream, &E);
+    if (s) return s;
+    *plan_out = reinterpret_cast<gqaoa_evolve_plan *>(E);
+    return GQAOA_OK;
+}
+
+int gqaoa_evolve_plan_run(gqaoa_evolve_plan *plan, const double *beta_host, const double *gamma_host,
+                          double *psol_host, double *energy_host, double *norm_host, void *stream) {
+    clear_error();
+    if (!plan || !beta_host || !gamma_host) return fail(GQAOA_EINVAL, "NULL plan or angles");
+    return evolve_plan_run(reinterpret_cast<EvolvePlan *>(plan), beta_host, gamma_host, psol_host, energy_host,
+                           norm_host, (hipStream_t)stream);
+}
+
+void gqaoa_evolve_plan_destroy(gqaoa_evolve_plan *plan) { evolve_plan_destroy(reinterpret_cast<EvolvePlan *>(plan)); }
 
 size_t gqaoa_x_workspace_bytes(int n, int p, int dtype) {
     if (n < GQAOA_MIN_N || n > GQAOA_MAX_N || p < 0 || p > kMaxP || !dtype_ok(dtype)) return 0;

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <new>
 #include <vector>
 
 namespace gqaoa {
@@ -649,7 +650,7 @@ static void launch_rev(int dtype, bool first, bool write, const PassShape &s, in
 // ---- workspace layout ---------------------------------------------------------------
 // Small tables first (per instance), then the state slots used by the adjoint.
 struct SvLayout {
-    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, target, counter, partials;
+    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, angles, target, counter, partials;
     size_t slots, slot_bytes, nslots, total;
 };
 
@@ -672,6 +673,7 @@ static SvLayout sv_layout(int num_inst, int n, int p, int dtype, int ckpt_every,
     L.eps = o;      o += al256(I * 16);
     L.dbeta = o;    o += al256(I * P * 8);
     L.dgamma = o;   o += al256(I * P * 8);
+    L.angles = o;   o += al256(I * P * 16);   // beta[p] then gamma[p], uploaded by graph-plan runs
     L.target = o;   o += al256(I * 4);
     L.counter = o;  o += al256(I * 4);
     L.partials = o; o += al256(std::max<size_t>(kMaxPassBlocks, I) * kFwdR * 8);
@@ -746,6 +748,7 @@ struct FwdPlan {
     SvLayout L;
     PassShape shape;
     const uint8_t *cost;
+    int fuse_mode = 0;  // 0: the GQAOA_SV_FUSE switch decides, 1: fused when the shape allows, -1: never
 };
 
 static FwdArgs base_fwd_args(const FwdPlan &P) {
@@ -780,8 +783,11 @@ static FinArgs base_fin_args(const FwdPlan &P) {
 // bandwidth than the separate finalize launch saves (0.99 vs 0.75 ms per
 // round at n = 28, complex64).
 static bool fused_round(const FwdPlan &P) {
-    const char *e = getenv("GQAOA_SV_FUSE");
-    if (!e || e[0] != '1') return false;
+    if (P.fuse_mode < 0) return false;
+    if (P.fuse_mode == 0) {
+        const char *e = getenv("GQAOA_SV_FUSE");
+        if (!e || e[0] != '1') return false;
+    }
     const PassShape &s = P.shape;
     return s.unroll == 8 && s.nt == 1 && s.amp == (P.dtype == GQAOA_C64 ? 2 : 1);
 }
@@ -1029,6 +1035,151 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
             if (dbeta) dbeta[(size_t)i * p + k] = db[(size_t)i * p + k];
             if (dgamma) dgamma[(size_t)i * p + k] = dg[(size_t)i * p + k];
         }
+    }
+    return GQAOA_OK;
+}
+
+// ---- graph-captured evolution ------------------------------------------------------------
+// For callers that evolve one instance many times with new angles (angle
+// searches at small n, where each round pass is a few microseconds and the
+// launches dominate): the whole call — angle tables, p round passes with
+// their finalizes, the final readout pass — is captured once into a HIP
+// graph. A run uploads the 2p angles, replays the graph and reads back the
+// readouts; the tables are computed on the device from the angles, with the
+// same float64 reduction and rounding as the host tables of run_evolve. A
+// state of at most 64 MB takes the fused round pass (one launch per round).
+template <typename T>
+__global__ void __launch_bounds__(256) evolve_tables_kernel(const double *__restrict__ ang, int p, int m,
+                                                            T *__restrict__ lut, double *__restrict__ mixf) {
+    const int j = blockIdx.x, k = threadIdx.x;
+    T re = 0, im = 0;
+    if (k <= m) {
+        double sn, cs;
+        sincos(fmod(ang[p + j] * (double)k, 2.0 * M_PI), &sn, &cs);
+        re = (T)cs;
+        im = (T)-sn;
+    }
+    lut[2 * ((size_t)j * 256 + k)] = re;
+    lut[2 * ((size_t)j * 256 + k) + 1] = im;
+    if (k == 0) {
+        double sb, cb;
+        sincos(ang[j], &sb, &cb);
+        mixf[2 * j] = cb - 1.0;
+        mixf[2 * j + 1] = -sb;
+    }
+}
+
+struct EvolvePlan {
+    FwdPlan P;
+    int device = -1, m = 0;
+    double *stage = nullptr;  // pinned: angles [2p], then readouts [(p+1) * 3]
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+void evolve_plan_destroy(EvolvePlan *E) {
+    if (!E) return;
+    if (E->exec) (void)hipGraphExecDestroy(E->exec);
+    if (E->graph) (void)hipGraphDestroy(E->graph);
+    if (E->cap) (void)hipStreamDestroy(E->cap);
+    if (E->stage) (void)hipHostFree(E->stage);
+    delete E;
+}
+
+struct EvolvePlanGuard {
+    EvolvePlan *e;
+    hipStream_t st;
+    ~EvolvePlanGuard() {
+        if (!e) return;
+        (void)hipStreamSynchronize(st);
+        evolve_plan_destroy(e);
+    }
+};
+
+static int enqueue_evolve(EvolvePlan *E, int init_uniform, void *psi, hipStream_t st) {
+    FwdPlan &P = E->P;
+    const double *ang = reinterpret_cast<const double *>(P.ws + P.L.angles);
+    double *mixf = reinterpret_cast<double *>(P.ws + P.L.mixf);
+    if (P.dtype == GQAOA_C64)
+        hipLaunchKernelGGL(evolve_tables_kernel<float>, dim3(P.p), dim3(256), 0, st, ang, P.p, E->m,
+                           reinterpret_cast<float *>(P.ws + P.L.lut), mixf);
+    else
+        hipLaunchKernelGGL(evolve_tables_kernel<double>, dim3(P.p), dim3(256), 0, st, ang, P.p, E->m,
+                           reinterpret_cast<double *>(P.ws + P.L.lut), mixf);
+    GQ_LAUNCH_CHECK();
+    int s;
+    for (int j = 1; j <= P.p; ++j)
+        if ((s = forward_round(P, j, psi, psi, init_uniform && j == 1, true, st))) return s;
+    return final_pass(P, psi, psi, false, true, st);
+}
+
+int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int init_uniform, void *psi, int target,
+                       void *ws, hipStream_t st, EvolvePlan **out) {
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    EvolvePlanGuard G{new (std::nothrow) EvolvePlan, st};
+    if (!G.e) return fail(GQAOA_EINVAL, "out of host memory");
+    EvolvePlan *E = G.e;
+    E->device = dev.device;
+    E->m = m;
+    FwdPlan &P = E->P;
+    P.dtype = dtype;
+    P.num_inst = 1;
+    P.n = n;
+    P.p = p;
+    P.N = 1ull << n;
+    P.ws = reinterpret_cast<char *>(ws);
+    P.L = sv_layout(1, n, p, dtype, 0, false);
+    P.shape = pass_shape(P.N, 1, dtype, dev);
+    P.cost = cost;
+    // One launch per round: the finalize folded into the round pass when the
+    // state stays in the last-level cache (at most 64 MB), where the pass's
+    // release fence is cheap; its counter is cleared here once and by the
+    // finalizing block after every round.
+    const size_t state_bytes = ((size_t)1 << n) * (dtype == GQAOA_C64 ? 8 : 16);
+    P.fuse_mode = state_bytes <= (size_t(64) << 20) ? 1 : -1;
+    GQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&E->stage), sizeof(double) * (2 * (size_t)p + 3 * ((size_t)p + 1)),
+                         hipHostMallocDefault));
+    GQ_HIP(hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking));
+    const int32_t tg = target;
+    GQ_HIP(hipMemcpyAsync(P.ws + P.L.target, &tg, 4, hipMemcpyHostToDevice, st));
+    GQ_HIP(hipMemsetAsync(P.ws + P.L.counter, 0, 4, st));  // outside the graph
+    GQ_HIP(hipStreamSynchronize(st));  // tg ends here; the captured work reads the target from the workspace
+    GQ_HIP(hipStreamBeginCapture(E->cap, hipStreamCaptureModeThreadLocal));
+    s = enqueue_evolve(E, init_uniform, psi, E->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(E->cap, &graph);
+    E->graph = graph;
+    if (s) return s;
+    GQ_HIP(e_end);
+    GQ_HIP(hipGraphInstantiate(&E->exec, E->graph, nullptr, nullptr, 0));
+    *out = E;
+    G.e = nullptr;
+    return GQAOA_OK;
+}
+
+int evolve_plan_run(EvolvePlan *E, const double *beta, const double *gamma, double *psol, double *energy,
+                    double *norm, hipStream_t st) {
+    int cur = -1;
+    GQ_HIP(hipGetDevice(&cur));
+    if (cur != E->device) return fail(GQAOA_EINVAL, "plan made on device %d, current device is %d", E->device, cur);
+    const int p = E->P.p;
+    for (int j = 0; j < p; ++j)
+        if (!std::isfinite(beta[j]) || !std::isfinite(gamma[j])) return fail(GQAOA_EINVAL, "non-finite angle in round %d", j + 1);
+    double *ang = E->stage, *ro = E->stage + 2 * (size_t)p;
+    std::copy(beta, beta + p, ang);
+    std::copy(gamma, gamma + p, ang + p);
+    const FwdPlan &P = E->P;
+    GQ_HIP(hipMemcpyAsync(P.ws + P.L.angles, ang, 16 * (size_t)p, hipMemcpyHostToDevice, st));
+    GQ_HIP(hipGraphLaunch(E->exec, st));
+    GQ_HIP(hipMemcpyAsync(ro, P.ws + P.L.readout, 24 * ((size_t)p + 1), hipMemcpyDeviceToHost, st));
+    GQ_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j <= p; ++j) {
+        if (psol) psol[j] = ro[3 * j];
+        if (energy) energy[j] = ro[3 * j + 1];
+        if (norm) norm[j] = ro[3 * j + 2];
     }
     return GQAOA_OK;
 }

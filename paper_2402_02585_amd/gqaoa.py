@@ -37,6 +37,9 @@ _SIGS = {
     "gqaoa_sv_items": ([_i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_workspace_bytes": ([_i32, _i32, _i32, _i32], _sz),
     "gqaoa_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_evolve_plan_create": ([_i32, _i32, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _sz, _vp, _vp], _i32),
+    "gqaoa_evolve_plan_run": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_evolve_plan_destroy": ([_vp], None),
     "gqaoa_solution_prob": ([_i32, _vp, _vp, _i32, _i32, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_x_workspace_bytes": ([_i32, _i32, _i32], _sz),
     "gqaoa_evolve_x": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
@@ -252,6 +255,52 @@ def gqaoa_evolve(n: int, m: int, cost, betas, gammas, dtype=C64, psi=None, init_
                             target_level, _np_ptr(psol), _np_ptr(energy), _np_ptr(norm), _ptr(ws),
                             ws.numel(), _stream(torch, stream)))
     return psi, psol, energy, norm
+
+
+class EvolvePlan:
+    """Graph-captured gqaoa_evolve (gqaoa_evolve_plan_*) for one instance and a
+    fixed p: each run(betas, gammas) uploads the angles, replays the graph and
+    returns (psol, energy, norm) numpy arrays [p+1]; the final state is left
+    in ``psi``. The plan holds the cost table, state and workspace tensors."""
+
+    def __init__(self, n: int, m: int, cost, p: int, dtype=C64, init_uniform: bool = True, target_level: int = 0,
+                 psi=None, stream=None):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self._handle = ctypes.c_void_p()
+        self.p = int(p)
+        dt = _dtype_code(dtype)
+        _, _, psi = _state_args(torch, n, cost, np.zeros(self.p), np.zeros(self.p), dt, psi)
+        self.psi, self.cost = psi, cost
+        self.workspace = _workspace(torch, lib.gqaoa_workspace_bytes(n, self.p, dt, 0))
+        _check(lib.gqaoa_evolve_plan_create(n, m, _ptr(cost), self.p, dt, int(bool(init_uniform)), _ptr(psi),
+                                            target_level, _ptr(self.workspace), self.workspace.numel(),
+                                            _stream(torch, stream), ctypes.byref(self._handle)))
+
+    def run(self, betas, gammas, stream=None):
+        torch = _torch()
+        b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).ravel())
+        g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).ravel())
+        if b.size != self.p or g.size != self.p:
+            raise ValueError(f"the plan runs p={self.p} rounds: {b.size} betas, {g.size} gammas given")
+        if not self._handle:
+            raise GQAOAError(-1, "plan already closed")
+        psol, energy, norm = np.empty(self.p + 1), np.empty(self.p + 1), np.empty(self.p + 1)
+        _check(self._lib.gqaoa_evolve_plan_run(self._handle, _np_ptr(b), _np_ptr(g), _np_ptr(psol), _np_ptr(energy),
+                                               _np_ptr(norm), _stream(torch, stream)))
+        return psol, energy, norm
+
+    def close(self):
+        if self._handle:
+            self._lib.gqaoa_evolve_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def gqaoa_x_workspace_bytes(n: int, p: int, dtype=C64) -> int:

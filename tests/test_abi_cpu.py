@@ -195,6 +195,21 @@ def test_batched_cost_and_items_argument_checks():
                               g._np_ptr(b), 2, g._np_ptr(bad), d, None, None) == -1
 
 
+def test_evolve_plan_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    out = ctypes.c_void_p()
+    need = lib.gqaoa_workspace_bytes(10, 4, 0, 0)
+    assert lib.gqaoa_evolve_plan_create(10, 42, d, 4, 0, 1, d, 0, d, need, None, None) == -1        # no plan_out
+    assert lib.gqaoa_evolve_plan_create(10, 42, d, 0, 0, 1, d, 0, d, need, None, ctypes.byref(out)) == -2   # p = 0
+    assert lib.gqaoa_evolve_plan_create(10, 42, d, 4, 0, 1, d, 43, d, need, None, ctypes.byref(out)) == -2  # target > m
+    assert lib.gqaoa_evolve_plan_create(10, 42, d, 4, 2, 1, d, 0, d, need, None, ctypes.byref(out)) == -1   # dtype
+    assert lib.gqaoa_evolve_plan_create(10, 42, d, 4, 0, 1, d, 0, d, need - 1, None, ctypes.byref(out)) == -3
+    assert not out.value
+    assert lib.gqaoa_evolve_plan_run(None, d, d, None, None, None, None) == -1
+    lib.gqaoa_evolve_plan_destroy(None)
+
+
 def test_scan_plan_argument_checks():
     lib = g.load_library()
     d = ctypes.c_void_p(16)

@@ -1,0 +1,75 @@
+"""GPU: the graph-captured evolution (gqaoa_evolve_plan_*) against the eager
+gqaoa_evolve and the oracle.
+
+The plan computes its phase tables on the device (float64 sin/cos, then the
+state's precision), the eager call on the host, so the two can differ in the
+last bit of a table entry: the bar between them is 1e-12 (complex128) and
+1e-6 (complex64) on every readout and amplitude. Against the oracle the bars
+of the statevector tests hold (1e-12 and 1e-5). Replays are interleaved with
+eager calls and synchronizations, with new angles each time, and the readout
+arrays are refilled before each run so a stale value cannot pass.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import log, need_gpu, rand_lits
+from oracle.cost import cost_table
+from oracle.evolve import evolve_sv
+from paper_2402_02585_amd import gqaoa as g
+from paper_2402_02585_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,m,p,dtype,tol,otol", [(10, 42, 20, g.C128, 1e-12, 1e-12), (16, 67, 64, g.C64, 1e-6, 1e-5),
+                                                  (6, 20, 7, g.C128, 1e-12, 1e-12)])
+def test_plan_matches_eager_and_oracle(n, m, p, dtype, tol, otol):
+    torch = need_gpu()
+    lits = rand_lits(n, m, 70 + n)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    ref_cost = cost_table(n, lits)
+    target = int(np.min(ref_cost))                    # the lowest occupied level (0 when satisfiable)
+    plan = g.EvolvePlan(n, m, cost, p, dtype=dtype, target_level=target)
+    try:
+        for rep in range(3):
+            b, gm = inst.uniform_angles(80 + rep, p)
+            psi_e, pe, ee, ne = g.gqaoa_evolve(n, m, cost, b, gm, dtype=dtype, target_level=target)
+            torch.cuda.synchronize()
+            plan.psi.fill_(0)
+            ps, en, no = plan.run(b, gm)
+            log(f"evolve plan n={n} p={p} dtype={dtype} replay {rep}")
+            for x, y in ((ps, pe), (en, ee), (no, ne)):
+                assert np.abs(x - y).max() <= tol * max(1.0, np.abs(y).max())
+            assert float((plan.psi - psi_e).abs().max()) <= tol
+            _, rp, re, rn = evolve_sv(n, ref_cost, b, gm, target=target)
+            assert np.abs(ps - rp).max() < otol and np.abs(no - rn).max() < otol
+            assert np.abs(en - re).max() < otol * m
+    finally:
+        plan.close()
+
+
+def test_plan_from_given_state():
+    """init_uniform = 0: each run starts from psi's contents; two runs of p
+    rounds from |s> equal one eager call of 2p rounds."""
+    torch = need_gpu()
+    n, m, p = 12, 50, 9
+    lits = rand_lits(n, m, 77)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    b, gm = inst.uniform_angles(78, 2 * p)
+    psi0 = torch.full((1 << n,), 2.0 ** (-n / 2), dtype=torch.complex128, device="cuda")
+    plan = g.EvolvePlan(n, m, cost, p, dtype=g.C128, init_uniform=False, psi=psi0.clone())
+    try:
+        plan.run(b[:p], gm[:p])
+        ps2, _, _ = plan.run(b[p:], gm[p:])
+        psi_e, pe, _, _ = g.gqaoa_evolve(n, m, cost, b, gm, dtype=g.C128)
+        torch.cuda.synchronize()
+        assert float((plan.psi - psi_e).abs().max()) < 1e-12
+        assert abs(ps2[-1] - pe[-1]) < 1e-12
+        with pytest.raises(ValueError):
+            plan.run(b[:p - 1], gm[:p - 1])
+        with pytest.raises(g.GQAOAError):
+            bad = b[:p].copy()
+            bad[0] = np.nan
+            plan.run(bad, gm[:p])
+    finally:
+        plan.close()
