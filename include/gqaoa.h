@@ -392,7 +392,9 @@ int gqaoa_draws_to_reject(int num_solutions, const double *q_host, int trials, u
  * HIP events on the launch stream and accumulate their durations under a
  * name (k = 0 disables; k < 0 is EINVAL): "sv_round_c64", "sv_round_c128" (forward round
  * passes), "sv_reverse_c64", "sv_reverse_c128" (adjoint passes), "cost_table",
- * "scan", and "x_pass_c64", "x_pass_c128" (X-QAOA streaming passes).
+ * "scan", "x_pass_c64", "x_pass_c128" (X-QAOA streaming passes), and
+ * "sv_resident_c64", "sv_resident_c128" (the one-launch evolution of a
+ * small state, all rounds).
  * Durations are collected when the call that launched them synchronizes.
  * gqaoa_profile_read returns GQAOA_EINVAL for an unknown name. */
 int gqaoa_profile_enable(int on);

@@ -102,7 +102,8 @@ struct ProfTotal {
     int64_t count = 0;
 };
 static const char *kProfNames[] = {"sv_round_c64", "sv_round_c128", "sv_reverse_c64", "sv_reverse_c128",
-                                   "cost_table", "scan", "x_pass_c64", "x_pass_c128"};
+                                   "cost_table", "scan", "x_pass_c64", "x_pass_c128",
+                                   "sv_resident_c64", "sv_resident_c128"};
 static ProfTotal g_prof_tot[sizeof(kProfNames) / sizeof(kProfNames[0])];
 static int64_t g_prof_seen[sizeof(kProfNames) / sizeof(kProfNames[0])];  // launches seen while enabled
 

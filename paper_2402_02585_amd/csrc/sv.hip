@@ -353,6 +353,170 @@ __global__ void __launch_bounds__(kSvThreads) sv_forward_kernel(FwdArgs a) {
     }
 }
 
+// ---- resident evolution of small states ------------------------------------------
+// A state of at most 2^14 (complex64) or 2^13 (complex128) amplitudes fits the
+// registers of one block, so all p rounds of one instance run in a single
+// launch: each thread owns the PER consecutive amplitudes z = tid PER + i in
+// every round, with their costs packed four to a register. Round j: add
+// delta_{j-1} (the previous mixer, applied lazily), read out psi_{j-1},
+// apply the phase from the round's table (staged in LDS, the next round's
+// table loaded while this one is used), sum phi_j; one float64 reduction per
+// round gives S_j, delta_j and the readouts, with the same per-element
+// arithmetic as the streaming round pass (delta and the table in the state's
+// precision, per-thread sums in that precision, float64 across threads). The
+// final state is written once, at the end.
+struct ResArgs {
+    const uint8_t *cost;
+    void *psi;             // [N] complex: initial state (unless init_uniform), final state
+    const void *lut;       // [p][256] complex, the state's precision
+    const double *mixf;    // [p][2]: e^{-i beta_j} - 1
+    double *readout;       // [p+1][3]: P_sol, E, norm of psi_0 .. psi_p
+    int n, p, init_uniform, target;
+};
+
+template <typename T, int THREADS, int PER>
+__global__ void __launch_bounds__(THREADS) sv_resident_kernel(ResArgs a) {
+    constexpr int kWaves = THREADS / kWave;
+    constexpr int kLutPer = (256 + THREADS - 1) / THREADS;
+    __shared__ Cx<T> lut_s[2][256];
+    __shared__ double red_s[2][kWaves][5];  // per-wave sums, double-buffered by round parity
+    const uint32_t N = 1u << a.n;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const bool owns = (uint32_t)tid * PER < N;
+    const Cx<T> *lut = reinterpret_cast<const Cx<T> *>(a.lut);
+    const uint32_t target = (uint32_t)a.target;
+    const double invN = ldexp(1.0, -a.n);
+    uint32_t cpk[(PER + 3) / 4];
+#pragma unroll
+    for (int w = 0; w < (PER + 3) / 4; ++w) cpk[w] = 0u;
+    Cx<T> x[PER];
+    if (owns) {
+        load_packed_costs<PER>(a.cost + (size_t)tid * PER, cpk);
+        const Cx<T> *src = reinterpret_cast<const Cx<T> *>(a.psi) + (size_t)tid * PER;
+        const T amp0 = T(sqrt(invN));
+#pragma unroll
+        for (int i = 0; i < PER; ++i) x[i] = a.init_uniform ? Cx<T>{amp0, T(0)} : src[i];
+    }
+    for (int k = tid; k < 256; k += THREADS) lut_s[1][k] = lut[k];  // round 1 uses buffer 1
+    __syncthreads();
+    Cx<T> dl{T(0), T(0)};
+    for (int j = 1; j <= a.p + 1; ++j) {
+        const bool ph = j <= a.p;
+        double mr = 0.0, mi = 0.0;  // this round's mixer factor, loaded before the sweep
+        if (ph) {
+            mr = a.mixf[2 * (j - 1)];
+            mi = a.mixf[2 * (j - 1) + 1];
+        }
+        Cx<T> next[kLutPer];  // the next round's table, loaded now, stored after the sweep
+        if (j < a.p)
+#pragma unroll
+            for (int r = 0; r < kLutPer; ++r)
+                if (tid + r * THREADS < 256) next[r] = lut[(size_t)j * 256 + tid + r * THREADS];
+        T sSr = 0, sSi = 0, sP = 0, sE = 0, sN = 0;
+        if (owns) {
+            const Cx<T> *tab = lut_s[j & 1];
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const uint32_t cz = (cpk[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+                Cx<T> v = x[i];
+                v.re += dl.re;
+                v.im += dl.im;
+                const T pr = v.re * v.re + v.im * v.im;
+                sN += pr;
+                sE += T(cz) * pr;
+                sP += cz == target ? pr : T(0);
+                if (ph) {
+                    v = cmul(tab[cz], v);
+                    sSr += v.re;
+                    sSi += v.im;
+                }
+                x[i] = v;
+            }
+        }
+        if (j < a.p)
+#pragma unroll
+            for (int r = 0; r < kLutPer; ++r)
+                if (tid + r * THREADS < 256) lut_s[(j + 1) & 1][tid + r * THREADS] = next[r];
+        // one barrier per round: it publishes the per-wave sums and the next
+        // table; a buffer is rewritten two rounds later, after the next
+        // round's barrier, which every thread passes only once it has read it
+        double r5[5] = {(double)sSr, (double)sSi, (double)sP, (double)sE, (double)sN};
+#pragma unroll
+        for (int q = 0; q < 5; ++q) r5[q] = wave_sum(r5[q]);
+        double(*buf)[5] = red_s[j & 1];
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) buf[tid / kWave][q] = r5[q];
+        __syncthreads();
+        if constexpr (kWaves > 1) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) r5[q] = wave_sum(lane < kWaves ? buf[lane][q] : 0.0);
+        }
+        if (tid == 0) {
+            double *ro = a.readout + 3 * (size_t)(j - 1);
+            ro[0] = r5[2];
+            ro[1] = r5[3];
+            ro[2] = r5[4];
+        }
+        if (ph) {
+            const double sr = r5[0] * invN, si = r5[1] * invN;
+            dl = {T(mr * sr - mi * si), T(mr * si + mi * sr)};
+        } else {
+            dl = {T(0), T(0)};
+        }
+    }
+    if (owns) {
+        Cx<T> *dst = reinterpret_cast<Cx<T> *>(a.psi) + (size_t)tid * PER;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) dst[i] = x[i];
+    }
+}
+
+// Largest n of the resident form: the state's registers in one block.
+static int resident_max_n(int dtype) { return dtype == GQAOA_C64 ? 14 : 13; }
+
+static bool resident_ok(int n, int dtype, int p) {
+    if (p < 1 || n > resident_max_n(dtype)) return false;
+    const char *e = getenv("GQAOA_SV_RESIDENT");  // "0": always stream (for comparisons)
+    return !(e && e[0] == '0');
+}
+
+typedef void (*ResFn)(ResArgs);
+template <typename T>
+static ResFn resident_fn(int n, int *threads) {
+    // one wave of 2^n / 64 amplitudes per lane while that is at most the run
+    // length, then 2^n / run threads (complex64: runs of 16, complex128: 8)
+    constexpr int kRun = sizeof(T) == 4 ? 16 : 8;
+    const int N = 1 << n;
+    *threads = std::max(kWave, N / kRun);
+    if (*threads == kWave) {
+        switch (std::max(1, N / kWave)) {
+            case 1: return sv_resident_kernel<T, 64, 1>;
+            case 2: return sv_resident_kernel<T, 64, 2>;
+            case 4: return sv_resident_kernel<T, 64, 4>;
+            case 8: return sv_resident_kernel<T, 64, 8>;
+            default: break;
+        }
+        if constexpr (kRun == 16) return sv_resident_kernel<T, 64, 16>;
+    }
+    switch (*threads) {
+        case 128: return sv_resident_kernel<T, 128, kRun>;
+        case 256: return sv_resident_kernel<T, 256, kRun>;
+        case 512: return sv_resident_kernel<T, 512, kRun>;
+        default: return sv_resident_kernel<T, 1024, kRun>;
+    }
+}
+
+static int launch_resident(int dtype, const ResArgs &a, hipStream_t st) {
+    int threads = 0;
+    const ResFn fn = dtype == GQAOA_C64 ? resident_fn<float>(a.n, &threads) : resident_fn<double>(a.n, &threads);
+    ProfScope ps(dtype == GQAOA_C64 ? "sv_resident_c64" : "sv_resident_c128", st);
+    hipLaunchKernelGGL(fn, dim3(1), dim3(threads), 0, st, a);
+    ps.end();
+    GQ_LAUNCH_CHECK();
+    return GQAOA_OK;
+}
+
 // ---- reverse (adjoint) pass -------------------------------------------------------
 struct RevArgs {
     const uint8_t *cost;
@@ -888,10 +1052,16 @@ int run_evolve(int n, int m, const uint8_t *cost, int p, const double *beta, con
     int32_t tg[1] = {target};
     int s = prepare_plan(P, 1, n, m_of, cost, p, beta, gamma, dtype, tg, ws, 0, false, st, lut, f, b, e, t);
     if (s) return s;
-    for (int j = 1; j <= p; ++j)
-        if ((s = forward_round(P, j, psi, psi, init_uniform && j == 1, true, st))) return s;
-    const bool write = p > 0 || init_uniform;
-    if ((s = final_pass(P, psi, psi, init_uniform && p == 0, write, st))) return s;
+    if (resident_ok(n, dtype, p)) {
+        ResArgs r{cost, psi, P.ws + P.L.lut, reinterpret_cast<const double *>(P.ws + P.L.mixf),
+                  reinterpret_cast<double *>(P.ws + P.L.readout), n, p, init_uniform ? 1 : 0, target};
+        if ((s = launch_resident(dtype, r, st))) return s;
+    } else {
+        for (int j = 1; j <= p; ++j)
+            if ((s = forward_round(P, j, psi, psi, init_uniform && j == 1, true, st))) return s;
+        const bool write = p > 0 || init_uniform;
+        if ((s = final_pass(P, psi, psi, init_uniform && p == 0, write, st))) return s;
+    }
     std::vector<double> ro((size_t)(p + 1) * 3);
     GQ_HIP(hipMemcpyAsync(ro.data(), P.ws + P.L.readout, ro.size() * 8, hipMemcpyDeviceToHost, st));
     GQ_HIP(hipStreamSynchronize(st));
@@ -1072,6 +1242,7 @@ __global__ void __launch_bounds__(256) evolve_tables_kernel(const double *__rest
 struct EvolvePlan {
     FwdPlan P;
     int device = -1, m = 0;
+    int target_host[1] = {0};
     double *stage = nullptr;  // pinned: angles [2p], then readouts [(p+1) * 3]
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1108,6 +1279,11 @@ static int enqueue_evolve(EvolvePlan *E, int init_uniform, void *psi, hipStream_
         hipLaunchKernelGGL(evolve_tables_kernel<double>, dim3(P.p), dim3(256), 0, st, ang, P.p, E->m,
                            reinterpret_cast<double *>(P.ws + P.L.lut), mixf);
     GQ_LAUNCH_CHECK();
+    if (resident_ok(P.n, P.dtype, P.p)) {
+        ResArgs r{P.cost, psi, P.ws + P.L.lut, mixf, reinterpret_cast<double *>(P.ws + P.L.readout), P.n, P.p,
+                  init_uniform, *E->target_host};
+        return launch_resident(P.dtype, r, st);
+    }
     int s;
     for (int j = 1; j <= P.p; ++j)
         if ((s = forward_round(P, j, psi, psi, init_uniform && j == 1, true, st))) return s;
@@ -1124,6 +1300,7 @@ int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int 
     EvolvePlan *E = G.e;
     E->device = dev.device;
     E->m = m;
+    E->target_host[0] = target;
     FwdPlan &P = E->P;
     P.dtype = dtype;
     P.num_inst = 1;

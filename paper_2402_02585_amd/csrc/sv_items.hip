@@ -28,35 +28,6 @@ namespace gqaoa {
 // reduction work per amplitude).
 static int item_threads(int n) { return n <= 11 ? 64 : (1 << (n - 5)); }
 
-// PER cost bytes from p into cpk (byte i of the run in byte i % 4 of word i / 4).
-template <int PER>
-__device__ __forceinline__ void load_costs(const uint8_t *__restrict__ p, uint32_t (&cpk)[(PER + 3) / 4]) {
-    static_assert(PER == 1 || PER == 2 || PER == 4 || PER == 8 || PER % 16 == 0, "cost run length");
-    if constexpr (PER >= 4) {
-        if ((reinterpret_cast<uintptr_t>(p) & (PER >= 16 ? 15 : PER - 1)) == 0) {
-            if constexpr (PER >= 16) {
-#pragma unroll
-                for (int u = 0; u < PER / 16; ++u) {
-                    const uint4 v = reinterpret_cast<const uint4 *>(p)[u];
-                    cpk[4 * u] = v.x;
-                    cpk[4 * u + 1] = v.y;
-                    cpk[4 * u + 2] = v.z;
-                    cpk[4 * u + 3] = v.w;
-                }
-            } else if constexpr (PER == 8) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(p);
-                cpk[0] = v.x;
-                cpk[1] = v.y;
-            } else {
-                cpk[0] = *reinterpret_cast<const uint32_t *>(p);
-            }
-            return;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) cpk[i >> 2] |= (uint32_t)p[i] << (8 * (i & 3));
-}
-
 template <int THREADS, int PER>
 __global__ void __launch_bounds__(THREADS) sv_items_kernel(SvItemsArgs a) {
     __shared__ float2 lut[256];
@@ -90,7 +61,7 @@ __global__ void __launch_bounds__(THREADS) sv_items_kernel(SvItemsArgs a) {
         uint32_t cpk[(PER + 3) / 4];
 #pragma unroll
         for (int w = 0; w < (PER + 3) / 4; ++w) cpk[w] = 0u;
-        if (owns) load_costs<PER>(src + (size_t)tid * PER, cpk);
+        if (owns) load_packed_costs<PER>(src + (size_t)tid * PER, cpk);
 #pragma unroll
         for (int i = 0; i < PER; ++i) xv[i] = float2{amp0, 0.f};
         float dr = 0.f, di = 0.f;

@@ -154,10 +154,11 @@ def test_fused_and_separate_finalize_agree(dt, monkeypatch):
 
 
 def test_sampled_profiling_counts():
-    """gqaoa_profile_enable(k) times one round pass in k; the evolution itself
-    is unchanged by profiling."""
+    """gqaoa_profile_enable(k) times one round pass in k (n = 16 streams its
+    rounds); a small state's single resident launch is timed under its own
+    name; the evolution itself is unchanged by profiling."""
     need_gpu()
-    n, m = 14, 59
+    n, m = 16, 67
     cost, _ = g.gqaoa_cost_table(n, rand_lits(n, m, 5))
     beta, gamma = inst.uniform_angles(6, 10)
     ref = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=g.C64)[1]
@@ -169,3 +170,12 @@ def test_sampled_profiling_counts():
     g.gqaoa_profile_reset()
     assert cnt == 3 and ms > 0          # passes 0, 4, 8 of the 10
     assert (got == ref).all()
+    n, m = 12, 50
+    cost, _ = g.gqaoa_cost_table(n, rand_lits(n, m, 7))
+    g.gqaoa_profile_enable(True)
+    g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=g.C128)
+    g.gqaoa_profile_enable(False)
+    ms, cnt = g.gqaoa_profile_read("sv_resident_c128")
+    assert g.gqaoa_profile_read("sv_round_c128")[1] == 0
+    g.gqaoa_profile_reset()
+    assert cnt == 1 and ms > 0

@@ -1,5 +1,6 @@
-"""GPU: the graph-captured evolution (gqaoa_evolve_plan_*) against the eager
-gqaoa_evolve and the oracle.
+"""GPU: the graph-captured evolution (gqaoa_evolve_plan_*) and the resident
+one-launch evolution of small states against the eager streaming rounds and
+the oracle.
 
 The plan computes its phase tables on the device (float64 sin/cos, then the
 state's precision), the eager call on the host, so the two can differ in the
@@ -9,6 +10,8 @@ of the statevector tests hold (1e-12 and 1e-5). Replays are interleaved with
 eager calls and synchronizations, with new angles each time, and the readout
 arrays are refilled before each run so a stale value cannot pass.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -73,3 +76,43 @@ def test_plan_from_given_state():
             plan.run(bad, gm[:p])
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("dtype,n_max,tol,otol", [(g.C64, 14, 5e-6, 1e-5), (g.C128, 13, 1e-12, 1e-12)])
+def test_resident_matches_streaming_every_size(dtype, n_max, tol, otol):
+    """Every n from 3 to the largest resident size (each block shape and
+    amplitudes-per-thread count): the one-launch resident evolution against
+    the streaming round passes (forced by GQAOA_SV_RESIDENT=0) and the
+    oracle, from |s> and from a given state, with a Max-SAT-style target."""
+    torch = need_gpu()
+    for n in range(3, n_max + 1):
+        m = min(inst.m_from_density(n, 4.2), 4 * (n * (n - 1) * (n - 2) // 6))
+        lits = rand_lits(n, m, 90 + n)
+        cost, _ = g.gqaoa_cost_table(n, lits)
+        ref_cost = cost_table(n, lits)
+        target = int(np.min(ref_cost))
+        p = 12
+        b, gm = inst.uniform_angles(91 + n, p)
+        rng = np.random.Generator(np.random.PCG64(92 + n))
+        v = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+        v /= np.linalg.norm(v)
+        cdt = torch.complex64 if dtype == g.C64 else torch.complex128
+        for init_uniform in (True, False):
+            psi0 = torch.tensor(v, dtype=cdt, device="cuda")
+            psi_r, pr, er, nr = g.gqaoa_evolve(n, m, cost, b, gm, dtype=dtype, psi=psi0.clone(),
+                                               init_uniform=init_uniform, target_level=target)
+            os.environ["GQAOA_SV_RESIDENT"] = "0"
+            try:
+                psi_s, ps, es, ns = g.gqaoa_evolve(n, m, cost, b, gm, dtype=dtype, psi=psi0.clone(),
+                                                   init_uniform=init_uniform, target_level=target)
+            finally:
+                del os.environ["GQAOA_SV_RESIDENT"]
+            torch.cuda.synchronize()
+            assert float((psi_r - psi_s).abs().max()) <= tol, (n, init_uniform)
+            for x, y in ((pr, ps), (nr, ns)):
+                assert np.abs(x - y).max() <= tol, (n, init_uniform)
+            assert np.abs(er - es).max() <= tol * m
+            _, rp, re, rn = evolve_sv(n, ref_cost, b, gm, psi0=None if init_uniform else v, target=target)
+            assert np.abs(pr - rp).max() < otol and np.abs(nr - rn).max() < otol, (n, init_uniform)
+            assert np.abs(er - re).max() < otol * m
+        log(f"resident n={n} dtype={dtype} ok")
