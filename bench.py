@@ -319,7 +319,7 @@ def batched_leg(torch, g, inst, steps: int):
                               "speedup_vs_plain_statevector": len(item_inst) * len(plist) / t_items / plain_sv,
                               "max_abs_psol_diff_vs_scan": items_dev,
                               "graph_scan_plus_items_ms": t_both * 1e3, "graph_equals_eager": both_equal,
-                              "kind": "gqaoa_sv_items: complex64 state in LDS, one block per (instance, angle pair), "
+                              "kind": "gqaoa_sv_items: complex64 state in registers, one block per (instance, angle pair), "
                                       "n <= 14, 16 random cells + the 4 scan peaks per instance"},
     }
 
