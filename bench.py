@@ -272,6 +272,28 @@ def batched_leg(torch, g, inst, steps: int):
     sv_ps = sv_ps.cpu().numpy()
     scan_at = np.stack([psol[i, :, gi, bi] for i, gi, bi in item_cells])
     items_dev = float(np.abs(sv_ps - scan_at).max())
+    # the larger instances (n = 15..20): the 4 peak cells of each, their
+    # states streamed from HBM (all items of one n in one batch)
+    large = [i for i, it in enumerate(insts) if it.n > 14]
+    l_ns = [insts[i].n for i in large]
+    l_ms = [insts[i].m for i in large]
+    l_costs, _, _ = g.gqaoa_cost_batched(l_ns, l_ms, [insts[i].lits for i in large], with_hist=False)
+    l_inst, l_cells = [], []
+    for k, i in enumerate(large):
+        for q in range(len(plist)):
+            gi, bi = np.unravel_index(int(np.argmax(psol[i, q])), psol[i, q].shape)
+            l_inst.append(k)
+            l_cells.append((i, int(gi), int(bi)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l_ps, _ = g.gqaoa_sv_items(l_ns, l_ms, l_costs, l_inst, [grid[b] for _, _, b in l_cells],
+                               [grid[c] for _, c, _ in l_cells], plist)
+    torch.cuda.synchronize()
+    t_large = time.perf_counter() - t0
+    l_ps = l_ps.cpu().numpy()
+    l_dev = float(np.abs(l_ps - np.stack([psol[i, :, c, b] for i, c, b in l_cells])).max())
+    l_amp_rounds = sum(2 ** insts[i].n for i, _, _ in l_cells) * plist[-1]
+    del l_costs
     # both paths in one graph: the scan on one branch, the items (on the
     # scan's own grid cells) on a parallel one
     cost_off = np.zeros(len(insts), dtype=np.uint64)
@@ -314,6 +336,12 @@ def batched_leg(torch, g, inst, steps: int):
         "speedup_vs_plain_statevector": rate / plain_sv,
         "speedup_vs_plain_level_space": rate / plain_h,
         "max_abs_psol_diff_vs_plain": max_dev,
+        "statevector_items_streamed": {"items": len(l_inst), "instances": len(large), "seconds": t_large,
+                                       "instance_angle_evals_per_s": len(l_inst) * len(plist) / t_large,
+                                       "amplitude_rounds_per_s": l_amp_rounds / t_large,
+                                       "max_abs_psol_diff_vs_scan": l_dev,
+                                       "kind": "gqaoa_sv_items on instances with n = 15..20: the 4 scan peaks "
+                                               "per instance, complex64 states streamed, batched per n"},
         "statevector_items": {"items": len(item_inst), "instances": len(small), "seconds": t_items,
                               "instance_angle_evals_per_s": len(item_inst) * len(plist) / t_items,
                               "speedup_vs_plain_statevector": len(item_inst) * len(plist) / t_items / plain_sv,

@@ -245,11 +245,13 @@ int gqaoa_scan_crossing(int num_inst, const int32_t *n_host, const int32_t *m_ho
  * protocol of Eq. (5) with (beta_host[k], gamma_host[k]) on instance
  * item_inst_host[k], whose cost table is in costs_dev at
  * gqaoa_cost_batched_offset(item_inst_host[k], n_host) (the layout written by
- * gqaoa_cost_batched), from |s>, complex64 state held in registers, for
+ * gqaoa_cost_batched), from |s>, complex64 state, for
  * p_list[num_p-1] rounds, recording after each p in p_list (ascending)
  *   psol_dev  [k*num_p + q] = P_sol at target_host[inst] (NULL: level 0),
  *   energy_dev[k*num_p + q] = E of Eq. (4) (NULL to skip), both float.
- * Item instances need n <= GQAOA_SV_ITEMS_MAX_N (ERANGE otherwise).
+ * Items of instances with n <= GQAOA_SV_ITEMS_MAX_N keep their state in
+ * registers (one block per item); larger ones (n <= 26) are evolved by the
+ * streaming round passes, all items of one n together.
  * Synchronizes the stream. Errors: EINVAL (NULL pointers, non-finite angles,
  * p_list not ascending), ERANGE (counts, n, m, targets, p values). */
 #define GQAOA_SV_ITEMS_MAX_N 14
@@ -282,7 +284,7 @@ int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host,
  * gqaoa_cost_batched), and writes item_psol_dev[k*num_p + q] (and
  * item_energy_dev, NULL to skip) after each p_list[q], the float values of
  * the scan's cell (i, q, g, b) computed without the level reduction. Item
- * instances need n <= GQAOA_SV_ITEMS_MAX_N.
+ * instances need n <= GQAOA_SV_ITEMS_MAX_N (the register-held items).
  * Synchronizes the stream. Errors: those of gqaoa_scan_batched and
  * gqaoa_sv_items, EINVAL for a NULL plan_out or an item cell outside the
  * grid, EHIP if the graph cannot be captured.

@@ -551,7 +551,6 @@ int gqaoa_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, c
     for (int k = 0; k < num_items; ++k) {
         const int i = item_inst_host[k];
         if (i < 0 || i >= num_inst) return fail(GQAOA_ERANGE, "item %d: instance %d", k, i);
-        if (n_host[i] > GQAOA_SV_ITEMS_MAX_N) return fail(GQAOA_ERANGE, "item %d: n=%d > %d", k, n_host[i], GQAOA_SV_ITEMS_MAX_N);
         if (!std::isfinite(beta_host[k]) || !std::isfinite(gamma_host[k])) return fail(GQAOA_EINVAL, "item %d: angles", k);
     }
     return run_sv_items(num_inst, n_host, m_host, target_host, costs_dev, num_items, item_inst_host, beta_host,

@@ -1218,10 +1218,18 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
 // readouts; the tables are computed on the device from the angles, with the
 // same float64 reduction and rounding as the host tables of run_evolve. A
 // state of at most 64 MB takes the fused round pass (one launch per round).
+// Block (j, i): round j of instance i; ang[i] = (beta[p], gamma[p]), the
+// instance's m from m_dev (or m_all when m_dev is null); tables [i][p][256]
+// and [i][p][2].
 template <typename T>
-__global__ void __launch_bounds__(256) evolve_tables_kernel(const double *__restrict__ ang, int p, int m,
+__global__ void __launch_bounds__(256) evolve_tables_kernel(const double *__restrict__ ang, int p,
+                                                            const int32_t *__restrict__ m_dev, int m_all,
                                                             T *__restrict__ lut, double *__restrict__ mixf) {
-    const int j = blockIdx.x, k = threadIdx.x;
+    const int j = blockIdx.x, k = threadIdx.x, i = blockIdx.y;
+    const int m = m_dev ? m_dev[i] : m_all;
+    ang += (size_t)i * 2 * p;
+    lut += (size_t)i * p * 256 * 2;
+    mixf += (size_t)i * p * 2;
     T re = 0, im = 0;
     if (k <= m) {
         double sn, cs;
@@ -1273,10 +1281,10 @@ static int enqueue_evolve(EvolvePlan *E, int init_uniform, void *psi, hipStream_
     const double *ang = reinterpret_cast<const double *>(P.ws + P.L.angles);
     double *mixf = reinterpret_cast<double *>(P.ws + P.L.mixf);
     if (P.dtype == GQAOA_C64)
-        hipLaunchKernelGGL(evolve_tables_kernel<float>, dim3(P.p), dim3(256), 0, st, ang, P.p, E->m,
+        hipLaunchKernelGGL(evolve_tables_kernel<float>, dim3(P.p), dim3(256), 0, st, ang, P.p, nullptr, E->m,
                            reinterpret_cast<float *>(P.ws + P.L.lut), mixf);
     else
-        hipLaunchKernelGGL(evolve_tables_kernel<double>, dim3(P.p), dim3(256), 0, st, ang, P.p, E->m,
+        hipLaunchKernelGGL(evolve_tables_kernel<double>, dim3(P.p), dim3(256), 0, st, ang, P.p, nullptr, E->m,
                            reinterpret_cast<double *>(P.ws + P.L.lut), mixf);
     GQ_LAUNCH_CHECK();
     if (resident_ok(P.n, P.dtype, P.p)) {
@@ -1357,6 +1365,102 @@ int evolve_plan_run(EvolvePlan *E, const double *beta, const double *gamma, doub
         if (psol) psol[j] = ro[3 * j];
         if (energy) energy[j] = ro[3 * j + 1];
         if (norm) norm[j] = ro[3 * j + 2];
+    }
+    return GQAOA_OK;
+}
+
+// ---- streamed statevector work items (states too large for registers) --------------------
+// Single-angle-pair items of one size n, evolved together: item k is
+// instance k of a batched streaming evolution (its own cost table copy,
+// state, tables and target), complex64, p = p_list[num_p-1] rounds from |s>;
+// the readouts at p_list go to the items' output rows.
+__global__ void gather_costs_kernel(const uint8_t *__restrict__ costs, const uint64_t *__restrict__ off, uint64_t N,
+                                    uint8_t *__restrict__ dst) {
+    const uint8_t *src = costs + off[blockIdx.y];
+    uint8_t *d = dst + (uint64_t)blockIdx.y * N;
+    for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < N; z += (uint64_t)gridDim.x * blockDim.x)
+        d[z] = src[z];
+}
+
+__global__ void gather_readouts_kernel(const double *__restrict__ ro, int p, int count, const int32_t *__restrict__ out,
+                                       const int32_t *__restrict__ p_list, int num_p, float *__restrict__ psol,
+                                       float *__restrict__ energy) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count * num_p) return;
+    const int k = t / num_p, q = t % num_p;
+    const double *r = ro + (size_t)k * 3 * (p + 1) + 3 * (size_t)p_list[q];
+    psol[(size_t)out[k] * num_p + q] = (float)r[0];
+    if (energy) energy[(size_t)out[k] * num_p + q] = (float)r[1];
+}
+
+int sv_items_stream(int n, int count, const int32_t *item_inst, const int32_t *item_out, const double *beta,
+                    const double *gamma, const uint8_t *costs, const uint64_t *cost_off, const int32_t *m_host,
+                    const int32_t *target_host, int num_p, const int32_t *p_list, float *psol, float *energy,
+                    hipStream_t st) {
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    const int p = p_list[num_p - 1];
+    const uint64_t N = 1ull << n;
+    // chunks of items whose states and cost copies stay within 4 GiB
+    const int chunk = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)count, (4ull << 30) / (9 * N)));
+    for (int c0 = 0; c0 < count; c0 += chunk) {
+        const int cnt = std::min(chunk, count - c0);
+        FwdPlan P;
+        P.dtype = GQAOA_C64;
+        P.num_inst = cnt;
+        P.n = n;
+        P.p = p;
+        P.N = N;
+        P.L = sv_layout(cnt, n, p, GQAOA_C64, 0, false);
+        P.shape = pass_shape(N, cnt, GQAOA_C64, dev);
+        P.fuse_mode = -1;
+        auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+        const size_t o_cost = al(P.L.total), o_psi = o_cost + al(cnt * N), o_off = o_psi + al(cnt * N * 8);
+        const size_t o_m = o_off + al(8 * (size_t)cnt), o_out = o_m + al(4 * (size_t)cnt);
+        const size_t o_pl = o_out + al(4 * (size_t)cnt), total = o_pl + al(4 * (size_t)num_p);
+        AsyncScratch guard(st);
+        GQ_HIP(guard.alloc(total));
+        char *base = reinterpret_cast<char *>(guard.ptr);
+        P.ws = base;
+        P.cost = reinterpret_cast<const uint8_t *>(base + o_cost);
+        std::vector<uint64_t> off(cnt);
+        std::vector<int32_t> m(cnt), tg(cnt), out(cnt);
+        std::vector<double> ang((size_t)cnt * 2 * p);
+        for (int k = 0; k < cnt; ++k) {
+            const int i = item_inst[c0 + k];
+            off[k] = cost_off[i];
+            m[k] = m_host[i];
+            tg[k] = target_host ? target_host[i] : 0;
+            out[k] = item_out[c0 + k];
+            std::fill(ang.begin() + (size_t)k * 2 * p, ang.begin() + (size_t)k * 2 * p + p, beta[c0 + k]);
+            std::fill(ang.begin() + (size_t)k * 2 * p + p, ang.begin() + (size_t)(k + 1) * 2 * p, gamma[c0 + k]);
+        }
+        GQ_HIP(hipMemcpyAsync(base + o_off, off.data(), 8 * (size_t)cnt, hipMemcpyHostToDevice, st));
+        GQ_HIP(hipMemcpyAsync(base + o_m, m.data(), 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+        GQ_HIP(hipMemcpyAsync(base + o_out, out.data(), 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+        GQ_HIP(hipMemcpyAsync(base + o_pl, p_list, 4 * (size_t)num_p, hipMemcpyHostToDevice, st));
+        GQ_HIP(hipMemcpyAsync(base + P.L.target, tg.data(), 4 * (size_t)cnt, hipMemcpyHostToDevice, st));
+        GQ_HIP(hipMemcpyAsync(base + P.L.angles, ang.data(), 8 * ang.size(), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(gather_costs_kernel, dim3((unsigned)std::min<uint64_t>(1024, (N + 255) / 256), cnt),
+                           dim3(256), 0, st, costs, reinterpret_cast<const uint64_t *>(base + o_off), N,
+                           reinterpret_cast<uint8_t *>(base + o_cost));
+        GQ_LAUNCH_CHECK();
+        hipLaunchKernelGGL(evolve_tables_kernel<float>, dim3(p, cnt), dim3(256), 0, st,
+                           reinterpret_cast<const double *>(base + P.L.angles), p,
+                           reinterpret_cast<const int32_t *>(base + o_m), 0, reinterpret_cast<float *>(base + P.L.lut),
+                           reinterpret_cast<double *>(base + P.L.mixf));
+        GQ_LAUNCH_CHECK();
+        void *psi = base + o_psi;
+        for (int j = 1; j <= p; ++j)
+            if ((s = forward_round(P, j, psi, psi, j == 1, true, st))) return s;
+        if ((s = final_pass(P, psi, psi, false, false, st))) return s;
+        hipLaunchKernelGGL(gather_readouts_kernel, dim3((cnt * num_p + 255) / 256), dim3(256), 0, st,
+                           reinterpret_cast<const double *>(base + P.L.readout), p, cnt,
+                           reinterpret_cast<const int32_t *>(base + o_out),
+                           reinterpret_cast<const int32_t *>(base + o_pl), num_p, psol, energy);
+        GQ_LAUNCH_CHECK();
+        GQ_HIP(hipStreamSynchronize(st));  // the host tables of this chunk end here
     }
     return GQAOA_OK;
 }

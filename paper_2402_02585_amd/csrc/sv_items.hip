@@ -13,7 +13,8 @@
 // when j-1 is a requested round, applies the phase and sums phi_j; one
 // reduction (float64) gives delta_j = (e^{-i beta} - 1) S_j / 2^n. The
 // reduction is the only exchange between threads (wave shuffles alone for a
-// one-wave block).
+// one-wave block). Items of larger instances (n > GQAOA_SV_ITEMS_MAX_N) are
+// evolved by the streaming round passes, all items of one n in one batch.
 #include "batch.h"
 
 #include <algorithm>
@@ -162,9 +163,6 @@ uint64_t batched_cost_offset(int i, const int32_t *n_host);
 int sv_items_order(const int32_t *n_host, int num_items, const int32_t *item_inst, const DeviceInfo &dev,
                    ItemOrder *out) {
     (void)dev;
-    for (int k = 0; k < num_items; ++k)
-        if (n_host[item_inst[k]] > GQAOA_SV_ITEMS_MAX_N)
-            return fail(GQAOA_ERANGE, "item %d: n=%d > %d", k, n_host[item_inst[k]], GQAOA_SV_ITEMS_MAX_N);
     out->order.resize(num_items);
     for (int k = 0; k < num_items; ++k) out->order[k] = k;
     std::stable_sort(out->order.begin(), out->order.end(),
@@ -188,6 +186,11 @@ int sv_items_launch(const SvItemsArgs &a, const DeviceInfo &dev, hipStream_t st)
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
 }
+
+int sv_items_stream(int n, int count, const int32_t *item_inst, const int32_t *item_out, const double *beta,
+                    const double *gamma, const uint8_t *costs, const uint64_t *cost_off, const int32_t *m_host,
+                    const int32_t *target_host, int num_p, const int32_t *p_list, float *psol, float *energy,
+                    hipStream_t st);
 
 int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *target_host,
                  const uint8_t *costs, int num_items, const int32_t *item_inst, const double *beta,
@@ -221,6 +224,21 @@ int run_sv_items(int num_inst, const int32_t *n_host, const int32_t *m_host, con
     GQ_HIP(hipMemcpyAsync(d_t, tg.data(), b_i, hipMemcpyHostToDevice, st));
     for (size_t g = 0; g + 1 < ord.first.size(); ++g) {
         const int k0 = ord.first[g], k1 = ord.first[g + 1];
+        const int n = n_host[items[k0].inst];
+        if (n > GQAOA_SV_ITEMS_MAX_N) {  // too large for registers: streamed, batched per n
+            std::vector<int32_t> ii(k1 - k0), io(k1 - k0);
+            std::vector<double> bb(k1 - k0), gg(k1 - k0);
+            for (int k = k0; k < k1; ++k) {
+                ii[k - k0] = items[k].inst;
+                io[k - k0] = items[k].out;
+                bb[k - k0] = items[k].beta;
+                gg[k - k0] = items[k].gamma;
+            }
+            if ((s = sv_items_stream(n, k1 - k0, ii.data(), io.data(), bb.data(), gg.data(), costs, off.data(), m_host,
+                                     target_host, num_p, p_list, psol, energy, st)))
+                return s;
+            continue;
+        }
         SvItemsArgs a{};
         a.items = d_items + k0;
         a.num_items = k1 - k0;

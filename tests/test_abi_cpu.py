@@ -183,8 +183,9 @@ def test_batched_cost_and_items_argument_checks():
     assert lib.gqaoa_cost_batched_offset(2, g._np_ptr(ns)) == 1024 + 32768
     b = np.zeros(2)
     pl = np.array([1, 4], dtype=np.int32)
-    items = np.array([0, 1], dtype=np.int32)     # instance 1 has n = 15 > 14
-    assert lib.gqaoa_sv_items(2, g._np_ptr(ns), g._np_ptr(ms), None, d, 2, g._np_ptr(items), g._np_ptr(b),
+    big2 = np.array([10, 27], dtype=np.int32)    # instance 1 has n = 27 > 26
+    items = np.array([0, 1], dtype=np.int32)
+    assert lib.gqaoa_sv_items(2, g._np_ptr(big2), g._np_ptr(ms), None, d, 2, g._np_ptr(items), g._np_ptr(b),
                               g._np_ptr(b), 2, g._np_ptr(pl), d, None, None) == -2
     items = np.array([0, 2], dtype=np.int32)     # no instance 2
     assert lib.gqaoa_sv_items(2, g._np_ptr(ns), g._np_ptr(ms), None, d, 2, g._np_ptr(items), g._np_ptr(b),

@@ -101,6 +101,38 @@ def test_items_every_block_shape():
         assert np.abs(en[k] - re[P_LIST]).max() / ms[i] < 1e-5, ns[i]
 
 
+def test_streamed_items_beyond_registers():
+    """Instances with n = 15..17 take the streaming round passes (all items of
+    one n in one batch) in the same call as register-held ones (n = 12..14),
+    with Max-SAT targets: against the oracle's statevector (1e-5) and the
+    level-space scan of the same cells (1e-5)."""
+    need_gpu()
+    its = _set(60, [12, 15, 13, 16, 14, 17], d=5.5)
+    ns = [n for n, _ in its]
+    ms = [l.shape[0] for _, l in its]
+    costs, _, _ = g.gqaoa_cost_batched(ns, ms, [l for _, l in its], with_hist=False)
+    refc = [cost_table(n, l) for n, l in its]
+    hists = [level_histogram(c, m) for c, m in zip(refc, ms)]
+    targets = [min_level(h) for h in hists]
+    rng = np.random.Generator(np.random.PCG64(61))
+    item_inst = np.array([0, 1, 1, 2, 3, 3, 3, 4, 5, 5], dtype=np.int32)
+    beta = rng.uniform(0, 2 * np.pi, item_inst.size)
+    gamma = rng.uniform(0, np.pi, item_inst.size)
+    log(f"streamed + register items: {item_inst.size} items, n = {ns}")
+    ps, en = g.gqaoa_sv_items(ns, ms, costs, item_inst, beta, gamma, P_LIST, targets=targets, with_energy=True)
+    ps, en = ps.cpu().numpy(), en.cpu().numpy()
+    H = np.zeros((len(its), max(ms) + 1), dtype=np.int64)
+    for i, h in enumerate(hists):
+        H[i, :ms[i] + 1] = h
+    for k, i in enumerate(item_inst):
+        _, rp, re, _ = evolve_sv(ns[i], refc[i], np.full(64, beta[k]), np.full(64, gamma[k]), target=targets[i])
+        assert np.abs(ps[k] - rp[P_LIST]).max() < 1e-5, (ns[i], ps[k], rp[P_LIST])
+        assert np.abs(en[k] - re[P_LIST]).max() / ms[i] < 1e-5, ns[i]
+        sp, _ = g.gqaoa_scan_batched([ns[i]], [ms[i]], H[i:i + 1], [beta[k]], [gamma[k]], P_LIST,
+                                     targets=[targets[i]], with_energy=False)
+        assert np.abs(sp.cpu().numpy().reshape(-1) - ps[k]).max() < 1e-5, ns[i]
+
+
 def test_items_at_the_size_limit():
     """n = 14, the largest item: 1024 threads of 16 register-held amplitudes."""
     need_gpu()
