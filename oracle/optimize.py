@@ -9,7 +9,9 @@ single-pair optimum ("the same initial seeds") and relaxes all 2p angles.
 The objective is a parameter: ``"energy"`` (Eq. (4), the paper's) or
 ``"psol"`` (maximize the solution probability).
 
-Parity unpinned beyond: the refined value is never worse than the best grid
+Pinned by a closed form: on a two-level cost the single-pair optimum is
+Grover's sin^2((2p+1) theta) (tests/test_instances_and_optimizer.py). Beyond
+that, the refined value is never worse than the best grid
 point, and the objective is invariant under (beta, gamma) -> (-beta, -gamma)
 and 2 pi shifts. Local optima of L-BFGS-B are not unique.
 """

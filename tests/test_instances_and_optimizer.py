@@ -83,3 +83,31 @@ def test_optimizer_refines_and_is_symmetric():
     grid = single_pair_grid(hist, p, gb, gg)
     mirror = single_pair_grid(hist, p, -gb, -gg)
     np.testing.assert_allclose(grid, mirror, atol=1e-13)
+
+
+@pytest.mark.parametrize("N0,n,p", [(4, 10, 1), (4, 10, 3), (16, 12, 5), (1, 8, 2)])
+def test_optimizer_reaches_grover_bound_on_two_levels(N0, n, p):
+    """A two-level cost (solutions at level 0, every other assignment at
+    level 1) makes the single-pair protocol a p-query search with a phase
+    oracle: no angle pair can beat Grover's sin^2((2p+1) theta), sin^2 theta =
+    N0 / 2^n (optimality of Grover search for symmetric algorithms, Zalka
+    1999), and (beta, gamma) = (pi, pi) is Grover's iteration, which reaches
+    it. So the optimizer's maximum must be that closed form, not less, and
+    no grid point may exceed it."""
+    hist = np.array([N0, 2 ** n - N0], dtype=np.int64)
+    theta = np.arcsin(np.sqrt(N0 / 2 ** n))
+    bound = np.sin((2 * p + 1) * theta) ** 2
+    assert (2 * p + 1) * theta <= np.pi / 2          # below the first Grover peak
+    gb = np.linspace(0, 2 * np.pi, 48, endpoint=False)
+    gg = np.linspace(0, np.pi, 25)
+    b, g, v_grid, v_ref = optimize_single_pair(hist, p, gb, gg, objective="psol")
+    assert -v_ref == pytest.approx(bound, abs=1e-6)
+    assert -single_pair_grid(hist, p, gb, gg).min() <= bound + 1e-12
+    assert psol_single_pair_hist(hist, np.pi, np.pi, p) == pytest.approx(bound, abs=1e-12)
+    # a grid that misses (pi, pi): the L-BFGS-B refinement has to climb to the bound
+    gb2 = np.linspace(0.05, 2 * np.pi + 0.05, 47, endpoint=False)
+    gg2 = np.linspace(0.03, np.pi - 0.03, 23)
+    b2, g2, v_grid2, v_ref2 = optimize_single_pair(hist, p, gb2, gg2, objective="psol")
+    assert -v_grid2 < bound - 1e-9
+    assert -v_ref2 == pytest.approx(bound, abs=1e-5)
+    assert -v_ref2 <= bound + 1e-12
