@@ -13,9 +13,14 @@ brute-force counting at large n), written from the paper's definitions:
   mlp.py       the angle-predictor MLP in float64 with bfloat16 rounding
                emulated at the storage points
   optimize.py  grid search followed by L-BFGS-B (App. C, "Optimization")
+  rounds.py    rounds to reach a target success probability, Max-SAT level,
+               the 1/sqrt(P) fit (Sec. III)
+  xqaoa.py     the transverse-field mixer comparator (Sec. IV)
+  fairness.py  fair-sampling metrics of Table I
   brute.py     ctypes wrapper of brute_count.c (plain loops) for n up to 34
 
-Every function names the passage it follows. Parity of ``optimize.py`` is
-unpinned beyond the properties in its header; training dynamics of ``mlp.py``
-are unpinned (its forward/backward are pinned).
+Every function names the passage it follows. ``optimize.py`` is pinned on
+two-level costs (Grover's optimum) and otherwise only by the properties in its
+header; training dynamics of ``mlp.py`` are unpinned (its forward/backward
+are pinned).
 """
