@@ -21,6 +21,6 @@ brute-force counting at large n), written from the paper's definitions:
 
 Every function names the passage it follows. ``optimize.py`` is pinned on
 two-level costs (Grover's optimum) and otherwise only by the properties in its
-header; training dynamics of ``mlp.py`` are unpinned (its forward/backward
-are pinned).
+header. ``mlp.py``'s training step is built from pinned pieces (forward,
+backward, Adam); training over many steps is not pinned further.
 """
