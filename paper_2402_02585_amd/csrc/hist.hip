@@ -67,9 +67,9 @@ hist_evolve_kernel(const unsigned long long *__restrict__ hist, int m, int n, in
             E += (double)k * pb;
             P += k == target ? pb : 0.0;
         }
-        P = wave_sum(P);
-        E = wave_sum(E);
-        Nn = wave_sum(Nn);
+        P = wave_sum_dpp(P);  // the one-wave block is converged here
+        E = wave_sum_dpp(E);
+        Nn = wave_sum_dpp(Nn);
         if (lane == 0) {
             out[3 * j] = P;
             out[3 * j + 1] = E;
@@ -104,8 +104,8 @@ hist_evolve_kernel(const unsigned long long *__restrict__ hist, int m, int n, in
             sr += w[i] * br[i];
             si += w[i] * bi[i];
         }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
+        sr = wave_sum_dpp(sr);
+        si = wave_sum_dpp(si);
         const double cr = R.mix[0] * sr - R.mix[1] * si, ci = R.mix[0] * si + R.mix[1] * sr;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {

@@ -84,6 +84,45 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Wave sums without LDS traffic, for per-round reductions inside a loop:
+// DPP row shifts (an inclusive scan within each row of 16 lanes) and lane
+// reads of the row totals, all on the vector and scalar units. The order of
+// the additions is fixed. Every lane of the wave must be active (the lane
+// reads do not look at EXEC); every lane receives the total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of lanes 0..K-1 of the wave (K a power of two, at most 16).
+template <int K>
+__device__ __forceinline__ double lanes_sum_dpp(double v) {
+    static_assert(K >= 1 && K <= 16 && (K & (K - 1)) == 0, "row-sized power of two");
+    if constexpr (K >= 2) v += dpp_move<0x111>(v);  // row_shr:1
+    if constexpr (K >= 4) v += dpp_move<0x112>(v);  // row_shr:2
+    if constexpr (K >= 8) v += dpp_move<0x114>(v);  // row_shr:4
+    if constexpr (K >= 16) v += dpp_move<0x118>(v); // row_shr:8
+    return lane_value(v, K - 1);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0x111>(v);
+    v += dpp_move<0x112>(v);
+    v += dpp_move<0x114>(v);
+    v += dpp_move<0x118>(v);
+    return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+}
+
 // Fixed-order reduction of R doubles across a block of kThreads threads.
 // Every thread passes its R values; thread 0 receives the block sums.
 template <int R, int kThreads>

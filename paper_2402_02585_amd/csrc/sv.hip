@@ -440,9 +440,10 @@ __global__ void __launch_bounds__(THREADS) sv_resident_kernel(ResArgs a) {
         // one barrier per round: it publishes the per-wave sums and the next
         // table; a buffer is rewritten two rounds later, after the next
         // round's barrier, which every thread passes only once it has read it
+        // (DPP wave sums: the block is converged here)
         double r5[5] = {(double)sSr, (double)sSi, (double)sP, (double)sE, (double)sN};
 #pragma unroll
-        for (int q = 0; q < 5; ++q) r5[q] = wave_sum(r5[q]);
+        for (int q = 0; q < 5; ++q) r5[q] = wave_sum_dpp(r5[q]);
         double(*buf)[5] = red_s[j & 1];
         if (lane == 0)
 #pragma unroll
@@ -450,7 +451,7 @@ __global__ void __launch_bounds__(THREADS) sv_resident_kernel(ResArgs a) {
         __syncthreads();
         if constexpr (kWaves > 1) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) r5[q] = wave_sum(lane < kWaves ? buf[lane][q] : 0.0);
+            for (int q = 0; q < 5; ++q) r5[q] = lanes_sum_dpp<kWaves>(lane < kWaves ? buf[lane][q] : 0.0);
         }
         if (tid == 0) {
             double *ro = a.readout + 3 * (size_t)(j - 1);

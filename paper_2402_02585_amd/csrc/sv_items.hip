@@ -100,11 +100,12 @@ __global__ void __launch_bounds__(THREADS) sv_items_kernel(SvItemsArgs a) {
             // S every round; P_sol and E only in the readout rounds
             double r[4] = {sr, si, sp, se};
             const int nq = rd ? 4 : 2;
+            // DPP wave sums (nq is uniform, so the whole block is converged)
             if constexpr (THREADS == kWave) {
-                // xor-butterfly sums: every lane ends with the same totals
+                // every lane ends with the same totals
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (k < nq) r[k] = wave_sum(r[k]);
+                    if (k < nq) r[k] = wave_sum_dpp(r[k]);
             } else {
                 // wave sums, then a wave sum of the per-wave sums (the same
                 // fixed order in every wave, so identical totals in every
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(THREADS) sv_items_kernel(SvItemsArgs a) {
                 // it has read this round's sums.
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (k < nq) r[k] = wave_sum(r[k]);
+                    if (k < nq) r[k] = wave_sum_dpp(r[k]);
                 double(*buf)[4] = red_s[j & 1];
                 const int lane = tid & (kWave - 1);
                 if (lane == 0)
@@ -121,10 +122,10 @@ __global__ void __launch_bounds__(THREADS) sv_items_kernel(SvItemsArgs a) {
                     for (int k = 0; k < 4; ++k)
                         if (k < nq) buf[tid / kWave][k] = r[k];
                 __syncthreads();
-                // lane w < waves takes wave w's sums, then one more wave sum
+                // lane w < waves takes wave w's sums, then one sum over those lanes
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    if (k < nq) r[k] = wave_sum(lane < THREADS / kWave ? buf[lane][k] : 0.0);
+                    if (k < nq) r[k] = lanes_sum_dpp<THREADS / kWave>(lane < THREADS / kWave ? buf[lane][k] : 0.0);
             }
             if (rd) {
                 if (tid == 0) {
