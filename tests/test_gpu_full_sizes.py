@@ -1,0 +1,96 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration it
+times, on sampled outputs the oracle computes one by one.
+
+Batched scan: 4096 satisfiable instances (n uniform in 8..20, d in
+{3.0, 4.2, 5.0}), the grid linspace(0, pi, 64) for beta and for gamma,
+readouts at p = 1, 4, 16, 64, run as a replay of a scan plan over the
+histograms of the batched cost kernel. The histograms of instances spread
+over the batch are compared bit for bit with the oracle's brute-force counts,
+and cells of instances spread over the batch (the first and the last
+included, the grid's corners included) with the oracle's float64 level-space
+evolution (Eq. (5)) within the scan's float32 bounds (1e-4 on P_sol, 1e-4 m
+on E).
+
+Adjoint: 256 satisfiable instances n = 20, m = 85, p = 32 independent angle
+pairs, complex128, checkpoints every 8 rounds, in one batch (the instance
+index runs over the whole launch grid); instances spread over the batch
+against the oracle's level-space P_sol and gradient at the complex128 bars.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import log, need_gpu
+from oracle.cost import cost_table, level_histogram
+from oracle.evolve import evolve_hist
+from oracle.grad import grad_hist
+from paper_2402_02585_amd import gqaoa as g
+from paper_2402_02585_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+def test_scan_plan_full_size_sampled():
+    torch = need_gpu()
+    its = inst.batched_scan_instances(3, 4096, 8, 20)
+    ns = [it.n for it in its]
+    ms = [it.m for it in its]
+    stride = max(ms) + 1
+    log(f"full-size scan: {len(its)} instances, n {min(ns)}..{max(ns)}")
+    H = g.gqaoa_hist_batched(ns, ms, [it.lits for it in its], hist_stride=stride).cpu().numpy()
+    rng = np.random.Generator(np.random.PCG64(4096))
+    picks = sorted({0, len(its) - 1} | {int(x) for x in rng.choice(len(its), 22, replace=False)})
+    for i in picks:
+        ref = level_histogram(cost_table(ns[i], its[i].lits), ms[i])
+        np.testing.assert_array_equal(H[i, :ms[i] + 1], ref, err_msg=f"instance {i}")
+        assert not H[i, ms[i] + 1:].any()
+    grid = np.linspace(0.0, np.pi, 64)
+    plist = [1, 4, 16, 64]
+    plan = g.ScanPlan(ns, ms, H, grid, grid, plist)
+    try:
+        plan.run(grid, grid)
+        torch.cuda.synchronize()
+        psol = plan.psol.cpu().numpy()
+        energy = plan.energy.cpu().numpy()
+    finally:
+        plan.close()
+    assert psol.shape == (len(its), len(plist), 64, 64)
+    corners = [(0, 0), (0, 63), (63, 0), (63, 63)]
+    checked = 0
+    for i in picks:
+        cells = corners if i in (0, len(its) - 1) else []
+        cells = cells + [(int(rng.integers(0, 64)), int(rng.integers(0, 64))) for _ in range(8)]
+        for gi, bi in cells:
+            _, rp, re, _ = evolve_hist(H[i, :ms[i] + 1], np.full(64, grid[bi]), np.full(64, grid[gi]))
+            for q, p in enumerate(plist):
+                assert abs(psol[i, q, gi, bi] - rp[p]) < 1e-4, (i, p, gi, bi, psol[i, q, gi, bi], rp[p])
+                assert abs(energy[i, q, gi, bi] - re[p]) < 1e-4 * ms[i], (i, p, gi, bi)
+            checked += 1
+    log(f"  {len(picks)} histograms bit-exact, {checked} cells x {len(plist)} readouts within bounds")
+    assert np.isfinite(psol).all() and (psol >= -1e-6).all() and (psol <= 1 + 1e-5).all()
+
+
+def test_adjoint_full_batch_sampled():
+    torch = need_gpu()
+    n, m, p, I, ckpt = 20, 85, 32, 256, 8
+    lits = []
+    for _, l in inst.sat_stream(4, n, m):
+        if inst.dpll_satisfiable(n, l):
+            lits.append(l)
+        if len(lits) == I:
+            break
+    costs = torch.empty((I, 2 ** n), dtype=torch.uint8, device="cuda")
+    for i, l in enumerate(lits):
+        g.gqaoa_cost_table(n, l, with_hist=False, cost=costs[i])
+    betas = np.stack([inst.uniform_angles(100 + i, p)[0] for i in range(I)])
+    gammas = np.stack([inst.uniform_angles(100 + i, p)[1] for i in range(I)])
+    log(f"full-batch adjoint: {I} instances n={n} p={p} complex128, checkpoint every {ckpt}")
+    P, db, dg = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, dtype=g.C128, ckpt_every=ckpt)
+    del costs
+    torch.cuda.empty_cache()
+    assert P.shape == (I,) and db.shape == (I, p) and dg.shape == (I, p)
+    for i in (0, 1, 63, 64, 127, 128, 200, I - 1):
+        ref_cost = cost_table(n, lits[i])
+        rP, rdb, rdg = grad_hist(level_histogram(ref_cost, m), betas[i], gammas[i])
+        assert abs(P[i] - rP) < 1e-12, i
+        assert np.abs(db[i] - rdb).max() < 1e-11, i
+        assert np.abs(dg[i] - rdg).max() < 1e-10, i
