@@ -18,7 +18,11 @@ Also reported (extra keys of the same JSON line):
   * ``adjoint``: batched adjoint gradients (256 instances, n = 20, p = 32),
   * ``xqaoa``: the X-QAOA comparator on the headline instance (p = 16),
   * ``rounds_to_target``: the single-pair rounds-to-target search over 512
-    instances.
+    instances,
+  * ``mlp``: angle-network inference over 65,536 instances and training steps,
+  * ``small_n_graph``: small states, eager calls against evolve-plan replays,
+  * ``fairness``: the fair-sampling Monte Carlo on the 5-variable worked
+    instance of Sec. IV.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -85,13 +89,14 @@ def host_info():
     return {"cpu_count": os.cpu_count(), "cpu_model": model}
 
 
-def cpu_baseline(legs: bool = True):
+def cpu_baseline(legs: bool = True, fair=None):
     """The oracle on bounded samples of each workload (one thread each).
 
     Headline: its statevector evolution (complex128, numpy) of one seed-2
     instance at n = 22, m = 92, p = 64 rounds. With ``legs``, beside it: the
     level-space path on 64 instances of the scan workload, the adjoint at the
-    gradient workload's size, the MLP on one batch of 256 and the X mixer."""
+    gradient workload's size, the MLP on one batch of 256, the X mixer and,
+    given the fairness leg's distribution, the fair-sampling Monte Carlo."""
     from oracle.cost import cost_table, level_histogram
     from oracle.evolve import evolve_hist, evolve_sv
     from paper_2402_02585_amd import instances as inst
@@ -175,6 +180,22 @@ def cpu_baseline(legs: bool = True):
     t_x = time.perf_counter() - t0
     out["legs"]["xqaoa"] = {"value": (1 << n) * p / t_x, "unit": "amplitude-rounds/s",
                             "sample": f"oracle X-mixer evolution, n={n} m={m} p={p}, complex128 ({t_x:.1f} s)"}
+    if fair is not None:
+        # fair sampling: the oracle's Monte Carlo on the leg's distribution
+        from oracle.fairness import draws_to_reject, shots_to_all
+        t0 = time.perf_counter()
+        so = shots_to_all(fair["p_sol"], 5000, 102, 1 << 30)
+        t_so = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        do = draws_to_reject(fair["p_sol"], 3, 202, fair["crit"], fair["n_min"], fair["max_draws"])
+        t_do = time.perf_counter() - t0
+        d_draws = int(do.sum()) + int((do == 0).sum()) * fair["max_draws"]
+        out["legs"]["fairness"] = {
+            "shots_per_s": int(so.sum()) / t_so, "draws_per_s": d_draws / t_do,
+            "gpu_over_oracle_shots": fair["gpu_shots_per_s"] / (int(so.sum()) / t_so),
+            "gpu_over_oracle_draws": fair["gpu_draws_per_s"] / (d_draws / t_do),
+            "sample": f"oracle Monte Carlo on the leg's distribution: 5000 shots-to-all runs ({t_so:.1f} s), "
+                      f"3 chi-squared trials ({d_draws} draws, {t_do:.1f} s), same seeds as the device runs"}
     return out
 
 
@@ -419,6 +440,53 @@ def adjoint_leg(torch, g, inst, reps: int = 2):
     return res
 
 
+def fairness_leg(torch, g, inst):
+    """Fair-sampling Monte Carlo (Sec. IV): the 5-variable worked instance under
+    G-QAOA at p = 2 with its energy-minimizing angles; 100,000 runs of
+    shots-to-all-solutions and 10,000 chi-squared trials of at most 1e5 draws.
+    Returns the leg and the solution probabilities (for the oracle's timing)."""
+    from paper_2402_02585_amd import fairness, fairness_eval
+
+    n, text = fairness_eval.PAPER_INSTANCES["5var"]
+    lits = inst.parse_paper_clauses(text)
+    m = lits.shape[0]
+    cost, hist = g.gqaoa_cost_table(n, lits)
+    x = fairness_eval.angles("G", n, m, cost, hist)[2]
+    psi, psol, _, _ = g.gqaoa_evolve(n, m, cost, x[:2], x[2:], dtype=g.C128)
+    _, pr = fairness.solution_probs(cost, psi)
+    K = pr.size
+    runs, trials, max_draws = 100000, 10000, 100000
+    crit = fairness.chi2_critical(K)
+    g.gqaoa_shots_to_all(pr, 1000, 7, 1 << 30)           # warm-up
+    g.gqaoa_draws_to_reject(pr, 64, 7, crit, 5 * K, 1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    shots = g.gqaoa_shots_to_all(pr, runs, 102, 1 << 30)
+    torch.cuda.synchronize()
+    t_shots = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rej = g.gqaoa_draws_to_reject(pr, trials, 202, crit, 5 * K, max_draws)
+    torch.cuda.synchronize()
+    t_rej = time.perf_counter() - t0
+    s = shots.cpu().numpy().astype(np.int64)
+    d = rej.cpu().numpy().astype(np.int64)
+    never = int((d == 0).sum())
+    draws = int(d.sum()) + never * max_draws
+    res = {
+        "workload": f"Sec. IV 5-variable instance (K={K} solutions), G-QAOA p=2 at its energy-minimizing angles "
+                    f"(P_sol {psol[-1]:.4f}); {runs} shots-to-all runs, {trials} chi-squared trials "
+                    f"(n_min 5K, at most {max_draws} draws)",
+        "shots_to_all": {"seconds": t_shots, "runs_per_s": runs / t_shots, "shots_per_s": int(s.sum()) / t_shots,
+                         "mean_shots": float(s.mean())},
+        "draws_to_reject": {"seconds": t_rej, "trials_per_s": trials / t_rej, "draws_per_s": draws / t_rej,
+                            "median_draws": float(np.median(np.where(d > 0, d, np.inf))),
+                            "never_rejected": never},
+    }
+    return res, {"p_sol": pr, "crit": crit, "n_min": 5 * K, "max_draws": max_draws,
+                 "gpu_shots_per_s": res["shots_to_all"]["shots_per_s"],
+                 "gpu_draws_per_s": res["draws_to_reject"]["draws_per_s"]}
+
+
 def xqaoa_leg(torch, g, inst, it, reps: int = 3):
     """X-QAOA comparator (transverse-field mixer) on the headline instance:
     n = 28, complex64, p = 16 (the first 16 headline angle pairs)."""
@@ -596,6 +664,7 @@ def main():
     ap.add_argument("--skip-rounds", action="store_true", help="omit the rounds-to-target leg")
     ap.add_argument("--skip-mlp", action="store_true", help="omit the angle-MLP leg")
     ap.add_argument("--skip-small", action="store_true", help="omit the small-n eager vs graph leg")
+    ap.add_argument("--skip-fairness", action="store_true", help="omit the fair-sampling Monte Carlo leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
@@ -706,8 +775,11 @@ def main():
         out["mlp"] = mlp_leg(torch, g)
     if not args.skip_small:
         out["small_n_graph"] = small_n_leg(torch, g, inst)
+    fair = None
+    if not args.skip_fairness:
+        out["fairness"], fair = fairness_leg(torch, g, inst)
     if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(fair=fair)
     print(json.dumps(out), flush=True)
 
 

@@ -7,8 +7,8 @@
 //     a non-solution outcome) until every solution was seen; a 64-bit mask
 //     records the solutions seen.
 //   * shots-to-reject-fairness: one wave per trial draws from the
-//     distribution conditioned on solutions; lane k holds the count O_k, a
-//     ballot finds the drawn category, and the chi-squared test against the
+//     distribution conditioned on solutions, 64 draws per step (one per
+//     lane); lane k holds the count O_k, and the chi-squared test against the
 //     uniform distribution is taken after every draw from N >= n_min on, in
 //     the exact integer form K sum O_k^2 - N^2 > crit N.
 //
@@ -63,28 +63,64 @@ __global__ void __launch_bounds__(256) shots_all_kernel(const double *__restrict
     out[r] = res;
 }
 
+// One wave per trial, 64 consecutive draws per step: lane l takes draw
+// N0 + l + 1 (its own SplitMix64 output) and finds its category by binary
+// search of the cdf; per-category ballots give each draw the number of
+// earlier draws of its category within the step, hence the count O_k just
+// before it; the increments 2 O_k + 1 of sum O_k^2, prefix-summed over the
+// lanes, give the sum after every draw, so each lane evaluates the test for
+// its N exactly as a draw-by-draw loop would (same integers, same double
+// comparison) and the first rejecting lane ends the trial.
 __global__ void __launch_bounds__(256) reject_kernel(const double *__restrict__ cdf, int K, int trials, uint64_t seed,
                                                      double crit, int n_min, int max_draws, int32_t *__restrict__ out) {
+    __shared__ double cs[kFairMaxK];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) cs[i] = cdf[i];
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int trial = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (trial >= trials) return;  // whole waves
-    // lane k < K-1 draws when u < cdf[k]; lanes from K-1 on always match, so
-    // the first match is k, or K-1 when u is past cdf[K-2]
-    const double c = lane < K - 1 ? cdf[lane] : __builtin_huge_val();
-    int cnt = 0;          // O_lane
-    int64_t sumsq = 0;    // sum_k O_k^2, the same in every lane
+    if (trial >= trials) return;  // whole waves, after the block's barrier
+    const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
+    int cnt = 0;          // O_lane (lanes < K)
+    int64_t sumsq = 0;    // sum_k O_k^2 before the step, the same in every lane
     int res = 0;
-    for (int N = 1; N <= max_draws; ++N) {
+    for (int N0 = 0; N0 < max_draws; N0 += kWave) {
+        const int N = N0 + lane + 1;  // this lane's draw count
         const double u = uniform_at(seed, ((uint64_t)trial << 32) + (uint64_t)(N - 1));
-        const uint64_t b = __ballot(u < c);
-        const int k = __builtin_ctzll(b);
-        const int ck = __shfl(cnt, k, kWave);
-        sumsq += 2 * (int64_t)ck + 1;
-        if (lane == k) ++cnt;
-        if (N >= n_min && (double)((int64_t)K * sumsq - (int64_t)N * N) > crit * (double)N) {
-            res = N;
+        // first k < K-1 with u < cdf[k] (cdf nondecreasing), else K-1
+        int lo = 0, len = K - 1;
+        while (len > 0) {
+            const int half = len >> 1;
+            if (u < cs[lo + half]) {
+                len = half;
+            } else {
+                lo += half + 1;
+                len -= half + 1;
+            }
+        }
+        const int cat = lo;
+        int earlier = 0, add = 0;
+        for (int k = 0; k < K; ++k) {
+            const uint64_t m = __ballot(cat == k);
+            if (cat == k) earlier = __popcll(m & below);
+            if (lane == k) add = __popcll(m);
+        }
+        const int ck = __shfl(cnt, cat, kWave) + earlier;  // O_cat just before this draw
+        int64_t s = 2 * (int64_t)ck + 1;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {  // inclusive prefix sum over the lanes
+            const int64_t t = __shfl_up(s, off, kWave);
+            if (lane >= off) s += t;
+        }
+        const int64_t sq = sumsq + s;
+        const bool rej = N <= max_draws && N >= n_min &&
+                         (double)((int64_t)K * sq - (int64_t)N * N) > crit * (double)N;
+        const uint64_t r = __ballot(rej);
+        if (r) {
+            res = N0 + __builtin_ctzll(r) + 1;
             break;
         }
+        sumsq += __shfl(s, kWave - 1, kWave);
+        cnt += add;
     }
     if (lane == 0) out[trial] = res;
 }
