@@ -115,10 +115,12 @@ def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
     return ps.reshape(I).cpu().numpy().astype(np.float64)
 
 
-def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.25, 0.06, 0.015), zoom: int = 16):
+def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 0.015), zoom: int = 16):
     """Best pair after one zoom x zoom window scan per width, each centred on the
     previous best (one replay of a graph-captured scan per width, all
-    instances). The peak narrows as p grows, hence three shrinking windows."""
+    instances). The peak narrows as p grows, hence shrinking windows; at
+    p = 64 the network's pair can sit a few tenths of a radian in beta from
+    the optimum, hence the first window's half-width of 0.5."""
     I = len(ns)
     b = np.asarray(betas, dtype=np.float64).copy()
     gm = np.asarray(gammas, dtype=np.float64).copy()
@@ -134,8 +136,9 @@ def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.25, 0.06, 0.015
         else:
             ps, _ = plan.run(bgrid, ggrid)
         v = ps[:, 0].reshape(I, -1)
-        j = v.argmax(dim=1).cpu().numpy()
-        vj = v.cpu().numpy()[np.arange(I), j].astype(np.float64)
+        jt = v.argmax(dim=1)
+        vj = v.gather(1, jt[:, None])[:, 0].cpu().numpy().astype(np.float64)  # only the best cell leaves the GPU
+        j = jt.cpu().numpy()
         better = vj > best
         b[better] = bgrid[better, j[better] % zoom]
         gm[better] = ggrid[better, j[better] // zoom]

@@ -7,7 +7,7 @@ P_sol-maximizing pairs over the fundamental domain (the paper's pi/180 grid,
 then two zoom levels) at p in {1, 4, 16, 64}. Inference instances from SeedSequence(6),
 n ~ U{12..24}. Reported, per p and overall:
 
-* mean P_sol of the learned pair, of the learned pair plus three shrinking
+* mean P_sol of the learned pair, of the learned pair plus four shrinking
   16 x 16 local window scans, of the fixed cluster-median pair (clustering alone), of the
   batched optimizer (all inference instances) and of the plain per-instance
   optimizer (a seeded subsample);
