@@ -741,7 +741,7 @@ def main():
     traffic = read_traffic()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "sv_forward_kernel<float, true, true, 2, 8, 1, false>", "avg_launch_ms": avg_round_ms,
+                "kernel": "sv_forward_kernel<float, true, true, 2, 4, 1, false>", "avg_launch_ms": avg_round_ms,
                 "launches": args.steps * P_ROUNDS, "launches_timed": round_cnt,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
     cost_table = {"avg_launch_ms": ct_ms / max(ct_cnt, 1),

@@ -124,14 +124,15 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 }
 
 // Fixed-order reduction of R doubles across a block of kThreads threads.
-// Every thread passes its R values; thread 0 receives the block sums.
+// Every thread of the block passes its R values (the block converged: the
+// wave sums are the DPP ones); thread 0 receives the block sums.
 template <int R, int kThreads>
 __device__ __forceinline__ void block_sum(double (&v)[R], double *lds /* R*kThreads/64 */) {
     constexpr int kWaves = kThreads / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = wave_sum(v[r]);
+    for (int r = 0; r < R; ++r) v[r] = wave_sum_dpp(v[r]);
     if (lane == 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[wave * R + r] = v[r];

@@ -35,7 +35,6 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSvThreads = 256;
-constexpr int kMaxPassRowsPerInst = 4096;  // blocks of one instance in a streaming pass
 constexpr int kFwdR = 7;   // S.re, S.im, psol, energy, norm, T.re, T.im (T = sum over target level)
 constexpr int kRevR = 4;   // L.re, L.im (sum of lambda_{k-1}), G.re, G.im
 
@@ -621,30 +620,38 @@ __global__ void __launch_bounds__(kSvThreads) sv_reverse_kernel(RevArgs a) {
     }
 }
 
-// ---- finalizers (one block per instance, fixed-order sums) ------------------------
-// 1024 threads, each summing at most kFinRows rows of partials whose loads
-// are all issued before the first add: the finalize sits between two
-// bandwidth-bound passes, so its cost is one memory latency, not a chain.
+// ---- finalizers (fixed-order sums of the per-block partial rows) -----------------
+// A streaming pass writes one row of partial sums per block. One finalize
+// block of kFinThreads threads takes up to kFinThreads rows of an instance,
+// one row per thread with every load issued before the first add (the
+// finalize sits between two bandwidth-bound passes, so its cost is one memory
+// latency, not a chain). A pass with more blocks per instance is folded
+// first: fold_partials_kernel sums each run of kFinThreads rows into one row,
+// in the same fixed order, so at most kMaxPassBlocks / kFinThreads plus one
+// row per instance remain.
 constexpr int kFinThreads = 1024;
-constexpr int kFinRows = kMaxPassRowsPerInst / kFinThreads;
 
 template <int R>
-__device__ __forceinline__ void reduce_partials(const double *p, int nblocks, double (&r)[R],
-                                                double *lds) {
-    double v[kFinRows][R];
+__device__ __forceinline__ void reduce_partials(const double *p, int nblocks /* <= kFinThreads */,
+                                                double (&r)[R], double *lds) {
+    const int b = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < kFinRows; ++i) {
-        const int b = threadIdx.x + i * kFinThreads;
-#pragma unroll
-        for (int k = 0; k < R; ++k) v[i][k] = b < nblocks ? p[(size_t)b * R + k] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        r[k] = 0.0;
-#pragma unroll
-        for (int i = 0; i < kFinRows; ++i) r[k] += v[i][k];
-    }
+    for (int k = 0; k < R; ++k) r[k] = b < nblocks ? p[(size_t)b * R + k] : 0.0;
     block_sum<R, kFinThreads>(r, lds);
+}
+
+// Block (f, i): rows [f kFinThreads, (f + 1) kFinThreads) of instance i's
+// nrows partial rows, summed into row f of the folded rows [inst][nfold][R].
+template <int R>
+__global__ void __launch_bounds__(kFinThreads) fold_partials_kernel(const double *p, int nrows, double *q, int nfold) {
+    __shared__ double lds[R * kFinThreads / kWave];
+    const int inst = blockIdx.y;
+    const int first = blockIdx.x * kFinThreads;
+    double r[R];
+    reduce_partials<R>(p + ((size_t)inst * nrows + first) * R, min(kFinThreads, nrows - first), r, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < R; ++k) q[((size_t)inst * nfold + blockIdx.x) * R + k] = r[k];
 }
 
 __global__ void __launch_bounds__(kFinThreads) sv_finalize_kernel(FinArgs a) {
@@ -696,20 +703,25 @@ struct PassShape {
     int amp, unroll, blocks_x, nt;
 };
 
-constexpr int kMaxPassBlocks = 4096;  // partial-sum rows per launch (all instances)
+constexpr int kMaxPassBlocks = 65536;  // partial-sum rows per launch (all instances)
 
 // Launch shape of the streaming passes. A lane moves exactly one 16-byte
 // chunk of the state per group (2 complex64 or 1 complex128 amplitudes), so
 // each wave-wide load or store instruction covers 1 KiB of contiguous memory;
-// UNROLL groups per loop trip keep that many loads in flight per lane.
+// UNROLL groups per loop trip keep that many loads in flight per lane. By
+// default the grid gives every block one tile (4 groups per lane, 256 blocks
+// per CU allowed, up to kMaxPassBlocks rows): at n = 28 that streams about 5%
+// faster than a persistent grid of 16 blocks per CU looping over 8-group
+// tiles, and the extra partial rows are folded before the finalize. The
+// fused finalize (the last block sums every row) keeps the persistent grid.
 // GQAOA_SV_SHAPE="amp,unroll,blocks_per_cu,nt" overrides the round pass (a
 // tuning hook; shapes outside the compiled set fall back to the default).
-static PassShape pass_shape(uint64_t N, int num_inst, int dtype, const DeviceInfo &dev) {
+static PassShape pass_shape(uint64_t N, int num_inst, int dtype, const DeviceInfo &dev, bool fused = false) {
     PassShape s;
-    int bpc = 16;
+    int bpc = fused ? 16 : 256;
     s.nt = 1;
     s.amp = dtype == GQAOA_C64 ? 2 : 1;
-    s.unroll = 8;
+    s.unroll = fused ? 8 : 4;
     if (const char *e = getenv("GQAOA_SV_SHAPE")) {
         int a = 0, u = 0, b = 0, t = 1;
         if (sscanf(e, "%d,%d,%d,%d", &a, &u, &b, &t) >= 3 && a > 0 && u > 0 && b > 0) {
@@ -727,7 +739,7 @@ static PassShape pass_shape(uint64_t N, int num_inst, int dtype, const DeviceInf
     const uint64_t per_block = (uint64_t)kSvThreads * s.amp * s.unroll;
     const uint64_t want = (N + per_block - 1) / per_block;
     const uint64_t cap = std::max<uint64_t>(1, (uint64_t)std::min(kMaxPassBlocks, dev.num_cus * bpc) / num_inst);
-    static_assert(kMaxPassBlocks <= kMaxPassRowsPerInst, "finalize covers every row of an instance");
+    static_assert(kMaxPassBlocks / kFinThreads <= kFinThreads, "one fold leaves rows for one finalize block");
     s.blocks_x = (int)std::max<uint64_t>(1, std::min(want, cap));
     return s;
 }
@@ -751,6 +763,7 @@ static void launch_fwd_t(const PassShape &s, int num_inst, const FwdArgs &a, hip
             GQ_FWD_SHAPE(T, 4, 4, 1) GQ_FWD_SHAPE(T, 4, 4, 0)
         }
         if (s.unroll == 1) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 1>), grid, block, 0, st, a);
+        else if (s.unroll == 4) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 4>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 2, 8>), grid, block, 0, st, a);
     } else {
         if constexpr (PHASE && WRITE) {
@@ -761,6 +774,7 @@ static void launch_fwd_t(const PassShape &s, int num_inst, const FwdArgs &a, hip
             GQ_FWD_SHAPE(T, 1, 4, 1) GQ_FWD_SHAPE(T, 1, 16, 1) GQ_FWD_SHAPE(T, 1, 8, 0) GQ_FWD_SHAPE(T, 2, 4, 1)
         }
         if (s.unroll == 1) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 1>), grid, block, 0, st, a);
+        else if (s.unroll == 4) hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 4>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((sv_forward_kernel<T, PHASE, WRITE, 1, 8>), grid, block, 0, st, a);
     }
 }
@@ -784,9 +798,11 @@ static void launch_rev_t(const PassShape &s, int num_inst, const RevArgs &a, hip
     const dim3 grid(s.blocks_x, num_inst), block(kSvThreads);
     if constexpr (sizeof(T) == 4) {
         if (s.unroll == 1) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 1>), grid, block, 0, st, a);
+        else if (s.unroll == 4) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 4>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 2, 8>), grid, block, 0, st, a);
     } else {
         if (s.unroll == 1) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 1>), grid, block, 0, st, a);
+        else if (s.unroll == 4) hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 4>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((sv_reverse_kernel<T, FIRST, WRITE, 1, 8>), grid, block, 0, st, a);
     }
 }
@@ -815,7 +831,7 @@ static void launch_rev(int dtype, bool first, bool write, const PassShape &s, in
 // ---- workspace layout ---------------------------------------------------------------
 // Small tables first (per instance), then the state slots used by the adjoint.
 struct SvLayout {
-    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, angles, target, counter, partials;
+    size_t lut, mixf, mixb, ebeta, delta, S, readout, T, eps, dbeta, dgamma, angles, target, counter, partials, folded;
     size_t slots, slot_bytes, nslots, total;
 };
 
@@ -842,6 +858,7 @@ static SvLayout sv_layout(int num_inst, int n, int p, int dtype, int ckpt_every,
     L.target = o;   o += al256(I * 4);
     L.counter = o;  o += al256(I * 4);
     L.partials = o; o += al256(std::max<size_t>(kMaxPassBlocks, I) * kFwdR * 8);
+    L.folded = o;   o += al256((kMaxPassBlocks / kFinThreads + I) * kFwdR * 8);  // rows left after a fold
     L.slots = o;
     L.slot_bytes = al256(I * ((size_t)1 << n) * cs);
     L.nslots = 0;
@@ -942,17 +959,47 @@ static FinArgs base_fin_args(const FwdPlan &P) {
     return f;
 }
 
+// Finalize of a pass with P.shape.blocks_x partial rows per instance, folded
+// first when one finalize block cannot take them all.
+template <int R>
+static int fold_for_finalize(const FwdPlan &P, const double *rows, const double **out, int *out_rows,
+                             hipStream_t st) {
+    const int n = P.shape.blocks_x;
+    if (n <= kFinThreads) {
+        *out = rows;
+        *out_rows = n;
+        return GQAOA_OK;
+    }
+    const int nfold = (n + kFinThreads - 1) / kFinThreads;
+    double *q = reinterpret_cast<double *>(P.ws + P.L.folded);
+    hipLaunchKernelGGL(fold_partials_kernel<R>, dim3(nfold, P.num_inst), dim3(kFinThreads), 0, st, rows, n, q, nfold);
+    GQ_LAUNCH_CHECK();
+    *out = q;
+    *out_rows = nfold;
+    return GQAOA_OK;
+}
+
+static int launch_finalize(const FwdPlan &P, FinArgs f, hipStream_t st) {
+    int s = fold_for_finalize<kFwdR>(P, f.partials, &f.partials, &f.nblocks, st);
+    if (s) return s;
+    hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
+    GQ_LAUNCH_CHECK();
+    return GQAOA_OK;
+}
+
 // GQAOA_SV_FUSE=1 folds the finalize into the last block of the round pass
-// (one launch per round). It is off by default: the release fence each block
-// needs before counting itself done writes back its XCD's L2, which costs more
-// bandwidth than the separate finalize launch saves (0.99 vs 0.75 ms per
-// round at n = 28, complex64).
+// (one launch per round, on the persistent grid). It is off by default: the
+// release fence each block needs before counting itself done writes back its
+// XCD's L2, which costs more bandwidth than the separate finalize launch saves
+// (0.99 vs 0.75 ms per round at n = 28, complex64).
+static bool fuse_requested() {
+    const char *e = getenv("GQAOA_SV_FUSE");
+    return e && e[0] == '1';
+}
+
 static bool fused_round(const FwdPlan &P) {
     if (P.fuse_mode < 0) return false;
-    if (P.fuse_mode == 0) {
-        const char *e = getenv("GQAOA_SV_FUSE");
-        if (!e || e[0] != '1') return false;
-    }
+    if (P.fuse_mode == 0 && !fuse_requested()) return false;
     const PassShape &s = P.shape;
     return s.unroll == 8 && s.nt == 1 && s.amp == (P.dtype == GQAOA_C64 ? 2 : 1);
 }
@@ -983,10 +1030,7 @@ static int forward_round(const FwdPlan &P, int j, const void *psi_in, void *psi_
     launch_fwd(P.dtype, true, true, P.shape, P.num_inst, a, st);
     ps.end();
     GQ_LAUNCH_CHECK();
-    if (finalize && !fused) {
-        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
-        GQ_LAUNCH_CHECK();
-    }
+    if (finalize && !fused) return launch_finalize(P, f, st);
     return GQAOA_OK;
 }
 
@@ -1003,9 +1047,7 @@ static int final_pass(const FwdPlan &P, const void *psi_in, void *psi_out, bool 
     GQ_LAUNCH_CHECK();
     FinArgs f = base_fin_args(P);
     f.readout_out = reinterpret_cast<double *>(P.ws + P.L.readout) + 3 * P.p;
-    hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
-    GQ_LAUNCH_CHECK();
-    return GQAOA_OK;
+    return launch_finalize(P, f, st);
 }
 
 static int prepare_plan(FwdPlan &P, int num_inst, int n, const int32_t *m_of, const uint8_t *cost,
@@ -1024,7 +1066,7 @@ static int prepare_plan(FwdPlan &P, int num_inst, int n, const int32_t *m_of, co
     P.N = 1ull << n;
     P.ws = reinterpret_cast<char *>(ws);
     P.L = sv_layout(num_inst, n, p, dtype, ckpt_every, grad);
-    P.shape = pass_shape(P.N, num_inst, dtype, dev);
+    P.shape = pass_shape(P.N, num_inst, dtype, dev, fuse_requested());
     P.cost = cost;
     if (p > 0) {
         build_tables(num_inst, m_of, p, beta, gamma, dtype, keep_lut, keep_f, keep_b, keep_e);
@@ -1142,8 +1184,7 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
         fa.stride = 2 * (p + 1);
         fa.eps_out = reinterpret_cast<double *>(P.ws + P.L.eps);
         fa.dbeta_out = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (p - 1);
-        hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, fa);
-        GQ_LAUNCH_CHECK();
+        if ((s = launch_finalize(P, fa, st))) return s;
     }
     // reverse sweep, segment by segment
     const size_t cs = dtype == GQAOA_C64 ? 8 : 16;
@@ -1190,6 +1231,7 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
                 rf.eps_out = reinterpret_cast<double *>(P.ws + P.L.eps);
                 rf.dbeta_km1 = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (k - 2);
             }
+            if ((s = fold_for_finalize<kRevR>(P, rf.partials, &rf.partials, &rf.nblocks, st))) return s;
             hipLaunchKernelGGL(sv_rev_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, rf);
             GQ_LAUNCH_CHECK();
         }
@@ -1318,7 +1360,6 @@ int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int 
     P.N = 1ull << n;
     P.ws = reinterpret_cast<char *>(ws);
     P.L = sv_layout(1, n, p, dtype, 0, false);
-    P.shape = pass_shape(P.N, 1, dtype, dev);
     P.cost = cost;
     // One launch per round: the finalize folded into the round pass when the
     // state stays in the last-level cache (at most 64 MB), where the pass's
@@ -1326,6 +1367,7 @@ int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int 
     // finalizing block after every round.
     const size_t state_bytes = ((size_t)1 << n) * (dtype == GQAOA_C64 ? 8 : 16);
     P.fuse_mode = state_bytes <= (size_t(64) << 20) ? 1 : -1;
+    P.shape = pass_shape(P.N, 1, dtype, dev, P.fuse_mode > 0);
     GQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&E->stage), sizeof(double) * (2 * (size_t)p + 3 * ((size_t)p + 1)),
                          hipHostMallocDefault));
     GQ_HIP(hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking));

@@ -135,9 +135,12 @@ def test_full_size_n28_p64_complex64():
 
 @pytest.mark.parametrize("dt", [g.C64, g.C128])
 def test_fused_and_separate_finalize_agree(dt, monkeypatch):
-    """The round pass either launches its finalize separately (default) or
-    folds it into its last block (GQAOA_SV_FUSE=1); both sum the same partial
-    rows, in different fixed orders, so results agree to rounding."""
+    """The round pass either launches its finalize separately (default, one
+    tile per block) or folds it into its last block (GQAOA_SV_FUSE=1, on the
+    persistent grid). The two grids round their float32 tile sums differently,
+    so the results agree to the state's precision: 1e-6 on P_sol and the norm,
+    1e-6 m on E (E is of order m/8) for complex64; 1e-14 (times m for E) for
+    complex128."""
     need_gpu()
     n, m = 18, 76
     lits = rand_lits(n, m, 44)
@@ -147,8 +150,8 @@ def test_fused_and_separate_finalize_agree(dt, monkeypatch):
     monkeypatch.setenv("GQAOA_SV_FUSE", "1")
     fused = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=dt)
     monkeypatch.delenv("GQAOA_SV_FUSE")
-    for a, b in zip(fused[1:], sep[1:]):
-        assert np.abs(a - b).max() < (1e-14 if dt == g.C128 else 1e-6)
+    for a, b, scale in zip(fused[1:], sep[1:], (1, m, 1)):
+        assert np.abs(a - b).max() < (1e-14 if dt == g.C128 else 1e-6) * scale
     ref = evolve_sv(n, cost_table(n, lits), beta, gamma)
     _check(fused, ref, dt, m)
 
