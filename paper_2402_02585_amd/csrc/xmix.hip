@@ -37,7 +37,7 @@ constexpr int kXThreads = 256;
 constexpr int kXThreadBits = 8;
 constexpr int kXTileBytesLog2 = 15;  // 32 KiB of LDS per tile
 constexpr int kXGroupBits = 8;       // qubits of a full high group
-constexpr int kXMaxBlocks = 4096;
+constexpr int kXMaxBlocks = 8192;
 constexpr int kXR = 7;  // partial sums per block of the small-n kernel
 constexpr int kXMaxChunks = 6;
 
@@ -593,7 +593,9 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
         const XGroup &last = groups[G - 1];
         const uint64_t total = 1ull << n;
         const uint64_t ntiles = total >> TB;
-        const int blocks = (int)std::min<uint64_t>(ntiles, std::min<uint64_t>((uint64_t)dev.num_cus * 8, kXMaxBlocks));
+        // 32 blocks per CU (about 4 resident at once by LDS): at n = 28 the passes
+        // ran 3% faster per round than with 8 per CU, and no faster with more
+        const int blocks = (int)std::min<uint64_t>(ntiles, std::min<uint64_t>((uint64_t)dev.num_cus * 32, kXMaxBlocks));
         {
             const int cb = (int)std::min<uint64_t>((total + 255) / 256, (uint64_t)dev.num_cus * 16);
             hipLaunchKernelGGL(x_cost_tiles_kernel, dim3(cb), dim3(256), 0, st, cost, L.cost_t, TB, last.mlo, last.q0,
