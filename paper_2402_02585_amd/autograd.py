@@ -3,7 +3,9 @@
 ``GQAOAProb.apply(betas, gammas, cost, n, m, ...)`` returns P_sol after
 len(betas) rounds of Eq. (3) from |s> (float64 scalar tensor); its backward
 returns dP/dbeta_k and dP/dgamma_k from the device adjoint sweep
-(``gqaoa_grad``: reverse sweep with checkpoints every ``ckpt_every`` rounds).
+(``gqaoa_grad``: reverse sweep with checkpoints every ``ckpt_every`` rounds;
+None keeps every round's state when that fits in device memory and
+checkpoints only when it does not).
 The forward call computes the gradient too (one adjoint sweep) and keeps it
 for the backward. ``GQAOAProbBatched`` does the same for a batch of
 instances with equal n (betas, gammas: [I, p]; returns P_sol[I]).
@@ -20,7 +22,7 @@ from . import gqaoa as g
 class GQAOAProb(torch.autograd.Function):
     @staticmethod
     def forward(ctx, betas, gammas, cost, n: int, m: int, target_level: int = 0, dtype=g.C128,
-                ckpt_every: int = 0):
+                ckpt_every: int | None = None):
         b = betas.detach().cpu().double().numpy()
         gm = gammas.detach().cpu().double().numpy()
         P, db, dg = g.gqaoa_grad(n, m, cost, b, gm, dtype, target_level, ckpt_every)
@@ -36,7 +38,7 @@ class GQAOAProb(torch.autograd.Function):
 
 class GQAOAProbBatched(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, betas, gammas, costs, n: int, ms, targets=None, dtype=g.C128, ckpt_every: int = 0):
+    def forward(ctx, betas, gammas, costs, n: int, ms, targets=None, dtype=g.C128, ckpt_every: int | None = None):
         b = betas.detach().cpu().double().numpy()
         gm = gammas.detach().cpu().double().numpy()
         P, db, dg = g.gqaoa_grad_batched(n, ms, costs, b, gm, dtype, targets, ckpt_every)

@@ -339,18 +339,43 @@ def gqaoa_grad_workspace_bytes(num_inst: int, n: int, p: int, dtype=C128, ckpt_e
     return int(load_library().gqaoa_grad_workspace_bytes(num_inst, n, p, _dtype_code(dtype), ckpt_every))
 
 
-def gqaoa_grad(n: int, m: int, cost, betas, gammas, dtype=C128, target_level: int = 0, ckpt_every: int = 0,
+def choose_ckpt_every(num_inst: int, n: int, p: int, dtype=C128, budget_bytes: int | None = None) -> int:
+    """Checkpoint interval of the adjoint sweep for a workspace budget: 0
+    (every round's state kept, nothing recomputed) when that fits, else the
+    largest interval whose workspace fits, which recomputes the fewest rounds
+    (the rounds of every segment but the last). The budget defaults to 90% of
+    the device's free memory. Raises GQAOAError (EWORKSPACE) when no interval
+    fits."""
+    lib = load_library()
+    dt = _dtype_code(dtype)
+    if budget_bytes is None:
+        free, _ = _torch().cuda.mem_get_info()
+        budget_bytes = int(0.9 * free)
+    if lib.gqaoa_grad_workspace_bytes(num_inst, n, p, dt, 0) <= budget_bytes:
+        return 0
+    for c in range(p - 1, 0, -1):
+        if lib.gqaoa_grad_workspace_bytes(num_inst, n, p, dt, c) <= budget_bytes:
+            return c
+    raise GQAOAError(-3, "no checkpoint interval fits the workspace budget",
+                     f"{num_inst} instances, n={n}, p={p}, budget {budget_bytes} bytes")
+
+
+def gqaoa_grad(n: int, m: int, cost, betas, gammas, dtype=C128, target_level: int = 0, ckpt_every: int | None = None,
                workspace=None, stream=None):
-    """Returns (P, dP/dbeta[p], dP/dgamma[p]) by the adjoint sweep."""
+    """Returns (P, dP/dbeta[p], dP/dgamma[p]) by the adjoint sweep (ckpt_every
+    as in gqaoa_grad_batched)."""
     P, db, dg = gqaoa_grad_batched(n, [m], cost, np.asarray(betas)[None, :], np.asarray(gammas)[None, :], dtype,
                                    [target_level], ckpt_every, workspace, stream)
     return float(P[0]), db[0], dg[0]
 
 
-def gqaoa_grad_batched(n: int, ms, costs, betas, gammas, dtype=C128, targets=None, ckpt_every: int = 0,
+def gqaoa_grad_batched(n: int, ms, costs, betas, gammas, dtype=C128, targets=None, ckpt_every: int | None = None,
                        workspace=None, stream=None):
     """Batched adjoint: costs uint8 [I, 2^n] (contiguous), betas/gammas [I, p].
-    Returns (P[I], dbeta[I, p], dgamma[I, p])."""
+    ckpt_every: rounds between stored states (0: every state kept); None
+    chooses it with choose_ckpt_every, within the given workspace's size or
+    the device's free memory, so states are recomputed only when keeping them
+    all would not fit. Returns (P[I], dbeta[I, p], dgamma[I, p])."""
     torch = _torch()
     lib = load_library()
     dt = _dtype_code(dtype)
@@ -359,6 +384,8 @@ def gqaoa_grad_batched(n: int, ms, costs, betas, gammas, dtype=C128, targets=Non
     g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64))
     I, p = b.shape
     tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    if ckpt_every is None:
+        ckpt_every = choose_ckpt_every(I, n, p, dtype, None if workspace is None else workspace.numel())
     need = lib.gqaoa_grad_workspace_bytes(I, n, p, dt, ckpt_every)
     ws = workspace if workspace is not None else _workspace(torch, need)
     P, db, dg = np.empty(I), np.empty((I, p)), np.empty((I, p))

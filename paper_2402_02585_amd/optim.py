@@ -141,7 +141,7 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
 
 
 def full_gqaoa(n: int, m: int, cost, p: int, beta0: float, gamma0: float, target: int = 0, dtype=g.C128,
-               ckpt_every: int = 0):
+               ckpt_every: int | None = None):
     """All 2p angles by L-BFGS-B (maximizing P_sol) with the adjoint gradient,
     from the single-pair seed. Returns (betas, gammas, psol)."""
     x0 = np.concatenate([np.full(p, beta0), np.full(p, gamma0)])

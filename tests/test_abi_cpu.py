@@ -255,3 +255,20 @@ def test_binding_fails_loudly_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(g.GQAOAError):
         g.gqaoa_cost_table(5, [[0, 2, 4]])
+
+
+def test_checkpoint_interval_choice():
+    """ckpt_every=None: every state kept when that workspace fits the budget,
+    else the largest interval that fits (fewest recomputed rounds)."""
+    I, n, p = 4, 16, 32
+    ws = lambda c: g.gqaoa_grad_workspace_bytes(I, n, p, g.C128, c)
+    assert g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=ws(0)) == 0
+    budget = ws(0) - 1
+    c = g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=budget)
+    assert 1 <= c < p and ws(c) <= budget
+    assert all(ws(k) > budget for k in range(c + 1, p))
+    smallest = min(ws(k) for k in range(1, p))
+    c = g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=smallest)
+    assert ws(c) == smallest and all(ws(k) > smallest for k in range(c + 1, p))
+    with pytest.raises(g.GQAOAError):
+        g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=smallest - 1)

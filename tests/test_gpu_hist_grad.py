@@ -98,3 +98,28 @@ def test_grad_batched_adjoint_config_sample():
         if i == 0:
             sP, sdb, sdg = grad_sv(n, ref_cost, betas[i], gammas[i])
             assert np.abs(db[i] - sdb).max() < 1e-11 and np.abs(dg[i] - sdg).max() < 1e-10
+
+
+def test_grad_auto_checkpointing_matches_explicit():
+    """ckpt_every=None keeps every state when that fits (bit-identical to
+    ckpt_every=0); given a workspace one byte short of that, it checkpoints at
+    the largest interval that fits, and the recomputed states (the same
+    launches on the same inputs) give bit-identical results."""
+    torch = need_gpu()
+    n, m, p, I = 14, 59, 12, 3
+    costs = torch.empty((I, 2 ** n), dtype=torch.uint8, device="cuda")
+    for i in range(I):
+        g.gqaoa_cost_table(n, rand_lits(n, m, 400 + i), with_hist=False, cost=costs[i])
+    rng = np.random.Generator(np.random.PCG64(401))
+    betas, gammas = rng.uniform(0, np.pi, (I, p)), rng.uniform(0, np.pi, (I, p))
+    ref = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, ckpt_every=0)
+    auto = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas)
+    for a, b in zip(ref, auto):
+        assert np.array_equal(a, b)
+    budget = g.gqaoa_grad_workspace_bytes(I, n, p, g.C128, 0) - 1
+    c = g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=budget)
+    assert 1 <= c < p
+    ws = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    small = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, workspace=ws)
+    for a, b in zip(ref, small):
+        assert np.array_equal(a, b)
