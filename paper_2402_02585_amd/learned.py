@@ -44,6 +44,27 @@ class AngleMLP:
         self.grads = torch.empty(g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
         self.step = 0
 
+    def save(self, path):
+        """Checkpoint of the network and its optimizer: parameters, Adam
+        moments and step count, as a plain .npz (no pickled objects)."""
+        np.savez(path, params=self.params.cpu().numpy(), state=self.state.cpu().numpy(),
+                 step=np.array([self.step], dtype=np.int64))
+
+    @classmethod
+    def load(cls, path):
+        """A model restored from save(); training continues from the saved step."""
+        torch = _torch()
+        with np.load(path, allow_pickle=False) as f:
+            params, state, step = f["params"], f["state"], int(f["step"][0])
+        if params.shape != (g.MLP_NPARAMS,) or state.shape != (2 * g.MLP_NPARAMS,):
+            raise ValueError(f"{path}: not an angle-network checkpoint")
+        m = cls.__new__(cls)
+        m.params = torch.tensor(params, dtype=torch.float32, device="cuda")
+        m.state = torch.tensor(state, dtype=torch.float32, device="cuda")
+        m.grads = torch.empty(g.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        m.step = step
+        return m
+
     def outputs(self, x):
         """Raw outputs [B, 2] by the inference kernels (no activation cache)."""
         return g.gqaoa_mlp_infer(self.params, x.contiguous())

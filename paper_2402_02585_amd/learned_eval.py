@@ -15,6 +15,7 @@ n ~ U{12..24}. Reported, per p and overall:
   pairs below 0.99 of the cluster-median pair go to the batched optimizer).
 
 Usage: python -m paper_2402_02585_amd.learned_eval [--train N] [--test N] [--out file]
+       [--save ckpt.npz] [--load ckpt.npz]
 """
 from __future__ import annotations
 
@@ -48,6 +49,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None, help="write the trained network and its optimizer state (.npz)")
+    ap.add_argument("--load", default=None, help="start from a saved network; --steps more training steps (0: none)")
     a = ap.parse_args(argv)
 
     t0 = time.perf_counter()
@@ -62,12 +65,17 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     log(f"labels for {a.train} x {len(P_LIST)} in {t_label:.2f} s")
-    model = learned.AngleMLP(seed=0)
+    model = learned.AngleMLP.load(a.load) if a.load else learned.AngleMLP(seed=0)
     t0 = time.perf_counter()
     losses = model.train(X, Y, steps=a.steps, batch=a.batch, lr=1e-3, log_every=max(1, a.steps // 8))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    log(f"trained {a.steps} steps in {t_train:.2f} s; loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}")
+    if losses:
+        log(f"trained {a.steps} steps in {t_train:.2f} s; loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}")
+    else:
+        losses = [(0, float("nan"))]
+    if a.save:
+        model.save(a.save)
     med = learned.cluster_median(lab, P_LIST)
 
     ns = [it.n for it in test]

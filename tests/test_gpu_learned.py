@@ -7,7 +7,9 @@ and checks on held-out instances that
     clustering-only baseline) in mean P_sol,
   * with one local window scan, the learned form reaches >= 0.99 of the
     batched optimizer's mean P_sol,
-  * the batched optimizer agrees with the plain per-call optimizer.
+  * the batched optimizer agrees with the plain per-call optimizer,
+  * a checkpoint restores the network and its optimizer exactly, and
+    training resumed from it continues bit for bit.
 """
 import math
 
@@ -38,7 +40,7 @@ def trained():
     ms = [it.m for it in test]
     hd = g.gqaoa_hist_batched(ns, ms, [it.lits for it in test], hist_stride=max(ms) + 1)
     return dict(model=model, losses=losses, lab=lab, test=test, ns=ns, ms=ms, hists_dev=hd,
-                hists=hd.cpu().numpy(), torch=torch)
+                hists=hd.cpu().numpy(), torch=torch, X=X, Y=Y)
 
 
 def test_training_reduces_loss(trained):
@@ -90,3 +92,22 @@ def test_plain_optimizer_agrees_with_batched():
         assert r["psol"] >= op[i, 0] - 2e-3
         assert r["psol"] == pytest.approx(psol_single_pair_hist(H[i, :it.m + 1], r["beta"], r["gamma"], 4), abs=1e-12)
         assert op[i, 0] >= r["psol"] - 2e-3
+
+
+def test_checkpoint_resume(trained, tmp_path):
+    """save() / load() keep parameters, Adam moments and the step count
+    exactly; two models restored from one checkpoint and trained on with the
+    same seed end bit-identical (the fixture's model is left untouched)."""
+    torch = trained["torch"]
+    model = trained["model"]
+    path = tmp_path / "angle_mlp.npz"
+    model.save(path)
+    a = learned.AngleMLP.load(path)
+    b = learned.AngleMLP.load(path)
+    assert torch.equal(a.params, model.params) and torch.equal(a.state, model.state) and a.step == model.step
+    la = a.train(trained["X"], trained["Y"], steps=50, batch=256, lr=1e-3, seed=3, log_every=49)
+    lb = b.train(trained["X"], trained["Y"], steps=50, batch=256, lr=1e-3, seed=3, log_every=49)
+    assert a.step == b.step == model.step + 50
+    assert torch.equal(a.params, b.params) and torch.equal(a.state, b.state)
+    assert la == lb
+    assert not torch.equal(a.params, model.params)
