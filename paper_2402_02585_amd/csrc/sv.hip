@@ -631,13 +631,20 @@ __global__ void __launch_bounds__(kSvThreads) sv_reverse_kernel(RevArgs a) {
 // row per instance remain.
 constexpr int kFinThreads = 1024;
 
-template <int R>
-__device__ __forceinline__ void reduce_partials(const double *p, int nblocks /* <= kFinThreads */,
+constexpr int kFinWave = kWave;  // finalize of at most one row per lane: one wave, no barrier
+
+template <int R, int T = kFinThreads>
+__device__ __forceinline__ void reduce_partials(const double *p, int nblocks /* <= T */,
                                                 double (&r)[R], double *lds) {
     const int b = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < R; ++k) r[k] = b < nblocks ? p[(size_t)b * R + k] : 0.0;
-    block_sum<R, kFinThreads>(r, lds);
+    if constexpr (T == kWave) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) r[k] = wave_sum_dpp(r[k]);
+    } else {
+        block_sum<R, T>(r, lds);
+    }
 }
 
 // Block (f, i): rows [f kFinThreads, (f + 1) kFinThreads) of instance i's
@@ -654,11 +661,13 @@ __global__ void __launch_bounds__(kFinThreads) fold_partials_kernel(const double
         for (int k = 0; k < R; ++k) q[((size_t)inst * nfold + blockIdx.x) * R + k] = r[k];
 }
 
-__global__ void __launch_bounds__(kFinThreads) sv_finalize_kernel(FinArgs a) {
-    __shared__ double lds[kFwdR * kFinThreads / kWave];
+// T threads: kFinThreads, or one wave when the instance has at most kFinWave rows
+template <int T>
+__global__ void __launch_bounds__(T) sv_finalize_kernel(FinArgs a) {
+    __shared__ double lds[kFwdR * T / kWave];
     const int inst = blockIdx.x;
     double r[kFwdR];
-    reduce_partials<kFwdR>(a.partials + (size_t)inst * a.nblocks * kFwdR, a.nblocks, r, lds);
+    reduce_partials<kFwdR, T>(a.partials + (size_t)inst * a.nblocks * kFwdR, a.nblocks, r, lds);
     if (threadIdx.x == 0) finalize_apply(a, inst, r);
 }
 
@@ -677,11 +686,12 @@ struct RevFinArgs {
     int grad_stride;
 };
 
-__global__ void __launch_bounds__(kFinThreads) sv_rev_finalize_kernel(RevFinArgs a) {
-    __shared__ double lds[kRevR * kFinThreads / kWave];
+template <int T>
+__global__ void __launch_bounds__(T) sv_rev_finalize_kernel(RevFinArgs a) {
+    __shared__ double lds[kRevR * T / kWave];
     const int inst = blockIdx.x;
     double r[kRevR];
-    reduce_partials<kRevR>(a.partials + (size_t)inst * a.nblocks * kRevR, a.nblocks, r, lds);
+    reduce_partials<kRevR, T>(a.partials + (size_t)inst * a.nblocks * kRevR, a.nblocks, r, lds);
     if (threadIdx.x != 0) return;
     a.dgamma_k[(size_t)inst * a.grad_stride] = 2.0 * r[3];
     if (a.mixb_km1) {
@@ -982,7 +992,8 @@ static int fold_for_finalize(const FwdPlan &P, const double *rows, const double 
 static int launch_finalize(const FwdPlan &P, FinArgs f, hipStream_t st) {
     int s = fold_for_finalize<kFwdR>(P, f.partials, &f.partials, &f.nblocks, st);
     if (s) return s;
-    hipLaunchKernelGGL(sv_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
+    if (f.nblocks <= kFinWave) hipLaunchKernelGGL(sv_finalize_kernel<kFinWave>, dim3(P.num_inst), dim3(kFinWave), 0, st, f);
+    else hipLaunchKernelGGL(sv_finalize_kernel<kFinThreads>, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
 }
@@ -1232,7 +1243,10 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
                 rf.dbeta_km1 = reinterpret_cast<double *>(P.ws + P.L.dbeta) + (k - 2);
             }
             if ((s = fold_for_finalize<kRevR>(P, rf.partials, &rf.partials, &rf.nblocks, st))) return s;
-            hipLaunchKernelGGL(sv_rev_finalize_kernel, dim3(P.num_inst), dim3(kFinThreads), 0, st, rf);
+            if (rf.nblocks <= kFinWave)
+                hipLaunchKernelGGL(sv_rev_finalize_kernel<kFinWave>, dim3(P.num_inst), dim3(kFinWave), 0, st, rf);
+            else
+                hipLaunchKernelGGL(sv_rev_finalize_kernel<kFinThreads>, dim3(P.num_inst), dim3(kFinThreads), 0, st, rf);
             GQ_LAUNCH_CHECK();
         }
     }
