@@ -529,9 +529,11 @@ def xqaoa_leg(torch, g, inst, it, reps: int = 3):
 def small_n_leg(torch, g, inst, calls: int = 200):
     """Launch-bound statevector calls: one instance evolved again and again
     with new angles, through the eager gqaoa_evolve and through a
-    graph-captured plan (one hipGraphLaunch per call)."""
+    graph-captured plan (one hipGraphLaunch per call). n = 10 and 14 take the
+    one-launch resident evolution; n = 20 the streaming round passes."""
     out = {}
-    for n, m, p, dt, name in ((10, 42, 20, g.C128, "n10_p20_c128"), (14, 59, 64, g.C64, "n14_p64_c64")):
+    for n, m, p, dt, name in ((10, 42, 20, g.C128, "n10_p20_c128"), (14, 59, 64, g.C64, "n14_p64_c64"),
+                              (20, 84, 32, g.C64, "n20_p32_c64")):
         it = inst.first_satisfiable(1, n, m)
         cost, _ = g.gqaoa_cost_table(n, it.lits)
         angles = [inst.uniform_angles(200 + k, p) for k in range(calls)]

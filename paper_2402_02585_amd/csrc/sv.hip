@@ -1273,8 +1273,7 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
 // their finalizes, the final readout pass — is captured once into a HIP
 // graph. A run uploads the 2p angles, replays the graph and reads back the
 // readouts; the tables are computed on the device from the angles, with the
-// same float64 reduction and rounding as the host tables of run_evolve. A
-// state of at most 64 MB takes the fused round pass (one launch per round).
+// same float64 reduction and rounding as the host tables of run_evolve.
 // Block (j, i): round j of instance i; ang[i] = (beta[p], gamma[p]), the
 // instance's m from m_dev (or m_all when m_dev is null); tables [i][p][256]
 // and [i][p][2].
@@ -1375,19 +1374,16 @@ int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int 
     P.ws = reinterpret_cast<char *>(ws);
     P.L = sv_layout(1, n, p, dtype, 0, false);
     P.cost = cost;
-    // One launch per round: the finalize folded into the round pass when the
-    // state stays in the last-level cache (at most 64 MB), where the pass's
-    // release fence is cheap; its counter is cleared here once and by the
-    // finalizing block after every round.
-    const size_t state_bytes = ((size_t)1 << n) * (dtype == GQAOA_C64 ? 8 : 16);
-    P.fuse_mode = state_bytes <= (size_t(64) << 20) ? 1 : -1;
-    P.shape = pass_shape(P.N, 1, dtype, dev, P.fuse_mode > 0);
+    // The round passes with their separate fold / finalize launches: on the
+    // one-tile grid they replay faster than the fused finalize at every size
+    // measured (n = 16..22, complex64).
+    P.fuse_mode = -1;
+    P.shape = pass_shape(P.N, 1, dtype, dev);
     GQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&E->stage), sizeof(double) * (2 * (size_t)p + 3 * ((size_t)p + 1)),
                          hipHostMallocDefault));
     GQ_HIP(hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking));
     const int32_t tg = target;
     GQ_HIP(hipMemcpyAsync(P.ws + P.L.target, &tg, 4, hipMemcpyHostToDevice, st));
-    GQ_HIP(hipMemsetAsync(P.ws + P.L.counter, 0, 4, st));  // outside the graph
     GQ_HIP(hipStreamSynchronize(st));  // tg ends here; the captured work reads the target from the workspace
     GQ_HIP(hipStreamBeginCapture(E->cap, hipStreamCaptureModeThreadLocal));
     s = enqueue_evolve(E, init_uniform, psi, E->cap);

@@ -26,10 +26,13 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("n,m,p,dtype,tol,otol", [(10, 42, 20, g.C128, 1e-12, 1e-12), (16, 67, 64, g.C64, 1e-6, 1e-5),
                                                   (6, 20, 7, g.C128, 1e-12, 1e-12),
-                                                  (15, 63, 12, g.C128, 1e-12, 1e-12)])
+                                                  (15, 63, 12, g.C128, 1e-12, 1e-12),
+                                                  (22, 92, 6, g.C64, 1e-6, 1e-5)])
 def test_plan_matches_eager_and_oracle(n, m, p, dtype, tol, otol):
     """n = 6, 10: both resident; n = 15 (complex128) and 16 (complex64): the
-    plan's fused streaming rounds against the eager separate finalizes."""
+    captured streaming rounds with their finalize launches against the eager
+    calls; n = 22: more than 1024 blocks per pass, so the captured graph also
+    folds the partial rows before each finalize."""
     torch = need_gpu()
     lits = rand_lits(n, m, 70 + n)
     cost, _ = g.gqaoa_cost_table(n, lits)
