@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published; counts packed two-wide FMAs
+VALU_LANE_OPS_PEAK = 39.3e12      # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one VALU instruction per lane and cycle
 PROFILE_EVERY = 7   # coprime with the 64 rounds of a step: the sampled launches cover every round index
 N_VARS, M_CLAUSES, P_ROUNDS = 28, 118, 64
 
@@ -346,7 +347,12 @@ def batched_leg(torch, g, inst, steps: int):
         "roofline": {"bound": "alu", "kernel": "scan_kernel", "achieved": scan_flops / t_scan / 1e12,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": scan_flops / t_scan / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
-                     "flops_per_scan": scan_flops, "mean_levels": float(levels.mean())},
+                     "flops_per_scan": scan_flops, "mean_levels": float(levels.mean()),
+                     # a level-round is 8 VALU instructions (phase 4, weighted sum 2, mixer 2) for 12 flops
+                     "valu_issue_frac": scan_flops * 8 / 12 / t_scan / VALU_LANE_OPS_PEAK,
+                     "note": "the fp32 peak counts packed two-wide FMAs, which this code does not emit; "
+                             "valu_issue_frac compares the issued lane-operations with one VALU instruction "
+                             "per lane and cycle"},
         "workload": "4096 satisfiable random 3-SAT, n~U{8..20}, d in {3.0,4.2,5.0}, beta,gamma=linspace(0,pi,64), "
                     "p in {1,4,16,64}, float32",
         "hist_batched_ms": t_hist * 1e3,
