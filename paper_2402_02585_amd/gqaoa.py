@@ -418,7 +418,10 @@ def gqaoa_scan_workspace_bytes(num_inst: int, hist_stride: int, nb: int, ng: int
 def _scan_common(ns, ms, hists, betas, gammas, targets, tile):
     ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
     ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
-    h = np.ascontiguousarray(np.asarray(hists).astype(np.uint64))
+    h = np.asarray(hists)
+    if h.dtype == np.int64:
+        h = h.view(np.uint64)        # counts: the same bits, no copy of a [I][stride] table
+    h = np.ascontiguousarray(h, dtype=np.uint64)
     I, stride = h.shape
     if ns.shape != (I,) or ms.shape != (I,):
         raise ValueError(f"ns and ms must have {I} entries")

@@ -136,7 +136,8 @@ def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
     return ps.reshape(I).cpu().numpy().astype(np.float64)
 
 
-def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 0.015), zoom: int = 16):
+def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 0.015), zoom: int = 16,
+                 start_psol=None):
     """Best pair after one zoom x zoom window scan per width, each centred on the
     previous best (one replay of a graph-captured scan per width, all
     instances). The peak narrows as p grows, hence shrinking windows; at
@@ -145,7 +146,9 @@ def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 
     I = len(ns)
     b = np.asarray(betas, dtype=np.float64).copy()
     gm = np.asarray(gammas, dtype=np.float64).copy()
-    best = evaluate_pairs(ns, ms, hists, b, gm, p)
+    # P_sol at the starting pairs (the caller's, when it has them already)
+    best = (evaluate_pairs(ns, ms, hists, b, gm, p) if start_psol is None
+            else np.asarray(start_psol, dtype=np.float64).copy())
     plan = None                      # one graph-captured scan, replayed per window
     for w in widths:
         offs = np.linspace(-w, w, zoom)

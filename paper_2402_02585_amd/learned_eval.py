@@ -113,7 +113,7 @@ def main(argv=None):
         p_learn = learned.evaluate_pairs(ns, ms, H, bl, gl, p)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        wb, wg, p_win = learned.refine_local(ns, ms, H, bl, gl, p)
+        wb, wg, p_win = learned.refine_local(ns, ms, H, bl, gl, p, start_psol=p_learn)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         t_learn += t1 - t0
