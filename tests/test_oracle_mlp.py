@@ -106,3 +106,48 @@ def test_angle_map_and_loss_gradient():
             om[i, j] -= h
             fd = (mlp.loss_and_dout(op, bt, gt)[0] - mlp.loss_and_dout(om, bt, gt)[0]) / (2 * h)
             assert dout[i, j] == pytest.approx(fd, abs=1e-8)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With the same gradient g at every step, the moments are m_t = (1 - b1^t) g
+    and v_t = (1 - b2^t) g^2, so the bias-corrected m-hat = g and v-hat = g^2 at
+    every t: each step moves every parameter by exactly lr * sign(g) (eps = 0).
+    A wrong moment recursion or a bias correction that does not use t fails."""
+    params = {"w": np.array([1.0, -2.0, 3.0, 0.25])}
+    grads = {"w": np.array([0.5, -4.0, 1e-3, -7.0])}
+    state = {}
+    lr = 0.01
+    for t in range(1, 13):
+        mlp.adam_step(params, grads, state, lr=lr, b1=0.9, b2=0.999, eps=0.0)
+        expect = np.array([1.0, -2.0, 3.0, 0.25]) - t * lr * np.sign(grads["w"])
+        np.testing.assert_allclose(params["w"], expect, rtol=0, atol=1e-13)
+    assert state["t"] == 12
+
+
+def test_adam_two_steps_hand_computed():
+    """Scalar parameter 0.5, gradients 1 then -2, lr 0.1, b1 0.9, b2 0.999, eps 0.
+    Step 1: m = 0.1, v = 0.001, m-hat = 1, v-hat = 1, so w = 0.4.
+    Step 2: m = 0.09 - 0.2 = -0.11, v = 0.000999 + 0.004 = 0.004999,
+    m-hat = -0.11 / 0.19 = -11/19, v-hat = 0.004999 / 0.001999 = 4999/1999,
+    step = 0.1 * (11/19) / sqrt(4999/1999) = 0.0366103527035846 (by hand with
+    exact fractions), so w = 0.4366103527035846."""
+    params = {"w": np.array([0.5])}
+    state = {}
+    mlp.adam_step(params, {"w": np.array([1.0])}, state, lr=0.1, b1=0.9, b2=0.999, eps=0.0)
+    assert params["w"][0] == pytest.approx(0.4, abs=1e-15)
+    mlp.adam_step(params, {"w": np.array([-2.0])}, state, lr=0.1, b1=0.9, b2=0.999, eps=0.0)
+    assert state["m_w"][0] == pytest.approx(-0.11, abs=1e-16)
+    assert state["v_w"][0] == pytest.approx(0.004999, abs=1e-17)
+    assert params["w"][0] == pytest.approx(0.4366103527035846, abs=1e-15)
+
+
+def test_loss_value_hand_computed_batch_of_two():
+    """o = [[0, 0], [ln 3, -ln 3]]: sigmoids 1/2, 1/2 and 3/4, 1/4, so
+    (beta, gamma) = (pi, pi/2) and (3 pi/2, pi/4). Targets (pi/2, pi/2) and
+    (pi, 0): the normalized errors are (1/4, 0) and (1/4, 1/4), the loss is the
+    batch mean of (1/16, 1/8) = 3/32, and dL/do = 2 r sig (1 - sig) / 2:
+    [[1/16, 0], [3/64, 3/64]]."""
+    o = np.array([[0.0, 0.0], [math.log(3.0), -math.log(3.0)]])
+    loss, dout = mlp.loss_and_dout(o, np.array([math.pi / 2, math.pi]), np.array([math.pi / 2, 0.0]))
+    assert loss == pytest.approx(3.0 / 32.0, abs=1e-15)
+    np.testing.assert_allclose(dout, [[1.0 / 16.0, 0.0], [3.0 / 64.0, 3.0 / 64.0]], rtol=0, atol=1e-15)
