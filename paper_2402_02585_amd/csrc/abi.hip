@@ -2,6 +2,7 @@
 // and dispatch to the kernel launchers. Every check runs before the first HIP
 // call, so an invalid call returns without touching the device.
 #include "internal.h"
+#include "tune_cache.h"
 
 #include <cmath>
 
@@ -433,7 +434,7 @@ static int check_scan_args(int num_inst, const int32_t *n_host, const int32_t *m
         if (p_list_host[q] < 1 || p_list_host[q] > kMaxP) return fail(GQAOA_ERANGE, "p_list[%d]=%d", q, p_list_host[q]);
         if (q && p_list_host[q] <= p_list_host[q - 1]) return fail(GQAOA_EINVAL, "p_list is not ascending");
     }
-    if (tile && (!(tile[0] == 1 || tile[0] == 2 || tile[0] == 4) || tile[1] < 1 || tile[1] > 32))
+    if (tile && !tile_valid(tile[0], tile[1]))
         return fail(GQAOA_EINVAL, "tile {%d, %d}", tile[0], tile[1]);
     const uint64_t items = (uint64_t)num_inst * ng * ((nb + 63) / 64);
     if (items >= (1ull << 31)) return fail(GQAOA_ERANGE, "too many work items (%llu)", (unsigned long long)items);

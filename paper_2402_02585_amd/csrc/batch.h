@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "tune_cache.h"
 
 namespace gqaoa {
 
@@ -36,10 +37,6 @@ struct ScanArgs {
     int nb, ng, ntiles, num_p;
     int per_inst;          // angle grids are per instance
     int p_list[kScanMaxP];
-};
-
-struct TileChoice {
-    int waves, blocks_per_cu;
 };
 
 // Host tables of a scan: occupied levels and weights of every instance,

@@ -306,9 +306,7 @@ static void tune_load_locked() {
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    char key[256];
-    int wv, bpc;
-    while (fscanf(f, "%255s %d %d", key, &wv, &bpc) == 3) g_tune[key] = TileChoice{wv, bpc};
+    tune_cache_read(f, g_tune);  // shapes outside the accepted range are dropped and retuned
     fclose(f);
 }
 
@@ -317,7 +315,7 @@ static void tune_store_locked() {
     if (!path) return;
     FILE *f = fopen(path, "w");
     if (!f) return;
-    for (auto &kv : g_tune) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.waves, kv.second.blocks_per_cu);
+    tune_cache_write(f, g_tune);
     fclose(f);
 }
 
