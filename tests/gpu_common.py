@@ -35,3 +35,19 @@ def c2_instance():
 def log(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def synthetic_hist(K: int, m: int, n: int, seed: int) -> np.ndarray:
+    """A level histogram with exactly K occupied levels out of 0..m (level 0
+    always among them) and counts summing to 2^n: a level-space input with
+    more occupied levels than random 3-SAT instances of the tested sizes reach.
+    uint64 [m + 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lev = np.concatenate([[0], rng.choice(np.arange(1, m + 1), K - 1, replace=False)])
+    w = rng.dirichlet(np.ones(K))
+    cnt = np.maximum(1, np.floor(w * 2.0 ** n)).astype(np.int64)
+    cnt[np.argmax(cnt)] += (1 << n) - int(cnt.sum())
+    h = np.zeros(m + 1, dtype=np.uint64)
+    h[lev] = cnt.astype(np.uint64)
+    assert int(h.sum()) == 1 << n and int((h > 0).sum()) == K
+    return h

@@ -60,6 +60,28 @@ def test_random_initial_state(n, m, p, seed, dt):
     assert np.abs(res[0].cpu().numpy() - ref[0]).max() < (1e-13 if dt == g.C128 else 2e-6)
 
 
+@pytest.mark.parametrize("n,dt", [(22, g.C64), (21, g.C128), (22, g.C128)])
+def test_random_initial_state_folded_grid(n, dt):
+    """The launch shape the headline uses: one tile per block, with the
+    per-round partial rows folded before the finalize (complex64 from n = 22,
+    complex128 from n = 21), from a random state that no level symmetry masks;
+    the whole final state and every round's readouts against the oracle."""
+    torch = need_gpu()
+    m, p, seed = inst.m_from_density(n, 4.2), 6, 300 + n
+    log(f"evolve random psi0 folded grid n={n} m={m} p={p} dt={dt}")
+    lits = rand_lits(n, m, seed)
+    beta, gamma = inst.uniform_angles(seed, p)
+    psi0 = rand_state(n, seed)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    tdt = torch.complex128 if dt == g.C128 else torch.complex64
+    psi = torch.tensor(psi0, dtype=tdt, device="cuda")
+    res = g.gqaoa_evolve(n, m, cost, beta, gamma, dtype=dt, psi=psi, init_uniform=False)
+    psi0_used = psi0 if dt == g.C128 else psi0.astype(np.complex64).astype(np.complex128)
+    ref = evolve_sv(n, cost_table(n, lits), beta, gamma, psi0=psi0_used)
+    _check(res, ref, dt, m)
+    assert np.abs(res[0].cpu().numpy() - ref[0]).max() < (1e-13 if dt == g.C128 else 2e-6)
+
+
 @pytest.mark.parametrize("dt", [g.C128, g.C64])
 def test_max_sat_target_and_solution_prob(dt):
     need_gpu()

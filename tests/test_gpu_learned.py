@@ -56,7 +56,7 @@ def test_labels_match_oracle(trained):
         h = lab["hists"][i, :lab["ms"][i] + 1]
         for q, p in enumerate(P_LIST):
             ref = psol_single_pair_hist(h, lab["beta"][i, q], lab["gamma"][i, q], p)
-            assert abs(lab["psol"][i, q] - ref) < 1e-4
+            assert abs(lab["psol"][i, q] - ref) < 1e-5
 
 
 def test_learned_beats_cluster_median_and_tracks_optimizer(trained):

@@ -1,9 +1,10 @@
 """GPU parity: batched single-angle-pair scan (Eq. (5)) against the oracle.
 
-The scan computes in float32. Tolerance 1e-4 absolute on P_sol and 1e-4 * m
-on E after up to 64 rounds: each round's phase multiply and mixer add round
-to float32 (relative 6e-8 per operation), and over p rounds with K levels
-these accumulate to well under 1e-4 in practice.
+The scan computes in float32. Tolerance 1e-5 absolute on P_sol and 1e-5 * m
+on E after up to 64 rounds (the single-precision bar): each round's phase
+multiply and mixer add round to float32 (relative 6e-8 per operation); over p
+rounds with K levels the amplitudes' relative error grows roughly like
+p * 6e-8 * sqrt(K) (about 4e-6 at p = 64, K = 128), and P_sol <= 1.
 """
 import numpy as np
 import pytest
@@ -42,8 +43,8 @@ def test_scan_matches_oracle(nb, ng, plist, tile):
             bi, gi = int(rng.integers(0, nb)), int(rng.integers(0, ng))
             _, rp, re, _ = evolve_hist(H[i, :it.m + 1], np.full(plist[-1], betas[bi]), np.full(plist[-1], gammas[gi]))
             for q, p in enumerate(plist):
-                assert abs(psol[i, q, gi, bi] - rp[p]) < 1e-4, (i, q, gi, bi, psol[i, q, gi, bi], rp[p])
-                assert abs(energy[i, q, gi, bi] - re[p]) < 1e-4 * it.m
+                assert abs(psol[i, q, gi, bi] - rp[p]) < 1e-5, (i, q, gi, bi, psol[i, q, gi, bi], rp[p])
+                assert abs(energy[i, q, gi, bi] - re[p]) < 1e-5 * it.m
 
 
 def test_scan_full_grid_small_instance_and_target():

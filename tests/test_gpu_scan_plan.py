@@ -7,7 +7,7 @@ bit for bit. Replays are interleaved with other eager work and
 synchronizations, with new grids, with the current grid (no upload) and
 with the first grid again, and the outputs are cleared before each replay so
 a stale value cannot pass. Sampled cells are also checked against the oracle
-(level space, float64) within the scan's float32 tolerance of 1e-4, and the
+(level space, float64) within the scan's float32 tolerance of 1e-5, and the
 statevector items against the scan's cells within 1e-5 (two float32 paths
 of the same exact state).
 """
@@ -92,7 +92,7 @@ def test_plan_replays_equal_eager(per_instance):
                 bb = b[i, bi] if per_instance else b[bi]
                 gg = gm[i, gi] if per_instance else gm[gi]
                 _, rp, _, _ = evolve_hist(H[i, :ms[i] + 1], np.full(P_LIST[-1], bb), np.full(P_LIST[-1], gg))
-                assert np.abs(ps[i, :, gi, bi] - rp[P_LIST]).max() < 1e-4
+                assert np.abs(ps[i, :, gi, bi] - rp[P_LIST]).max() < 1e-5
     finally:
         plan.close()
 
@@ -155,6 +155,6 @@ def test_plan_maxsat_targets():
         for i in range(0, len(its), 5):
             _, rp, _, _ = evolve_hist(H[i, :ms[i] + 1], np.full(P_LIST[-1], b[3]), np.full(P_LIST[-1], gm[2]),
                                       target=tg[i])
-            assert np.abs(ps[i, :, 2, 3] - rp[P_LIST]).max() < 1e-4
+            assert np.abs(ps[i, :, 2, 3] - rp[P_LIST]).max() < 1e-5
     finally:
         plan.close()
