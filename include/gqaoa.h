@@ -70,6 +70,19 @@ int gqaoa_abi_version(void);
 int gqaoa_cost_table(int n, int m, const int32_t *lits_host, uint8_t *cost_dev,
                      uint64_t *hist_dev, void *stream);
 
+/* Allocation-free form of gqaoa_cost_table, for callers that cannot allocate
+ * device memory (serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, errors and results (cost table and histogram bit-identical), with
+ * the call's scratch (clause records and per-block histogram rows) in a static
+ * device array of 12 KiB + 2 MiB instead of stream-ordered allocations. Every
+ * valid (n, m) fits in it. Each GPU the library runs on holds its own copy
+ * until the process ends. All calls on one GPU share that copy: calls that
+ * overlap on one GPU (different streams without ordering, several host
+ * threads) race; order them. Like gqaoa_cost_table it synchronizes the stream
+ * once, after uploading the clause records, so it cannot be graph-captured. */
+int gqaoa_cost_table_noalloc(int n, int m, const int32_t *lits_host, uint8_t *cost_dev,
+                             uint64_t *hist_dev, void *stream);
+
 /* Histograms only, for many instances in one launch (no cost table kept).
  * Instance i has n_host[i] variables, m_host[i] clauses whose literals start
  * at lits_host[3*off_i], off_i = sum of m_host[<i]. hists_dev is

@@ -14,6 +14,7 @@ namespace gqaoa {
 
 // launchers (cost_table.hip, sv.hip, hist.hip, mlp.hip)
 int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist, hipStream_t st);
+int launch_cost_table_noalloc(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist, hipStream_t st);
 uint64_t batched_cost_offset(int i, const int32_t *n_host);
 int launch_hist_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const int32_t *lits,
                         uint64_t *hists, int hist_stride, uint8_t *costs, hipStream_t st);
@@ -229,6 +230,17 @@ int gqaoa_cost_table(int n, int m, const int32_t *lits_host, uint8_t *cost_dev, 
     int s = check_clauses(n, m, lits_host, 0);
     if (s) return s;
     return launch_cost_table(n, m, lits_host, cost_dev, hist_dev, (hipStream_t)stream);
+}
+
+int gqaoa_cost_table_noalloc(int n, int m, const int32_t *lits_host, uint8_t *cost_dev, uint64_t *hist_dev,
+                             void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (m < 1 || m > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "m=%d outside [1, 255]", m);
+    if (!lits_host || !cost_dev) return fail(GQAOA_EINVAL, "NULL lits_host or cost_dev");
+    int s = check_clauses(n, m, lits_host, 0);
+    if (s) return s;
+    return launch_cost_table_noalloc(n, m, lits_host, cost_dev, hist_dev, (hipStream_t)stream);
 }
 
 static int check_batched_instances(int num_inst, const int32_t *n_host, const int32_t *m_host,

@@ -178,20 +178,31 @@ namespace gqaoa {
 
 // Pack validated clauses (lit = 2*var + neg, 3 distinct vars) into the records
 // above. Clauses with all three variables at bits >= 11 go to `uni`; the rest
-// go to `vec`, padded with empty records to a multiple of kGroup.
-inline void pack_clauses(int m, const int32_t *lits, std::vector<ClauseRec> &vec,
-                         std::vector<UniformRec> &uni) {
-    vec.clear();
-    uni.clear();
+// go to `vec`, padded with empty records to a multiple of kGroup. Fixed-capacity
+// form: for m clauses vec needs room for m rounded up to kGroup records, uni for m.
+inline void pack_clauses(int m, const int32_t *lits, ClauseRec *vec, int *nvec, UniformRec *uni, int *nuni) {
+    int nv = 0, nu = 0;
     for (int i = 0; i < m; ++i) {
         bool uniform = false;
         const ClauseRec r = make_record(lits[3 * i], lits[3 * i + 1], lits[3 * i + 2], &uniform);
         if (uniform)
-            uni.push_back(UniformRec{r.hivar, r.hineg});
+            uni[nu++] = UniformRec{r.hivar, r.hineg};
         else
-            vec.push_back(r);
+            vec[nv++] = r;
     }
-    while (vec.size() % kGroup) vec.push_back(ClauseRec{0u, 0u, 0ull, 0ull, 0ull});
+    while (nv % kGroup) vec[nv++] = ClauseRec{0u, 0u, 0ull, 0ull, 0ull};
+    *nvec = nv;
+    *nuni = nu;
+}
+
+inline void pack_clauses(int m, const int32_t *lits, std::vector<ClauseRec> &vec,
+                         std::vector<UniformRec> &uni) {
+    vec.resize((size_t)(m + kGroup - 1) / kGroup * kGroup);
+    uni.resize((size_t)m);
+    int nv = 0, nu = 0;
+    pack_clauses(m, lits, vec.data(), &nv, uni.data(), &nu);
+    vec.resize((size_t)nv);
+    uni.resize((size_t)nu);
 }
 
 }  // namespace gqaoa

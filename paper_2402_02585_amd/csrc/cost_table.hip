@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 namespace gqaoa {
@@ -352,6 +354,36 @@ static void level_window(int m, int *a0, int *nb) {
     *nb = std::min(2, hi / 32 - *a0 + 1);
 }
 
+// Cost kernel and histogram reduce on records already on the device.
+static int enqueue_cost_kernels(int n, int m, int nblocks, int nvec, int nuni, const ClauseRec *d_vec,
+                                const UniformRec *d_uni, uint32_t *d_bh, uint8_t *cost, uint64_t *hist,
+                                hipStream_t stream) {
+    const int hist_len = m + 1;
+    int a0 = 0, nb = 1;
+    level_window(m, &a0, &nb);
+    ProfScope ps("cost_table", stream);
+    if (nb == 1)
+        hipLaunchKernelGGL(cost_table_kernel<1>, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes(nvec), stream,
+                           d_vec, nvec, d_uni, nuni, n, cost, d_bh, hist_len, a0);
+    else
+        hipLaunchKernelGGL(cost_table_kernel<2>, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes(nvec), stream,
+                           d_vec, nvec, d_uni, nuni, n, cost, d_bh, hist_len, a0);
+    ps.end();
+    GQ_LAUNCH_CHECK();
+    if (hist) {
+        hipLaunchKernelGGL(hist_reduce_kernel, dim3(hist_len), dim3(256), 0, stream, d_bh, nblocks, hist_len,
+                           reinterpret_cast<unsigned long long *>(hist));
+        GQ_LAUNCH_CHECK();
+    }
+    return GQAOA_OK;
+}
+
+static int cost_grid(int n, const DeviceInfo &dev, int cap) {
+    const uint64_t nwords = n >= kLowBits ? (1ull << (n - kLowBits)) : 1;
+    const uint64_t want = (nwords + kCostThreads - 1) / kCostThreads;
+    return (int)std::min<uint64_t>(want, (uint64_t)std::min(dev.num_cus * 8, cap));
+}
+
 int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist,
                       hipStream_t stream) {
     DeviceInfo dev;
@@ -360,9 +392,7 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     std::vector<ClauseRec> vec;
     std::vector<UniformRec> uni;
     pack_clauses(m, lits, vec, uni);
-    const uint64_t nwords = n >= kLowBits ? (1ull << (n - kLowBits)) : 1;
-    const uint64_t want = (nwords + kCostThreads - 1) / kCostThreads;
-    const int nblocks = (int)std::min<uint64_t>(want, (uint64_t)dev.num_cus * 8);
+    const int nblocks = cost_grid(n, dev, 1 << 30);
     const int hist_len = m + 1;
     const size_t rec_bytes = sizeof(ClauseRec) * vec.size() + sizeof(UniformRec) * (uni.size() + 1);
     const size_t bh_bytes = sizeof(uint32_t) * (size_t)nblocks * hist_len;
@@ -378,23 +408,68 @@ int launch_cost_table(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t
     if (!uni.empty()) memcpy(staging.data() + sizeof(ClauseRec) * vec.size(), uni.data(), sizeof(UniformRec) * uni.size());
     GQ_HIP(hipMemcpyAsync(scratch, staging.data(), rec_bytes, hipMemcpyHostToDevice, stream));
     GQ_HIP(hipStreamSynchronize(stream));  // staging is host pageable memory owned here
-    int a0 = 0, nb = 1;
-    level_window(m, &a0, &nb);
-    ProfScope ps("cost_table", stream);
-    if (nb == 1)
-        hipLaunchKernelGGL(cost_table_kernel<1>, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes((int)vec.size()),
-                           stream, d_vec, (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len, a0);
-    else
-        hipLaunchKernelGGL(cost_table_kernel<2>, dim3(nblocks), dim3(kCostThreads), cost_lds_bytes((int)vec.size()),
-                           stream, d_vec, (int)vec.size(), d_uni, (int)uni.size(), n, cost, d_bh, hist_len, a0);
-    ps.end();
-    GQ_LAUNCH_CHECK();
-    if (hist) {
-        hipLaunchKernelGGL(hist_reduce_kernel, dim3(hist_len), dim3(256), 0, stream, d_bh, nblocks, hist_len,
-                           reinterpret_cast<unsigned long long *>(hist));
-        GQ_LAUNCH_CHECK();
+    return enqueue_cost_kernels(n, m, nblocks, (int)vec.size(), (int)uni.size(), d_vec, d_uni, d_bh, cost, hist,
+                                stream);
+}
+
+// ---- allocation-free form: scratch in a static device array --------------------------------
+// The clause records and the per-block histogram rows of gqaoa_cost_table,
+// for callers that cannot allocate device memory. The grid is capped at
+// kStaticBlocks blocks (the kernel's loop over tiles covers any n), so every
+// valid (n, m) fits: 12 KiB of records and at most 2 MiB of rows. Each GPU
+// holds its own copy of the array until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr int kStaticBlocks = 2048;
+constexpr size_t kStaticRecBytes =
+    (sizeof(ClauseRec) * kMaxVec + sizeof(UniformRec) * kMaxVec + 255) & ~size_t(255);
+constexpr size_t kStaticRowBytes = sizeof(uint32_t) * (size_t)kStaticBlocks * kMaxVec;
+constexpr size_t kStaticScratchBytes = kStaticRecBytes + kStaticRowBytes;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_addr;  // device -> device address of `scratch`
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current).
+static int static_scratch(unsigned char **out) {
+    int dev = -1;
+    GQ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *ptr = nullptr;
+        GQ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        it = g_scratch_addr.emplace(dev, reinterpret_cast<unsigned char *>(ptr)).first;
     }
+    *out = it->second;
     return GQAOA_OK;
+}
+
+int launch_cost_table_noalloc(int n, int m, const int32_t *lits, uint8_t *cost, uint64_t *hist,
+                              hipStream_t stream) {
+    DeviceInfo dev;
+    int st = device_info(&dev);
+    if (st) return st;
+    unsigned char *base = nullptr;
+    if ((st = static_scratch(&base))) return st;
+    ClauseRec vec[kMaxVec];
+    UniformRec uni[kMaxVec];
+    int nvec = 0, nuni = 0;
+    pack_clauses(m, lits, vec, &nvec, uni, &nuni);
+    const int nblocks = cost_grid(n, dev, kStaticBlocks);
+    const size_t vec_bytes = sizeof(ClauseRec) * (size_t)nvec, uni_bytes = sizeof(UniformRec) * (size_t)nuni;
+    const size_t row_bytes = sizeof(uint32_t) * (size_t)nblocks * (size_t)(m + 1);
+    if (vec_bytes + uni_bytes > kStaticRecBytes || row_bytes > kStaticRowBytes)
+        return fail(GQAOA_ERANGE, "cost table n=%d m=%d needs %zu + %zu scratch bytes, more than the static %zu + %zu",
+                    n, m, vec_bytes + uni_bytes, row_bytes, kStaticRecBytes, kStaticRowBytes);
+    ClauseRec *d_vec = reinterpret_cast<ClauseRec *>(base);
+    UniformRec *d_uni = reinterpret_cast<UniformRec *>(base + vec_bytes);
+    uint32_t *d_bh = reinterpret_cast<uint32_t *>(base + kStaticRecBytes);
+    if (nvec) GQ_HIP(hipMemcpyAsync(d_vec, vec, vec_bytes, hipMemcpyHostToDevice, stream));
+    if (nuni) GQ_HIP(hipMemcpyAsync(d_uni, uni, uni_bytes, hipMemcpyHostToDevice, stream));
+    GQ_HIP(hipStreamSynchronize(stream));  // the records are host stack memory of this call
+    // every block writes its whole row of hist_len counts, so no row needs clearing
+    return enqueue_cost_kernels(n, m, nblocks, nvec, nuni, d_vec, d_uni, d_bh, cost, hist, stream);
 }
 
 // Byte offset of each instance's cost table in the concatenated output: the

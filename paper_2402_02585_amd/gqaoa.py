@@ -31,6 +31,7 @@ _SIGS = {
     "gqaoa_last_error": ([], _c.c_char_p),
     "gqaoa_abi_version": ([], _i32),
     "gqaoa_cost_table": ([_i32, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_cost_table_noalloc": ([_i32, _i32, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_hist_batched": ([_i32, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
     "gqaoa_cost_batched_offset": ([_i32, _vp], _c.c_uint64),
     "gqaoa_cost_batched": ([_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp], _i32),
@@ -142,6 +143,24 @@ def gqaoa_cost_table(n: int, lits, with_hist: bool = True, cost=None, stream=Non
         cost = torch.empty(1 << n, dtype=torch.uint8, device="cuda")
     hist = torch.empty(m + 1, dtype=torch.int64, device="cuda") if with_hist else None
     _check(lib.gqaoa_cost_table(n, m, _np_ptr(flat), _ptr(cost), _ptr(hist), _stream(torch, stream)))
+    return cost, hist
+
+
+def gqaoa_cost_table_noalloc(n: int, lits, hist=None, cost=None, stream=None):
+    """gqaoa_cost_table with the library's static scratch (no device
+    allocation inside the call). cost: uint8 [2^n] device tensor, hist: int64
+    [m+1] device tensor or None; allocated here when not given. Returns (cost, hist)."""
+    torch = _torch()
+    lib = load_library()
+    flat = _lits(lits)
+    m = flat.size // 3
+    if cost is None:
+        cost = torch.empty(1 << n, dtype=torch.uint8, device="cuda")
+    if cost.dtype != torch.uint8 or cost.numel() < (1 << n) or not cost.is_cuda:
+        raise ValueError(f"cost must be a device uint8 tensor of 2^{n} entries")
+    if hist is not None and (hist.dtype != torch.int64 or hist.numel() < m + 1 or not hist.is_cuda):
+        raise ValueError(f"hist must be a device int64 tensor of {m + 1} entries")
+    _check(lib.gqaoa_cost_table_noalloc(n, m, _np_ptr(flat), _ptr(cost), _ptr(hist), _stream(torch, stream)))
     return cost, hist
 
 

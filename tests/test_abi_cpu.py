@@ -272,3 +272,17 @@ def test_checkpoint_interval_choice():
     assert ws(c) == smallest and all(ws(k) > smallest for k in range(c + 1, p))
     with pytest.raises(g.GQAOAError):
         g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=smallest - 1)
+
+
+def test_cost_table_noalloc_rejects_bad_arguments():
+    """The allocation-free cost table validates like gqaoa_cost_table, before
+    any device call."""
+    lib = g.load_library()
+    dummy = ctypes.c_void_p(16)
+    ok = _lits([[0, 2, 4]])
+    assert lib.gqaoa_cost_table_noalloc(2, 1, g._np_ptr(ok), dummy, None, None) == -2    # n < 3
+    assert lib.gqaoa_cost_table_noalloc(35, 1, g._np_ptr(ok), dummy, None, None) == -2   # n > 34
+    assert lib.gqaoa_cost_table_noalloc(5, 256, g._np_ptr(ok), dummy, None, None) == -2  # m > 255
+    assert lib.gqaoa_cost_table_noalloc(5, 1, None, dummy, None, None) == -1
+    assert lib.gqaoa_cost_table_noalloc(5, 1, g._np_ptr(ok), None, None, None) == -1
+    assert lib.gqaoa_cost_table_noalloc(5, 1, g._np_ptr(_lits([[0, 1, 4]])), dummy, None, None) == -1  # var 0 twice
