@@ -209,6 +209,32 @@ int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const doubl
                       const double *gamma_host, int target_level, double *psol_host,
                       double *energy_host, double *norm_host, void *stream);
 
+/* Level-space adjoint gradient for many instances (float64): for instance i,
+ * P_i = w_t |b_t|^2 after p_i rounds of Eq. (3) from |s> in the level space
+ * above (t = target_host[i], NULL = level 0) and dP_i/dbeta_k, dP_i/dgamma_k for
+ * every round k < p_i: the reverse sweep of gqaoa_grad with <s|x> =
+ * sum_l w_l x_l and the diagonal C replaced by the level index. These are the
+ * gradients of full G-QAOA (all 2p angles, App. C "Optimization") at O(p K)
+ * work per instance, K = occupied levels, instead of O(p 2^n). The forward
+ * states are recomputed by running each (unitary) round backwards, so the
+ * device state is O(K) per instance for any p.
+ * Instance i: hists_host + i*hist_stride holds N_k for k <= m_host[i] (host
+ * memory, as gqaoa_scan_batched), n_host[i] variables (sum N_k = 2^n), p_i =
+ * p_host[i] in [1, p_max] (NULL: p_max for all), angles beta_host[i*p_max + k]
+ * and gamma_host[i*p_max + k] for k < p_i.
+ * Outputs (host, each may be NULL): psol_host[i], dbeta_host[i*p_max + k],
+ * dgamma_host[i*p_max + k]; entries k >= p_i are 0. Synchronizes the stream.
+ * ws: gqaoa_hist_grad_workspace_bytes(num_inst, hist_stride, p_max) bytes (0
+ * for invalid sizes). Errors: EINVAL (NULL pointers), ERANGE (num_inst in
+ * [1, 2^20], hist_stride in [2, 4096], n_i in [3, 62], m_i in [1, 255] with
+ * m_i < hist_stride, target in [0, m_i], p_max in [1, 100000], p_i), EWORKSPACE. */
+size_t gqaoa_hist_grad_workspace_bytes(int num_inst, int hist_stride, int p_max);
+int gqaoa_hist_grad_batched(int num_inst, const int32_t *n_host, const int32_t *m_host,
+                            const uint64_t *hists_host, int hist_stride, const int32_t *target_host,
+                            int p_max, const int32_t *p_host, const double *beta_host,
+                            const double *gamma_host, double *psol_host, double *dbeta_host,
+                            double *dgamma_host, void *ws_dev, size_t ws_bytes, void *stream);
+
 /* ---- batched single-angle-pair scan, Eq. (5) -------------------------------
  * For every instance i, beta_b (b < nb) and gamma_g (g < ng), runs the
  * single-angle-pair protocol in the level space for p_list[num_p-1] rounds

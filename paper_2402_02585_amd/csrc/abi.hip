@@ -29,6 +29,11 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
              double *dgamma, void *ws, hipStream_t st);
 int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *beta, const double *gamma,
                     int target, double *psol, double *energy, double *norm, hipStream_t st);
+size_t hist_grad_workspace_bytes(int num_inst, int hist_stride, int pstride);
+int run_hist_grad(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
+                  int hist_stride, const int32_t *target_host, int pstride, const int32_t *p_host,
+                  const double *beta, const double *gamma, double *psol, double *dbeta, double *dgamma,
+                  void *ws, hipStream_t st);
 size_t scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p, int per_inst);
 int scan_max_levels();
 int run_scan(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists, int hist_stride,
@@ -425,6 +430,40 @@ int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const doubl
     if (p > 0 && (!beta_host || !gamma_host)) return fail(GQAOA_EINVAL, "NULL angles");
     return run_hist_evolve(n, m, hist_dev, p, beta_host, gamma_host, target_level, psol_host, energy_host, norm_host,
                            (hipStream_t)stream);
+}
+
+size_t gqaoa_hist_grad_workspace_bytes(int num_inst, int hist_stride, int p_max) {
+    if (num_inst < 1 || num_inst > (1 << 20) || hist_stride < 2 || hist_stride > 4096 || p_max < 1 || p_max > kMaxP)
+        return 0;
+    return hist_grad_workspace_bytes(num_inst, hist_stride, p_max);
+}
+
+int gqaoa_hist_grad_batched(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists_host,
+                            int hist_stride, const int32_t *target_host, int p_max, const int32_t *p_host,
+                            const double *beta_host, const double *gamma_host, double *psol_host,
+                            double *dbeta_host, double *dgamma_host, void *ws_dev, size_t ws_bytes, void *stream) {
+    clear_error();
+    if (num_inst < 1 || num_inst > (1 << 20)) return fail(GQAOA_ERANGE, "num_inst=%d outside [1, 2^20]", num_inst);
+    if (hist_stride < 2 || hist_stride > 4096) return fail(GQAOA_ERANGE, "hist_stride=%d", hist_stride);
+    if (p_max < 1 || p_max > kMaxP) return fail(GQAOA_ERANGE, "p_max=%d outside [1, %d]", p_max, kMaxP);
+    if (!n_host || !m_host || !hists_host || !beta_host || !gamma_host || !ws_dev)
+        return fail(GQAOA_EINVAL, "NULL argument");
+    for (int i = 0; i < num_inst; ++i) {
+        if (n_host[i] < GQAOA_MIN_N || n_host[i] > 62) return fail(GQAOA_ERANGE, "instance %d: n=%d", i, n_host[i]);
+        if (m_host[i] < 1 || m_host[i] > GQAOA_MAX_M || m_host[i] + 1 > hist_stride)
+            return fail(GQAOA_ERANGE, "instance %d: m=%d", i, m_host[i]);
+        const int t = target_host ? target_host[i] : 0;
+        if (t < 0 || t > m_host[i]) return fail(GQAOA_ERANGE, "instance %d: target_level=%d", i, t);
+        if (p_host && (p_host[i] < 1 || p_host[i] > p_max))
+            return fail(GQAOA_ERANGE, "instance %d: p=%d outside [1, %d]", i, p_host[i], p_max);
+    }
+    const size_t need = hist_grad_workspace_bytes(num_inst, hist_stride, p_max);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    return run_hist_grad(num_inst, n_host, m_host, hists_host, hist_stride, target_host, p_max, p_host, beta_host,
+                         gamma_host, psol_host, dbeta_host, dgamma_host, ws_dev, (hipStream_t)stream);
 }
 
 size_t gqaoa_scan_workspace_bytes(int num_inst, int hist_stride, int nb, int ng, int num_p, int per_instance_grid) {

@@ -48,6 +48,9 @@ _SIGS = {
     "gqaoa_grad": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_grad_batched": ([_i32, _i32, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
     "gqaoa_hist_evolve": ([_i32, _i32, _vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_hist_grad_workspace_bytes": ([_i32, _i32, _i32], _sz),
+    "gqaoa_hist_grad_batched": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp],
+                                _i32),
     "gqaoa_scan_workspace_bytes": ([_i32, _i32, _i32, _i32, _i32, _i32], _sz),
     "gqaoa_scan_batched": ([_i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _i32, _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                             _sz, _vp], _i32),
@@ -426,6 +429,36 @@ def gqaoa_hist_evolve(n: int, m: int, hist, betas, gammas, target_level: int = 0
     _check(lib.gqaoa_hist_evolve(n, m, _ptr(hist), p, _np_ptr(b), _np_ptr(g), target_level, _np_ptr(psol),
                                  _np_ptr(energy), _np_ptr(norm), _stream(torch, stream)))
     return psol, energy, norm
+
+
+def gqaoa_hist_grad_batched(ns, ms, hists, betas, gammas, targets=None, p=None, workspace=None, stream=None):
+    """Level-space adjoint gradient of P_sol for many instances (float64).
+    hists: host int64/uint64 [I, stride]; betas, gammas: [I, p_max] (instance
+    i uses its first p[i] angles; p None: all p_max). Returns numpy
+    (P[I], dP/dbeta[I, p_max], dP/dgamma[I, p_max]); entries beyond p[i] are 0."""
+    torch = _torch()
+    lib = load_library()
+    ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(ms, dtype=np.int32))
+    h = np.asarray(hists)
+    if h.dtype == np.int64:
+        h = h.view(np.uint64)
+    h = np.ascontiguousarray(h, dtype=np.uint64)
+    I, stride = h.shape
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64).reshape(I, -1))
+    g = np.ascontiguousarray(np.asarray(gammas, dtype=np.float64).reshape(I, -1))
+    if b.shape != g.shape:
+        raise ValueError(f"betas {b.shape} and gammas {g.shape} differ")
+    pmax = b.shape[1]
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int32).reshape(I))
+    pp = None if p is None else np.ascontiguousarray(np.asarray(p, dtype=np.int32).reshape(I))
+    need = lib.gqaoa_hist_grad_workspace_bytes(I, stride, pmax)
+    ws = workspace if workspace is not None else _workspace(torch, need)
+    P, db, dg = np.empty(I), np.empty((I, pmax)), np.empty((I, pmax))
+    _check(lib.gqaoa_hist_grad_batched(I, _np_ptr(ns), _np_ptr(ms), _np_ptr(h), stride, _np_ptr(tg), pmax,
+                                       _np_ptr(pp), _np_ptr(b), _np_ptr(g), _np_ptr(P), _np_ptr(db), _np_ptr(dg),
+                                       _ptr(ws), ws.numel(), _stream(torch, stream)))
+    return P, db, dg
 
 
 def gqaoa_scan_workspace_bytes(num_inst: int, hist_stride: int, nb: int, ng: int, num_p: int,

@@ -12,8 +12,10 @@ seed. Here every evaluation runs on the GPU:
   through one ``gqaoa_scan_batched`` call, then two rounds of per-instance
   zoomed grids around each best point (per p, one graph-captured scan plan
   replayed at each zoom level).
-* ``full_gqaoa``: all 2p angles by L-BFGS-B with the adjoint gradient
-  (``gqaoa_grad``).
+* ``full_gqaoa_batched`` / ``full_gqaoa``: all 2p angles by L-BFGS-B with the
+  level-space adjoint gradient (``gqaoa_hist_grad_batched``), many instances
+  in lockstep; ``full_gqaoa_statevector`` does the same with the statevector
+  adjoint (``gqaoa_grad``).
 
 Objective: ``"psol"`` maximizes P_sol (the headline quantity of Sec. III);
 ``"energy"`` minimizes Eq. (4), the paper's stated cost function.
@@ -140,10 +142,134 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
     return np.mod(beta, 2 * math.pi), gamma, out_p, out_e
 
 
-def full_gqaoa(n: int, m: int, cost, p: int, beta0: float, gamma0: float, target: int = 0, dtype=g.C128,
-               ckpt_every: int | None = None):
-    """All 2p angles by L-BFGS-B (maximizing P_sol) with the adjoint gradient,
-    from the single-pair seed. Returns (betas, gammas, psol)."""
+def lockstep_lbfgsb(evaluate, x0s, ftol: float = 1e-6, max_workers: int = 512):
+    """scipy L-BFGS-B from every start point of ``x0s``, run in lockstep.
+
+    Each optimization runs in its own host thread and asks for its objective
+    through ``evaluate(idx, xs) -> (F, G)``, which the calling thread serves
+    for all waiting optimizations at once (idx: their positions in x0s, xs
+    their points; F[k] the value and G[k] the gradient at xs[k]). Every
+    optimization takes the same steps as a scipy call of its own, as long as
+    evaluate's result for one point does not depend on the others in the
+    batch. At most ``max_workers`` optimizations run at a time. Returns the
+    scipy results in the order of x0s."""
+    import threading
+
+    x0s = [np.asarray(x, dtype=np.float64) for x in x0s]
+    results = [None] * len(x0s)
+    for c0 in range(0, len(x0s), max_workers):
+        idx = list(range(c0, min(len(x0s), c0 + max_workers)))
+        W = len(idx)
+        cv = threading.Condition()
+        req = [None] * W            # point a worker waits on
+        ans = [None] * W
+        ready = [threading.Event() for _ in range(W)]
+        state = {"posted": 0, "done": 0, "error": None}
+
+        def worker(w):
+            def fun(x):
+                with cv:
+                    req[w] = np.array(x, dtype=np.float64)
+                    state["posted"] += 1
+                    cv.notify()
+                ready[w].wait()
+                ready[w].clear()
+                if state["error"] is not None:
+                    raise RuntimeError("batched evaluation failed")
+                return ans[w]
+            try:
+                results[idx[w]] = minimize(fun, x0s[idx[w]], jac=True, method="L-BFGS-B", options={"ftol": ftol})
+            except Exception:
+                pass
+            finally:
+                with cv:
+                    state["done"] += 1
+                    cv.notify()
+
+        threads = [threading.Thread(target=worker, args=(w,), daemon=True) for w in range(W)]
+        for t in threads:
+            t.start()
+        while True:
+            with cv:
+                cv.wait_for(lambda: state["posted"] + state["done"] >= W)
+                waiting = [w for w in range(W) if req[w] is not None]
+                if not waiting:
+                    break
+                xs = [req[w] for w in waiting]
+                for w in waiting:
+                    req[w] = None
+                state["posted"] -= len(waiting)
+            try:
+                F, G = evaluate([idx[w] for w in waiting], xs)
+            except Exception as e:
+                state["error"] = e
+                for w in waiting:
+                    ready[w].set()
+                for t in threads:
+                    t.join()
+                raise
+            for k, w in enumerate(waiting):
+                ans[w] = (float(F[k]), np.asarray(G[k], dtype=np.float64))
+                ready[w].set()
+        for t in threads:
+            t.join()
+    return results
+
+
+def full_gqaoa_batched(ns, ms, hists, p, beta0, gamma0, targets=None):
+    """Full G-QAOA (App. C, "Optimization"): all 2 p_i angles of every instance
+    by L-BFGS-B (maximizing P_sol, ftol 1e-6) from its single pair (beta0_i,
+    gamma0_i) broadcast to every round, with the level-space adjoint gradient
+    (``gqaoa_hist_grad_batched``); the instances' optimizations run in
+    lockstep, one batched gradient call per step. p: one round count or one
+    per instance. Returns (betas [I, p_max], gammas [I, p_max], psol [I]),
+    entries past p_i zero."""
+    hists = np.asarray(hists)
+    ns = np.asarray(ns, dtype=np.int32)
+    ms = np.asarray(ms, dtype=np.int32)
+    I = hists.shape[0]
+    p = np.broadcast_to(np.asarray(p, dtype=np.int32), (I,)).copy()
+    tg = np.zeros(I, dtype=np.int32) if targets is None else np.asarray(targets, dtype=np.int32)
+    beta0 = np.broadcast_to(np.asarray(beta0, dtype=np.float64), (I,))
+    gamma0 = np.broadcast_to(np.asarray(gamma0, dtype=np.float64), (I,))
+    pmax = int(p.max())
+    x0s = [np.concatenate([np.full(p[i], beta0[i]), np.full(p[i], gamma0[i])]) for i in range(I)]
+
+    def evaluate(idx, xs):
+        idx = np.asarray(idx)
+        B = np.zeros((idx.size, pmax))
+        G = np.zeros((idx.size, pmax))
+        for k, i in enumerate(idx):
+            B[k, :p[i]] = xs[k][:p[i]]
+            G[k, :p[i]] = xs[k][p[i]:]
+        P, db, dg = g.gqaoa_hist_grad_batched(ns[idx], ms[idx], hists[idx], B, G, targets=tg[idx], p=p[idx])
+        grads = [-np.concatenate([db[k, :p[i]], dg[k, :p[i]]]) for k, i in enumerate(idx)]
+        return -P, grads
+
+    res = lockstep_lbfgsb(evaluate, x0s)
+    betas = np.zeros((I, pmax))
+    gammas = np.zeros((I, pmax))
+    psol = np.zeros(I)
+    for i, r in enumerate(res):
+        if r is None:
+            raise RuntimeError(f"the optimization of instance {i} failed")
+        betas[i, :p[i]] = r.x[:p[i]]
+        gammas[i, :p[i]] = r.x[p[i]:]
+        psol[i] = -r.fun
+    return betas, gammas, psol
+
+
+def full_gqaoa(n: int, m: int, hist, p: int, beta0: float, gamma0: float, target: int = 0):
+    """``full_gqaoa_batched`` for one instance: (betas[p], gammas[p], psol)."""
+    b, gm, P = full_gqaoa_batched([n], [m], np.asarray(hist).reshape(1, -1), [p], [beta0], [gamma0], [target])
+    return b[0], gm[0], float(P[0])
+
+
+def full_gqaoa_statevector(n: int, m: int, cost, p: int, beta0: float, gamma0: float, target: int = 0,
+                           dtype=g.C128, ckpt_every: int | None = None):
+    """``full_gqaoa`` with the statevector adjoint (``gqaoa_grad``, O(2^n p) per
+    gradient) instead of the level space; the same optimum from |s>, kept as
+    its amplitude-level check. Returns (betas, gammas, psol)."""
     x0 = np.concatenate([np.full(p, beta0), np.full(p, gamma0)])
 
     def f(x):

@@ -12,10 +12,10 @@ Single angle pair: the least p for which some (beta, gamma) reaches S is the
 minimum over a grid of the first round at which each pair crosses S
 (``gqaoa_scan_crossing``, one launch for all instances and pairs), refined
 by windows of finer pairs around the best ones (per-instance grids, bounded
-by the best p so far). Full G-QAOA (angles per round): starting one round
-below the single-pair count, all 2p angles are optimized with the adjoint
-gradient from the best single pair at that p, stepping down while the
-optimum still reaches S.
+by the best p so far). Full G-QAOA (angles per round): the least p at
+which all 2p angles, optimized with the level-space adjoint gradient from the
+best single pair at that p, reach S, by bisection below the single-pair count
+(many instances in lockstep).
 """
 from __future__ import annotations
 
@@ -101,26 +101,84 @@ def single_pair_rounds(ns, ms, hists, S: float, p_max, targets=None, grid=None, 
     return p_star, np.mod(beta, 2 * math.pi), gamma
 
 
-def full_rounds(n: int, m: int, cost, hist, S: float, p_single: int, target: int = 0, grid=(120, 61),
-                dtype=g.C128, p_floor: int = 1):
-    """Least full-G-QAOA rounds reaching S, searching down from p_single - 1.
+def _best_pairs_at(ns, ms, hists, tg, p, gb, gg):
+    """Best single pair of the grid at each instance's own round count p[i]
+    (one scan per distinct p). Returns (beta[I], gamma[I])."""
+    I = len(p)
+    beta = np.zeros(I)
+    gamma = np.zeros(I)
+    for pv in np.unique(p):
+        sel = np.nonzero(p == pv)[0]
+        ps, _ = g.gqaoa_scan_batched(ns[sel], ms[sel], hists[sel], gb, gg, [int(pv)], targets=tg[sel],
+                                     with_energy=False)
+        j = _argbest(ps.reshape(sel.size, -1))
+        beta[sel] = gb[j % gb.size]
+        gamma[sel] = gg[j // gb.size]
+    return beta, gamma
 
-    At each p the seed is the best single pair of a (beta, gamma) grid at
-    that p (one batched-scan launch), then all 2p angles are optimized
-    (``optim.full_gqaoa``). Returns (p_full, betas, gammas, psol) at the
-    least p reached (p_single with None angles if no smaller p reaches S)."""
-    hist = np.asarray(hist).reshape(1, -1)
+
+def _argbest(v):
+    """Per row: index of the largest entry, ties to the lowest index."""
+    return v.argmax(dim=1).cpu().numpy()
+
+
+def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(120, 61), p_floor: int = 1):
+    """Least full-G-QAOA rounds reaching S for every instance.
+
+    For a candidate p the seed is the best single pair of a (beta, gamma) grid
+    at that p, then all 2p angles are optimized (``optim.full_gqaoa_batched``,
+    all candidates of one step in lockstep). The best P over all 2p angles
+    cannot fall when p grows (a round with beta = gamma = 0 is the identity),
+    so the least p with P >= S is found by bisection on [p_floor, p_single],
+    p_single (the single-pair rounds, reached by one pair) being the upper
+    end. Instances with p_single = 0 (not reached) are skipped.
+    Returns (p_full[I] (0 where skipped), betas [I, p_max], gammas [I, p_max],
+    psol[I], optimized[I]) at p_full; optimized[i] is False where no p below
+    p_single reached S (then the angles are zero and psol NaN)."""
+    hists = np.asarray(hists)
+    ns = np.asarray(ns, dtype=np.int32)
+    ms = np.asarray(ms, dtype=np.int32)
+    I = hists.shape[0]
+    tg = np.zeros(I, dtype=np.int32) if targets is None else np.asarray(targets, dtype=np.int32)
+    hi = np.asarray(p_single, dtype=np.int64).copy()
+    lo = np.minimum(np.full(I, p_floor, dtype=np.int64), hi)
+    pmax = int(max(1, hi.max()))
+    betas = np.zeros((I, pmax))
+    gammas = np.zeros((I, pmax))
+    psol = np.full(I, np.nan)
+    opt = np.zeros(I, dtype=bool)
     gb, gg = optim.fundamental_grid(*grid)
-    best = (p_single, None, None, None)
-    for p in range(p_single - 1, p_floor - 1, -1):
-        ps, _ = g.gqaoa_scan_batched([n], [m], hist, gb, gg, [p], targets=[target], with_energy=False)
-        j = int(ps.reshape(-1).argmax().item())
-        b0, g0 = gb[j % gb.size], gg[j // gb.size]
-        bs, gs, P = optim.full_gqaoa(n, m, cost, p, b0, g0, target=target, dtype=dtype)
-        if P < S:
+    while True:
+        act = np.nonzero((hi > 0) & (lo < hi))[0]
+        if act.size == 0:
             break
-        best = (p, bs, gs, P)
-    return best
+        mid = (lo[act] + hi[act]) // 2
+        b0, g0 = _best_pairs_at(ns[act], ms[act], hists[act], tg[act], mid, gb, gg)
+        bs, gs, P = optim.full_gqaoa_batched(ns[act], ms[act], hists[act], mid, b0, g0, tg[act])
+        ok = P >= S
+        for k, i in enumerate(act):
+            if ok[k]:
+                hi[i] = mid[k]
+                betas[i] = 0.0
+                gammas[i] = 0.0
+                betas[i, :mid[k]] = bs[k, :mid[k]]
+                gammas[i, :mid[k]] = gs[k, :mid[k]]
+                psol[i] = P[k]
+                opt[i] = True
+            else:
+                lo[i] = mid[k] + 1
+    return hi, betas, gammas, psol, opt
+
+
+def full_rounds(n: int, m: int, hist, S: float, p_single: int, target: int = 0, grid=(120, 61), p_floor: int = 1):
+    """``full_rounds_batched`` for one instance: (p_full, betas, gammas, psol)
+    at the least p reached, with None angles and psol when no p below
+    p_single reaches S."""
+    pf, bs, gs, P, ok = full_rounds_batched([n], [m], np.asarray(hist).reshape(1, -1), S, [p_single], [target],
+                                            grid, p_floor)
+    if not ok[0]:
+        return int(pf[0]), None, None, None
+    return int(pf[0]), bs[0, :pf[0]].copy(), gs[0, :pf[0]].copy(), float(P[0])
 
 
 def sqrt_fit(P, p):

@@ -16,8 +16,10 @@ Reported:
     ceil(cap_c / sqrt(P)); the fit log p = a + b log(1/P) (b = 1/2 is the
     quadratic speed-up) and the median of p sqrt(P);
   * S = 25% and 75% for the n = ``conv_n`` instances (the convergence study);
-  * full G-QAOA rounds (all angles optimized with the adjoint gradient) for a
-    seeded subsample with n <= ``full_n_max``;
+  * full G-QAOA rounds (all 2p angles optimized by L-BFGS-B with the
+    level-space adjoint gradient, bisection below the single-pair count) for
+    every instance with n <= ``full_n_max`` (default 20: Sec. V compares the
+    single-pair results at 26 qubits with full G-QAOA results at 20);
   * rounds against density (slope of a linear fit) for both sets;
   * the spread of the single-pair angles (median and interquartile range),
     which is the parameter clustering of Sec. III.B and its Max-SAT appendix.
@@ -69,8 +71,11 @@ def main(argv=None):
     ap.add_argument("--per-n-large", type=int, default=50, help="instances per n for n >= 23")
     ap.add_argument("--cap-c", type=float, default=3.0)
     ap.add_argument("--conv-n", type=int, default=16)
-    ap.add_argument("--full", type=int, default=12, help="instances of the full G-QAOA subsample")
-    ap.add_argument("--full-n-max", type=int, default=14)
+    ap.add_argument("--full", type=int, default=0,
+                    help="full G-QAOA on a seeded subsample of this many instances per set (0: all with n <= full-n-max)")
+    ap.add_argument("--full-n-max", type=int, default=20)
+    ap.add_argument("--full-grid", type=int, nargs=2, default=[120, 61],
+                    help="grid of the single-pair seed at each candidate p of the full G-QAOA search")
     ap.add_argument("--grid", type=int, nargs=2, default=[360, 181], help="grid for n <= 20")
     ap.add_argument("--grid-large", type=int, nargs=2, default=[360, 181],
                     help="grid for n > 20 (the paper samples 4000 pairs there; a coarse grid misses the narrow "
@@ -154,26 +159,36 @@ def main(argv=None):
                 f"{t_s:.1f} s")
             if S == 0.5:
                 p_half, b_half, g_half = p_star, beta, gamma
-        # full G-QAOA on a seeded subsample
-        rng = np.random.Generator(np.random.PCG64(77 if kind == "sat" else 78))
+        # full G-QAOA (all 2p angles, level-space adjoint) on every instance with
+        # n <= full_n_max that the single pair reached in more than one round
+        # (or a seeded subsample of --full of them)
         pool = np.nonzero((ns <= a.full_n_max) & (p_half > 1))[0]
-        sub = rng.choice(pool, min(a.full, pool.size), replace=False) if pool.size else []
-        full = []
-        t0 = time.perf_counter()
-        for i in sub:
-            it = its[i]
-            cost, hist = g.gqaoa_cost_table(it.n, it.lits)
-            pf, _, _, Pf = rounds.full_rounds(it.n, it.m, cost, H[i, :it.m + 1], 0.5, int(p_half[i]),
-                                              target=int(targets[i]), grid=(120, 61))
-            full.append({"n": it.n, "m": it.m, "P": float(P[i]), "p_single": int(p_half[i]), "p_full": int(pf)})
-        t_full = time.perf_counter() - t0
-        if len(full) >= 3:
-            b, icpt, c = rounds.sqrt_fit([f["P"] for f in full], [f["p_full"] for f in full])
-            entry["full_gqaoa"] = {"instances": len(full), "seconds": t_full, "fit_slope": b, "median_p_sqrtP": c,
-                                   "mean_ratio_full_to_single": float(np.mean([f["p_full"] / f["p_single"] for f in full])),
-                                   "records": full}
-            log(f"{kind} full G-QAOA: {len(full)} instances, slope {b:.3f}, mean p_full/p_single "
-                f"{entry['full_gqaoa']['mean_ratio_full_to_single']:.3f}, {t_full:.1f} s")
+        if a.full and pool.size > a.full:
+            rng = np.random.Generator(np.random.PCG64(77 if kind == "sat" else 78))
+            pool = np.sort(rng.choice(pool, a.full, replace=False))
+        if pool.size:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pf, _, _, Pf, okf = rounds.full_rounds_batched(ns[pool], ms[pool], H[pool], 0.5, p_half[pool],
+                                                           targets=targets[pool], grid=tuple(a.full_grid))
+            t_full = time.perf_counter() - t0
+            full = [{"n": int(ns[i]), "m": int(ms[i]), "P": float(P[i]), "p_single": int(p_half[i]),
+                     "p_full": int(pf[k])} for k, i in enumerate(pool)]
+            rec = {"instances": len(full), "seconds": t_full, "grid": a.full_grid,
+                   "mean_ratio_full_to_single": float(np.mean(pf / p_half[pool])),
+                   "instances_below_single": int(okf.sum()), "records": full}
+            if len(full) >= 3:
+                b, icpt, c = rounds.sqrt_fit(P[pool], pf)
+                rec.update({"fit_slope": b, "median_p_sqrtP": c})
+                per_n = {}
+                for n in np.unique(ns[pool]):
+                    mk = ns[pool] == n
+                    per_n[str(int(n))] = {"median_p_full": float(np.median(pf[mk])),
+                                          "median_p_single": float(np.median(p_half[pool][mk]))}
+                rec["per_n"] = per_n
+            entry["full_gqaoa"] = rec
+            log(f"{kind} full G-QAOA: {len(full)} instances, slope {rec.get('fit_slope', float('nan')):.3f}, "
+                f"mean p_full/p_single {rec['mean_ratio_full_to_single']:.3f}, {t_full:.1f} s")
         res[kind] = entry
     out = json.dumps(res, default=float)
     print(out, flush=True)

@@ -138,6 +138,32 @@ def test_grad_and_scan_argument_checks():
     assert lib.gqaoa_scan_workspace_bytes(1, 43, 4, 4, 2, 1) >= ws
 
 
+def test_scan_rejects_more_than_128_occupied_levels():
+    """128 occupied levels is the largest register array of the scan kernels:
+    an instance with 129 gets ERANGE from both scan forms, before any device
+    call; 128 passes validation (the call then fails only for want of a GPU)."""
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    ns = np.array([30], dtype=np.int32)
+    m = np.array([200], dtype=np.int32)
+    b = np.zeros(4)
+    pl = np.array([1, 4], dtype=np.int32)
+    for K, want in ((129, -2), (128, None)):
+        hist = np.zeros((1, 201), dtype=np.uint64)
+        hist[0, :K] = 1
+        hist[0, 0] += (1 << 30) - K
+        ws = lib.gqaoa_scan_workspace_bytes(1, 201, 4, 4, 2, 0)
+        s1 = lib.gqaoa_scan_batched(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 201, None, 4, g._np_ptr(b), 4,
+                                    g._np_ptr(b), 0, 2, g._np_ptr(pl), d, None, None, d, ws, None)
+        s2 = lib.gqaoa_scan_crossing(1, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), 201, None, 4, g._np_ptr(b), 4,
+                                     g._np_ptr(b), 0, 8, None, ctypes.c_float(0.5), d, None, d, ws, None)
+        if want is not None:
+            assert s1 == want and s2 == want, (K, s1, s2)
+            assert b"occupied levels" in lib.gqaoa_last_error()
+        else:
+            assert s1 not in (-1, -2, -3) and s2 not in (-1, -2, -3), (K, s1, s2)
+
+
 def test_fairness_argument_checks():
     lib = g.load_library()
     d = ctypes.c_void_p(16)
@@ -272,6 +298,31 @@ def test_checkpoint_interval_choice():
     assert ws(c) == smallest and all(ws(k) > smallest for k in range(c + 1, p))
     with pytest.raises(g.GQAOAError):
         g.choose_ckpt_every(I, n, p, g.C128, budget_bytes=smallest - 1)
+
+
+def test_hist_grad_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    ns = np.array([10, 12], dtype=np.int32)
+    ms = np.array([42, 50], dtype=np.int32)
+    hist = np.zeros((2, 51), dtype=np.uint64)
+    hist[:, :5] = 1
+    ang = np.zeros((2, 6))
+    ws = lib.gqaoa_hist_grad_workspace_bytes(2, 51, 6)
+    assert ws > 0 and lib.gqaoa_hist_grad_workspace_bytes(2, 51, 0) == 0
+
+    def call(p_max=6, p=None, t=None, wsb=ws, m=ms, stride=51):
+        return lib.gqaoa_hist_grad_batched(2, g._np_ptr(ns), g._np_ptr(m), g._np_ptr(hist), stride, g._np_ptr(t),
+                                           p_max, g._np_ptr(p), g._np_ptr(ang), g._np_ptr(ang), None, None, None,
+                                           d, wsb, None)
+    assert call(p_max=0) == -2
+    assert call(p=np.array([3, 7], dtype=np.int32)) == -2          # p_i > p_max
+    assert call(p=np.array([0, 2], dtype=np.int32)) == -2          # p_i < 1
+    assert call(t=np.array([0, 51], dtype=np.int32)) == -2         # target > m
+    assert call(m=np.array([42, 51], dtype=np.int32)) == -2        # m + 1 > stride
+    assert call(wsb=ws - 1) == -3
+    assert lib.gqaoa_hist_grad_batched(2, g._np_ptr(ns), g._np_ptr(ms), None, 51, None, 6, None, g._np_ptr(ang),
+                                       g._np_ptr(ang), None, None, None, d, ws, None) == -1
 
 
 def test_cost_table_noalloc_rejects_bad_arguments():

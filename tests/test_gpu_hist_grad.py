@@ -123,3 +123,104 @@ def test_grad_auto_checkpointing_matches_explicit():
     small = g.gqaoa_grad_batched(n, [m] * I, costs, betas, gammas, workspace=ws)
     for a, b in zip(ref, small):
         assert np.array_equal(a, b)
+
+
+def _hist_batch(specs, seed0):
+    """Histograms (host, int64 [I, stride]) of random instances (n, m) and, for
+    m >= 128 entries given as ("synthetic", K, m, n), synthetic ones with K
+    occupied levels."""
+    from gpu_common import synthetic_hist
+    rows, ns, ms = [], [], []
+    for j, sp in enumerate(specs):
+        if sp[0] == "synthetic":
+            _, K, m, n = sp
+            h = synthetic_hist(K, m, n, seed0 + j).astype(np.int64)
+        else:
+            n, m = sp
+            h = level_histogram(cost_table(n, rand_lits(n, m, seed0 + j)), m)
+        rows.append(h)
+        ns.append(n)
+        ms.append(m)
+    stride = max(ms) + 1
+    H = np.zeros((len(rows), stride), dtype=np.int64)
+    for i, h in enumerate(rows):
+        H[i, :len(h)] = h
+    return H, ns, ms
+
+
+def test_hist_grad_batched_vs_oracle_sweep():
+    """Level-space adjoint (float64) for a batch of instances with different
+    n, m, targets and round counts, including 65..256 occupied levels (all
+    three register layouts), against the oracle's level-space sweep: 1e-12 on
+    P and dP/dbeta, 1e-12 * m on dP/dgamma; entries past an instance's p are 0."""
+    need_gpu()
+    specs = [(8, 34), (10, 42), (12, 50), (14, 59), (16, 67), (11, 90), (9, 60), (20, 84),
+             ("synthetic", 100, 200, 30), ("synthetic", 129, 180, 26), ("synthetic", 256, 255, 40),
+             ("synthetic", 64, 64, 20), ("synthetic", 65, 70, 22)]
+    H, ns, ms = _hist_batch(specs, 700)
+    I, pmax = len(specs), 24
+    rng = np.random.Generator(np.random.PCG64(701))
+    p = rng.integers(1, pmax + 1, I)
+    p[0], p[1] = pmax, 1
+    targets = np.zeros(I, dtype=np.int32)
+    for i in (2, 5, 6, 9):
+        targets[i] = int(np.nonzero(H[i])[0][0]) if H[i, 0] == 0 else int(np.nonzero(H[i])[0][1])
+    targets[7] = ms[7]                       # an unoccupied level: P = 0, gradient 0
+    B = rng.uniform(0, np.pi, (I, pmax))
+    G = rng.uniform(0, np.pi, (I, pmax))
+    log(f"hist grad batched I={I} pmax={pmax}")
+    P, db, dg = g.gqaoa_hist_grad_batched(ns, ms, H, B, G, targets=targets, p=p)
+    for i in range(I):
+        rP, rdb, rdg = grad_hist(H[i, :ms[i] + 1], B[i, :p[i]], G[i, :p[i]], int(targets[i]))
+        assert abs(P[i] - rP) < 1e-12, (i, P[i], rP)
+        assert np.abs(db[i, :p[i]] - rdb).max() < 1e-12, (i, np.abs(db[i, :p[i]] - rdb).max())
+        assert np.abs(dg[i, :p[i]] - rdg).max() < 1e-12 * ms[i], (i, np.abs(dg[i, :p[i]] - rdg).max())
+        assert not db[i, p[i]:].any() and not dg[i, p[i]:].any()
+    assert P[7] == 0.0 and not db[7].any() and not dg[7].any()
+
+
+def test_hist_grad_batched_central_fd_and_statevector():
+    """The same gradient against central differences (h = 1e-4, float64) of the
+    oracle's level-space P (bar 1e-6, the truncation error h^2 P'''/6 being
+    far smaller), and against the device statevector adjoint (complex128) on
+    the same instance (1e-12)."""
+    need_gpu()
+    n, m, p = 10, 44, 9
+    lits = rand_lits(n, m, 731)
+    ref_cost = cost_table(n, lits)
+    h = level_histogram(ref_cost, m)
+    beta, gamma = inst.uniform_angles(732, p)
+    P, db, dg = g.gqaoa_hist_grad_batched([n], [m], h[None, :], beta[None, :], gamma[None, :])
+    eps = 1e-4
+    for k in range(p):
+        for arr, d in ((beta, db[0, k]), (gamma, dg[0, k])):
+            xp, xm = arr.copy(), arr.copy()
+            xp[k] += eps
+            xm[k] -= eps
+            bp, gp = (xp, gamma) if arr is beta else (beta, xp)
+            bm, gm_ = (xm, gamma) if arr is beta else (beta, xm)
+            fd = (evolve_hist(h, bp, gp)[1][-1] - evolve_hist(h, bm, gm_)[1][-1]) / (2 * eps)
+            assert abs(d - fd) < 1e-6, (k, d, fd)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    Ps, dbs, dgs = g.gqaoa_grad(n, m, cost, beta, gamma, dtype=g.C128, ckpt_every=0)
+    assert abs(P[0] - Ps) < 1e-12
+    assert np.abs(db[0] - dbs).max() < 1e-12
+    assert np.abs(dg[0] - dgs).max() < 1e-12 * m
+
+
+def test_hist_grad_batched_many_rounds():
+    """p = 400 rounds: the reverse sweep runs every round backwards instead of
+    storing the forward states; its rounding stays within 1e-11 of the
+    oracle's stored-state sweep."""
+    need_gpu()
+    H, ns, ms = _hist_batch([(16, 67), (20, 84), ("synthetic", 120, 150, 28)], 740)
+    rng = np.random.Generator(np.random.PCG64(741))
+    pmax = 400
+    B = rng.uniform(0, 2 * np.pi, (3, pmax))
+    G = rng.uniform(0, np.pi, (3, pmax))
+    P, db, dg = g.gqaoa_hist_grad_batched(ns, ms, H, B, G)
+    for i in range(3):
+        rP, rdb, rdg = grad_hist(H[i, :ms[i] + 1], B[i], G[i])
+        assert abs(P[i] - rP) < 1e-11
+        assert np.abs(db[i] - rdb).max() < 1e-11, np.abs(db[i] - rdb).max()
+        assert np.abs(dg[i] - rdg).max() < 1e-11 * ms[i], np.abs(dg[i] - rdg).max()

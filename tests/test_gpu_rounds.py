@@ -137,13 +137,53 @@ def test_full_rounds_reach_target_in_oracle():
     h = hist.cpu().numpy().reshape(1, -1)
     p1, b1, g1 = rounds.single_pair_rounds([it.n], [it.m], h, 0.5, 200, grid=(60, 31), zoom_levels=1)
     assert p1[0] > 1
-    pf, bs, gs, P = rounds.full_rounds(it.n, it.m, cost, h[0], 0.5, int(p1[0]), grid=(60, 31))
+    pf, bs, gs, P = rounds.full_rounds(it.n, it.m, h[0], 0.5, int(p1[0]), grid=(60, 31))
     assert pf <= p1[0]
+    ref_h = level_histogram(cost_table(it.n, it.lits), it.m)
     if bs is not None:
-        ref_h = level_histogram(cost_table(it.n, it.lits), it.m)
         ps = evolve_hist(ref_h, bs, gs)[1][-1]
         assert ps >= 0.5 - 1e-9 and abs(ps - P) < 1e-9
+    # the same optimum through the statevector adjoint at p_full
+    if bs is not None:
+        j = pf
+        b0 = optim.fundamental_grid(60, 31)
+        ps_grid, _ = g.gqaoa_scan_batched([it.n], [it.m], h, b0[0], b0[1], [j], with_energy=False)
+        k = int(ps_grid.reshape(-1).argmax().item())
+        sb, sg = b0[0][k % 60], b0[1][k // 60]
+        _, _, Psv = optim.full_gqaoa_statevector(it.n, it.m, cost, j, sb, sg)
+        assert abs(Psv - P) < 1e-5, (Psv, P)
     torch.cuda.synchronize()
+
+
+def test_full_rounds_batched_matches_single_and_oracle():
+    """Full G-QAOA rounds for a batch (satisfiable, target 0, and unsatisfiable,
+    target k_min) equal the one-instance calls (the lockstep runs take the
+    same steps), and the returned angles reach S in the oracle's evolution."""
+    need_gpu()
+    its = (inst.batched_scan_instances(24, 4, 9, 12, density_range=(3.0, 4.5), dup="drop") +
+           inst.batched_scan_instances(25, 3, 9, 11, want="unsat", density_range=(4.6, 8.0), dup="drop"))
+    ns = [it.n for it in its]
+    ms = [it.m for it in its]
+    H = g.gqaoa_hist_batched(ns, ms, [it.lits for it in its], hist_stride=max(ms) + 1).cpu().numpy()
+    tg, _ = rounds.maxsat_targets(ns, H)
+    tg[:4] = 0
+    p1, _, _ = rounds.single_pair_rounds(ns, ms, H, 0.5, 300, targets=tg, grid=(60, 31), zoom_levels=1)
+    log(f"full rounds batched: p_single {p1.tolist()}")
+    pf, B, G, P, ok = rounds.full_rounds_batched(ns, ms, H, 0.5, p1, targets=tg, grid=(60, 31))
+    assert ((pf <= p1) & ((pf > 0) == (p1 > 0))).all()
+    assert ok.any()
+    for i, it in enumerate(its):
+        if p1[i] == 0:
+            continue
+        pf1, b1, g1, P1 = rounds.full_rounds(it.n, it.m, H[i, :it.m + 1], 0.5, int(p1[i]), target=int(tg[i]),
+                                             grid=(60, 31))
+        assert pf1 == pf[i]
+        if ok[i]:
+            np.testing.assert_array_equal(b1, B[i, :pf[i]])
+            assert P1 == P[i]
+            ref_h = level_histogram(cost_table(it.n, it.lits), it.m)
+            ps = evolve_hist(ref_h, B[i, :pf[i]], G[i, :pf[i]], int(tg[i]))[1][-1]
+            assert ps >= 0.5 - 1e-9 and abs(ps - P[i]) < 1e-9
 
 
 def test_per_instance_caps():
