@@ -427,6 +427,49 @@ int gqaoa_draws_to_reject(int num_solutions, const double *q_host, int trials, u
                           double crit, int n_min, int max_draws, int32_t *draws_dev,
                           void *stream);
 
+/* ---- selections on device data -----------------------------------------------
+ * Small steps the drivers take between the calls above (picking optimized
+ * angles from a scan, the earliest crossing of Sec. III.A, the solution
+ * distribution of Sec. IV), kept on the device so that no other framework
+ * computes on the library's outputs.
+ *
+ * gqaoa_row_best: x_dev is a row-major rows x cols matrix. For every row r,
+ * idx_dev[r] (int32) = the column of its best entry, ties to the lowest
+ * column, and val_dev[r] (NULL to skip) = that entry:
+ *   GQAOA_ROW_ARGMAX_F32: the largest float (a NaN never beats a number);
+ *   GQAOA_ROW_ARGMIN_F32: the smallest float;
+ *   GQAOA_ROW_MIN_POSITIVE_I32: the least int32 > 0 (the earliest first
+ *     crossing of gqaoa_scan_crossing); idx and val are 0 if the row has none.
+ * rows >= 1, cols in [1, 2^30]. Enqueues only. Errors: ERANGE, EINVAL. */
+enum { GQAOA_ROW_ARGMAX_F32 = 0, GQAOA_ROW_ARGMIN_F32 = 1, GQAOA_ROW_MIN_POSITIVE_I32 = 2 };
+int gqaoa_row_best(int rows, int cols, const void *x_dev, int mode, int32_t *idx_dev, void *val_dev,
+                   void *stream);
+
+/* The assignments of one cost level and their output probabilities (the
+ * solution distribution whose fairness Sec. IV measures, level 0; or any
+ * other level): for the k-th z in ascending order with C(z) = level,
+ * z_dev[k] = z (int64) and prob_dev[k] = |psi_z|^2 (float64, from the state's
+ * components), for k < min(count, max_out); *count_host = the number of such
+ * z. Either output may be NULL. cost_dev: uint8[2^n]; psi_dev: float2 or
+ * double2 [2^n]. ws: gqaoa_level_probs_workspace_bytes(n) bytes (8 bytes per
+ * 16384 assignments). Synchronizes the stream. Errors: ERANGE (n, level,
+ * max_out < 0), EINVAL, EWORKSPACE. */
+size_t gqaoa_level_probs_workspace_bytes(int n);
+int gqaoa_level_probs(int n, const uint8_t *cost_dev, const void *psi_dev, int dtype, int level,
+                      int64_t max_out, int64_t *z_dev, double *prob_dev, int64_t *count_host,
+                      void *ws_dev, size_t ws_bytes, void *stream);
+
+/* The angle map of the network (gqaoa_mlp_forward / gqaoa_mlp_infer outputs
+ * [batch][2]): beta_dev[b] = 2 pi sigmoid(o_b0), gamma_dev[b] = pi
+ * sigmoid(o_b1), in float64. batch in [1, 2^26]. Enqueues only. */
+int gqaoa_mlp_angles(int batch, const float *out_dev, double *beta_dev, double *gamma_dev, void *stream);
+
+/* Row gather (training batches): dst row r = src row idx_dev[r] for r <
+ * rows, rows of row_bytes bytes (a multiple of 4, at most 1 MiB); an index
+ * outside [0, src_rows) gives a row of zeros. Enqueues only. */
+int gqaoa_gather_rows(int rows, const int32_t *idx_dev, int src_rows, const void *src_dev, int row_bytes,
+                      void *dst_dev, void *stream);
+
 /* ---- instrumentation ---------------------------------------------------------
  * gqaoa_profile_enable(k) with k >= 1 makes the library bracket one launch
  * in k (counted per name, from the last reset) of its streaming kernels with

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgqaoa.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["abi.hip", "cost_table.hip", "sv.hip", "hist.hip", "mlp.hip", "xmix.hip", "fairness.hip", "sv_items.hip", "plan.hip", "hist_grad.hip"]
+SOURCES = ["abi.hip", "cost_table.hip", "sv.hip", "hist.hip", "mlp.hip", "xmix.hip", "fairness.hip", "sv_items.hip", "plan.hip", "hist_grad.hip", "reduce.hip"]
 ARCH = "gfx950"
 
 COMMON = [

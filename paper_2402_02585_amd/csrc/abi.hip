@@ -29,6 +29,13 @@ int run_grad(int num_inst, int n, const int32_t *m_of, const uint8_t *cost, int 
              double *dgamma, void *ws, hipStream_t st);
 int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *beta, const double *gamma,
                     int target, double *psol, double *energy, double *norm, hipStream_t st);
+int run_row_best(int rows, int cols, const void *x, int mode, int32_t *idx, void *val, hipStream_t st);
+size_t level_probs_workspace_bytes(int n);
+int run_level_probs(int n, const uint8_t *cost, const void *psi, int dtype, int level, int64_t max_out,
+                    int64_t *z_out, double *p_out, int64_t *count, void *ws, hipStream_t st);
+int run_mlp_angles(int batch, const float *out, double *beta, double *gamma, hipStream_t st);
+int run_gather_rows(int rows, const int32_t *idx, int src_rows, const void *src, int row_bytes, void *dst,
+                    hipStream_t st);
 size_t hist_grad_workspace_bytes(int num_inst, int hist_stride, int pstride);
 int run_hist_grad(int num_inst, const int32_t *n_host, const int32_t *m_host, const uint64_t *hists,
                   int hist_stride, const int32_t *target_host, int pstride, const int32_t *p_host,
@@ -430,6 +437,63 @@ int gqaoa_hist_evolve(int n, int m, const uint64_t *hist_dev, int p, const doubl
     if (p > 0 && (!beta_host || !gamma_host)) return fail(GQAOA_EINVAL, "NULL angles");
     return run_hist_evolve(n, m, hist_dev, p, beta_host, gamma_host, target_level, psol_host, energy_host, norm_host,
                            (hipStream_t)stream);
+}
+
+int gqaoa_row_best(int rows, int cols, const void *x_dev, int mode, int32_t *idx_dev, void *val_dev, void *stream) {
+    clear_error();
+    if (rows < 1) return fail(GQAOA_ERANGE, "rows=%d", rows);
+    if (cols < 1 || cols > (1 << 30)) return fail(GQAOA_ERANGE, "cols=%d outside [1, 2^30]", cols);
+    if (mode < GQAOA_ROW_ARGMAX_F32 || mode > GQAOA_ROW_MIN_POSITIVE_I32) return fail(GQAOA_EINVAL, "mode=%d", mode);
+    if (!x_dev || !idx_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    return run_row_best(rows, cols, x_dev, mode, idx_dev, val_dev, (hipStream_t)stream);
+}
+
+size_t gqaoa_level_probs_workspace_bytes(int n) {
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return 0;
+    return level_probs_workspace_bytes(n);
+}
+
+int gqaoa_level_probs(int n, const uint8_t *cost_dev, const void *psi_dev, int dtype, int level, int64_t max_out,
+                      int64_t *z_dev, double *prob_dev, int64_t *count_host, void *ws_dev, size_t ws_bytes,
+                      void *stream) {
+    clear_error();
+    if (n < GQAOA_MIN_N || n > GQAOA_MAX_N) return fail(GQAOA_ERANGE, "n=%d outside [3, 34]", n);
+    if (level < 0 || level > GQAOA_MAX_M) return fail(GQAOA_ERANGE, "level=%d outside [0, 255]", level);
+    if (max_out < 0) return fail(GQAOA_ERANGE, "max_out=%lld", (long long)max_out);
+    if (!dtype_ok(dtype)) return fail(GQAOA_EINVAL, "dtype=%d", dtype);
+    if (!cost_dev || !psi_dev || !count_host || !ws_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    const size_t need = level_probs_workspace_bytes(n);
+    if (ws_bytes < need) return fail(GQAOA_EWORKSPACE, "workspace %zu < %zu bytes", ws_bytes, need);
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    return run_level_probs(n, cost_dev, psi_dev, dtype, level, max_out, z_dev, prob_dev, count_host, ws_dev,
+                           (hipStream_t)stream);
+}
+
+int gqaoa_mlp_angles(int batch, const float *out_dev, double *beta_dev, double *gamma_dev, void *stream) {
+    clear_error();
+    if (batch < 1 || batch > (1 << 26)) return fail(GQAOA_ERANGE, "batch=%d", batch);
+    if (!out_dev || !beta_dev || !gamma_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    return run_mlp_angles(batch, out_dev, beta_dev, gamma_dev, (hipStream_t)stream);
+}
+
+int gqaoa_gather_rows(int rows, const int32_t *idx_dev, int src_rows, const void *src_dev, int row_bytes,
+                      void *dst_dev, void *stream) {
+    clear_error();
+    if (rows < 1 || src_rows < 1) return fail(GQAOA_ERANGE, "rows=%d src_rows=%d", rows, src_rows);
+    if (row_bytes < 4 || row_bytes > (1 << 20) || row_bytes % 4) return fail(GQAOA_ERANGE, "row_bytes=%d", row_bytes);
+    if (!idx_dev || !src_dev || !dst_dev) return fail(GQAOA_EINVAL, "NULL argument");
+    DeviceInfo dev;
+    int s = device_info(&dev);
+    if (s) return s;
+    return run_gather_rows(rows, idx_dev, src_rows, src_dev, row_bytes, dst_dev, (hipStream_t)stream);
 }
 
 size_t gqaoa_hist_grad_workspace_bytes(int num_inst, int hist_stride, int p_max) {

@@ -22,11 +22,12 @@ from . import gqaoa as g
 
 
 def solution_probs(cost, psi, level: int = 0):
-    """(z values, |psi_z|^2) of the assignments with C(z) = level, z ascending."""
+    """(z values, |psi_z|^2) of the assignments with C(z) = level, z ascending
+    (selected on the device by ``gqaoa_level_probs``)."""
     import torch
-    idx = torch.nonzero(cost == level).flatten()
-    pr = psi[idx].abs().to(torch.float64) ** 2
-    return idx.cpu().numpy(), pr.cpu().numpy()
+    n = int(psi.numel()).bit_length() - 1
+    dt = g.C64 if psi.dtype == torch.complex64 else g.C128
+    return g.gqaoa_level_probs(n, cost, psi, dt, level)
 
 
 def shots_to_all_solutions(p_sol, runs: int = 100000, seed: int = 0, max_shots: int = 1 << 30):

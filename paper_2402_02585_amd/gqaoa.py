@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgqaoa.so")
 
 C64, C128 = 0, 1
+ROW_ARGMAX_F32, ROW_ARGMIN_F32, ROW_MIN_POSITIVE_I32 = 0, 1, 2   # modes of gqaoa_row_best
 SV_ITEMS_MAX_N = 14          # GQAOA_SV_ITEMS_MAX_N: largest n of a statevector work item (state in registers)
 MLP_NPARAMS = 160 * 256 + 256 + 256 * 256 + 256 + 256 * 2 + 2
 MLP_OFFSETS = {"W1": (0, (160, 256)), "b1": (40960, (256,)), "W2": (41216, (256, 256)),
@@ -70,6 +71,11 @@ _SIGS = {
     "gqaoa_mlp_adam": ([_vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
     "gqaoa_mlp_loss": ([_i32, _vp, _vp, _vp, _vp, _vp], _i32),
     "gqaoa_mlp_features": ([_i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_row_best": ([_i32, _i32, _vp, _i32, _vp, _vp, _vp], _i32),
+    "gqaoa_level_probs_workspace_bytes": ([_i32], _sz),
+    "gqaoa_level_probs": ([_i32, _vp, _vp, _i32, _i32, _c.c_int64, _vp, _vp, _vp, _vp, _sz, _vp], _i32),
+    "gqaoa_mlp_angles": ([_i32, _vp, _vp, _vp, _vp], _i32),
+    "gqaoa_gather_rows": ([_i32, _vp, _i32, _vp, _i32, _vp, _vp], _i32),
     "gqaoa_profile_enable": ([_i32], _i32),
     "gqaoa_profile_reset": ([], None),
     "gqaoa_profile_read": ([_c.c_char_p, _vp, _vp], _i32),
@@ -699,6 +705,72 @@ def gqaoa_mlp_features(hists, ns, ms, ps, x=None, stream=None):
     _check(lib.gqaoa_mlp_features(B, _ptr(hists), stride, _ptr(ns), _ptr(ms), _ptr(ps), _ptr(x),
                                   _stream(torch, stream)))
     return x
+
+
+# ---- selections on device data --------------------------------------------------------------
+def gqaoa_row_best(x, mode: int, with_value: bool = True, stream=None):
+    """Best entry of every row of a contiguous device matrix x (any shape:
+    rows = x.shape[0], the rest flattened): float32 for ROW_ARGMAX_F32 /
+    ROW_ARGMIN_F32, int32 for ROW_MIN_POSITIVE_I32. Returns (idx int32 [rows],
+    value [rows] or None) as device tensors; ties go to the lowest column."""
+    torch = _torch()
+    want = torch.int32 if mode == ROW_MIN_POSITIVE_I32 else torch.float32
+    if x.dtype != want or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError(f"x must be a contiguous device {want} tensor")
+    rows = int(x.shape[0])
+    cols = int(x.numel() // max(rows, 1))
+    idx = torch.empty(rows, dtype=torch.int32, device="cuda")
+    val = torch.empty(rows, dtype=want, device="cuda") if with_value else None
+    _check(load_library().gqaoa_row_best(rows, cols, _ptr(x), int(mode), _ptr(idx), _ptr(val), _stream(torch, stream)))
+    return idx, val
+
+
+def gqaoa_level_probs(n: int, cost, psi, dtype=C64, level: int = 0, max_out: int | None = None, stream=None):
+    """(z int64, |psi_z|^2 float64) numpy arrays of the assignments with
+    C(z) = level, z ascending (all of them when max_out is None)."""
+    torch = _torch()
+    lib = load_library()
+    dt = _dtype_code(dtype)
+    ws = _workspace(torch, lib.gqaoa_level_probs_workspace_bytes(n))
+    cap = 4096 if max_out is None else int(max_out)
+    cnt = np.zeros(1, dtype=np.int64)
+    while True:
+        z = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
+        pr = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
+        _check(lib.gqaoa_level_probs(n, _ptr(cost), _ptr(psi), dt, int(level), cap, _ptr(z), _ptr(pr),
+                                     _np_ptr(cnt), _ptr(ws), ws.numel(), _stream(torch, stream)))
+        total = int(cnt[0])
+        if max_out is not None or total <= cap:
+            k = min(total, cap)
+            return z[:k].cpu().numpy(), pr[:k].cpu().numpy()
+        cap = total
+
+
+def gqaoa_mlp_angles(out, stream=None):
+    """Network outputs [B, 2] (float32, device) -> (beta, gamma) float64 device tensors."""
+    torch = _torch()
+    B = int(out.shape[0])
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != 2 * B:
+        raise ValueError("out must be contiguous float32 [B, 2]")
+    beta = torch.empty(B, dtype=torch.float64, device="cuda")
+    gamma = torch.empty(B, dtype=torch.float64, device="cuda")
+    _check(load_library().gqaoa_mlp_angles(B, _ptr(out), _ptr(beta), _ptr(gamma), _stream(torch, stream)))
+    return beta, gamma
+
+
+def gqaoa_gather_rows(src, idx, out=None, stream=None):
+    """Rows src[idx[r]] of a contiguous device tensor (first dimension = rows)
+    into out [len(idx), *src.shape[1:]]; idx: int32 device tensor."""
+    torch = _torch()
+    R = int(idx.numel())
+    row_bytes = src[0].numel() * src.element_size()
+    if out is None:
+        out = torch.empty((R,) + tuple(src.shape[1:]), dtype=src.dtype, device="cuda")
+    if idx.dtype != torch.int32 or not src.is_contiguous() or not out.is_contiguous():
+        raise ValueError("idx must be int32, src and out contiguous")
+    _check(load_library().gqaoa_gather_rows(R, _ptr(idx), int(src.shape[0]), _ptr(src), int(row_bytes), _ptr(out),
+                                            _stream(torch, stream)))
+    return out
 
 
 # ---- instrumentation ------------------------------------------------------------------------

@@ -70,21 +70,26 @@ class AngleMLP:
         return g.gqaoa_mlp_infer(self.params, x.contiguous())
 
     def angles(self, x):
-        """(beta, gamma) numpy arrays: beta = 2 pi sigmoid(o0), gamma = pi sigmoid(o1)."""
-        o = self.outputs(x).cpu().numpy().astype(np.float64)
-        s = 1.0 / (1.0 + np.exp(-o))
-        return 2 * math.pi * s[:, 0], math.pi * s[:, 1]
+        """(beta, gamma) numpy arrays: beta = 2 pi sigmoid(o0), gamma = pi sigmoid(o1)
+        (the map runs on the device)."""
+        beta, gamma = g.gqaoa_mlp_angles(self.outputs(x))
+        return beta.cpu().numpy(), gamma.cpu().numpy()
 
     def train(self, X, Y, steps: int = 2000, batch: int = 512, lr: float = 1e-3, seed: int = 0, log_every: int = 0):
-        """Adam on the angle-regression loss. X [N, 131], Y [N, 2] device tensors."""
+        """Adam on the angle-regression loss. X [N, 131], Y [N, 2] device tensors.
+        Batches are drawn with replacement by a seeded host generator and
+        gathered on the device."""
         torch = _torch()
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(seed)
+        rng = np.random.Generator(np.random.PCG64(seed))
         N = X.shape[0]
+        B = min(batch, N)
+        xb = torch.empty((B, X.shape[1]), dtype=X.dtype, device="cuda")
+        yb = torch.empty((B, Y.shape[1]), dtype=Y.dtype, device="cuda")
         losses = []
         for s in range(steps):
-            idx = torch.randint(0, N, (min(batch, N),), device="cuda", generator=gen)
-            xb, yb = X[idx].contiguous(), Y[idx].contiguous()
+            idx = torch.from_numpy(rng.integers(0, N, B).astype(np.int32)).to("cuda")
+            g.gqaoa_gather_rows(X, idx, out=xb)
+            g.gqaoa_gather_rows(Y, idx, out=yb)
             out, act = g.gqaoa_mlp_forward(self.params, xb)
             dout, loss = g.gqaoa_mlp_loss(out, yb)
             g.gqaoa_mlp_backward(self.params, act, dout, grads=self.grads)
@@ -101,7 +106,7 @@ def features_for(hists_dev, ns, ms, p: int):
     I = hists_dev.shape[0]
     nd = torch.tensor(np.asarray(ns, dtype=np.int32), device="cuda")
     md = torch.tensor(np.asarray(ms, dtype=np.int32), device="cuda")
-    pd = torch.full((I,), p, dtype=torch.int32, device="cuda")
+    pd = torch.tensor(np.full(I, p, dtype=np.int32), device="cuda")
     return g.gqaoa_mlp_features(hists_dev.contiguous(), nd, md, pd)
 
 
@@ -159,10 +164,9 @@ def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 
             ps, _ = plan.run()
         else:
             ps, _ = plan.run(bgrid, ggrid)
-        v = ps[:, 0].reshape(I, -1)
-        jt = v.argmax(dim=1)
-        vj = v.gather(1, jt[:, None])[:, 0].cpu().numpy().astype(np.float64)  # only the best cell leaves the GPU
-        j = jt.cpu().numpy()
+        jd, vd = g.gqaoa_row_best(ps.reshape(I, -1), g.ROW_ARGMAX_F32)   # only the best cell leaves the GPU
+        j = jd.cpu().numpy()
+        vj = vd.cpu().numpy().astype(np.float64)
         better = vj > best
         b[better] = bgrid[better, j[better] % zoom]
         gm[better] = ggrid[better, j[better] // zoom]

@@ -93,6 +93,7 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
     gb, gg = fundamental_grid(*(grid or paper_grid()))
     tg = None if targets is None else np.asarray(targets)
     want_e = objective != "psol"
+    mode = g.ROW_ARGMIN_F32 if want_e else g.ROW_ARGMAX_F32
     per_inst = P * gb.size * gg.size * 4 * (2 if want_e else 1)
     chunk = max(1, int(max_out_bytes // per_inst))
     beta = np.empty((I, P))
@@ -102,14 +103,15 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
         sl = slice(c0, min(I, c0 + chunk))
         psol, energy = g.gqaoa_scan_batched(ns[sl], ms[sl], hists[sl], gb, gg, p_list,
                                             targets=None if tg is None else tg[sl], tile=tile, with_energy=want_e)
-        val = -psol if objective == "psol" else energy
-        flat = val.reshape(sl.stop - sl.start, P, -1)
-        idx = flat.argmin(dim=2)                       # ties -> lowest (gamma, beta) index
-        best_v[sl] = flat.gather(2, idx[:, :, None])[:, :, 0].cpu().numpy()
-        idx = idx.cpu().numpy()
+        rows = (sl.stop - sl.start) * P
+        # best cell per (instance, p), ties -> lowest (gamma, beta) index
+        jd, vd = g.gqaoa_row_best((psol if objective == "psol" else energy).reshape(rows, -1), mode)
+        idx = jd.cpu().numpy().reshape(-1, P)
+        v = vd.cpu().numpy().reshape(-1, P).astype(np.float64)
+        best_v[sl] = -v if objective == "psol" else v
         beta[sl] = gb[idx % gb.size]
         gamma[sl] = gg[idx // gb.size]
-        del psol, energy, val, flat
+        del psol, energy
     db, dg = gb[1] - gb[0], gg[1] - gg[0]
     plans = {}                       # per p: a graph-captured scan replayed at every zoom level
     for _ in range(zoom_levels):
@@ -123,9 +125,10 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
                 ps, en = plans[p].run()
             else:
                 ps, en = plans[p].run(bgrid, ggrid)
-            v = (-ps if objective == "psol" else en)[:, 0].reshape(I, -1)
-            j = v.argmin(dim=1).cpu().numpy()
-            vj = v.cpu().numpy()[np.arange(I), j]
+            jd, vd = g.gqaoa_row_best((en if want_e else ps).reshape(I, -1), mode)
+            j = jd.cpu().numpy()
+            vj = vd.cpu().numpy().astype(np.float64)
+            vj = vj if want_e else -vj
             better = vj < best_v[:, q]
             beta[better, q] = bgrid[better, j[better] % zoom]
             gamma[better, q] = ggrid[better, j[better] // zoom]

@@ -27,11 +27,6 @@ from . import gqaoa as g
 from . import optim
 
 
-def _torch():
-    import torch
-    return torch
-
-
 def maxsat_targets(ns, hists):
     """(k_min[I], D[I]) from host histograms [I, stride]."""
     hists = np.asarray(hists)
@@ -41,15 +36,11 @@ def maxsat_targets(ns, hists):
     return k.astype(np.int32), D
 
 
-def _min_first(first, nb):
-    """Per instance: (least nonzero first-crossing round or 0, flat argmin)."""
-    torch = _torch()
-    big = torch.iinfo(torch.int32).max
-    f = first.reshape(first.shape[0], -1)
-    f = torch.where(f > 0, f, torch.full_like(f, big))
-    val, idx = f.min(dim=1)
-    val = torch.where(val == big, torch.zeros_like(val), val)
-    return val.cpu().numpy().astype(np.int64), idx.cpu().numpy()
+def _min_first(first):
+    """Per instance: (least nonzero first-crossing round or 0, its flat grid
+    index, ties to the lowest)."""
+    jd, vd = g.gqaoa_row_best(first.reshape(first.shape[0], -1), g.ROW_MIN_POSITIVE_I32)
+    return vd.cpu().numpy().astype(np.int64), jd.cpu().numpy()
 
 
 def single_pair_rounds(ns, ms, hists, S: float, p_max, targets=None, grid=None, zoom: int = 16,
@@ -76,7 +67,7 @@ def single_pair_rounds(ns, ms, hists, S: float, p_max, targets=None, grid=None, 
         sl = slice(c0, min(I, c0 + chunk))
         first = g.gqaoa_scan_crossing(ns[sl], ms[sl], hists[sl], gb, gg, caps[sl], S,
                                       targets=None if tg is None else tg[sl], tile=tile)
-        v, idx = _min_first(first, gb.size)
+        v, idx = _min_first(first)
         p_star[sl] = v
         beta[sl] = gb[idx % gb.size]
         gamma[sl] = gg[idx // gb.size]
@@ -91,7 +82,7 @@ def single_pair_rounds(ns, ms, hists, S: float, p_max, targets=None, grid=None, 
         ggrid = np.clip(gamma[live, None] + offs[None, :] * dg, 0.0, math.pi)
         first = g.gqaoa_scan_crossing(ns[live], ms[live], hists[live], bgrid, ggrid, p_star[live], S,
                                       targets=None if tg is None else tg[live], tile=tile)
-        v, idx = _min_first(first, zoom)
+        v, idx = _min_first(first)
         better = (v > 0) & (v < p_star[live])
         sel = live[better]
         p_star[sel] = v[better]
@@ -119,7 +110,7 @@ def _best_pairs_at(ns, ms, hists, tg, p, gb, gg):
 
 def _argbest(v):
     """Per row: index of the largest entry, ties to the lowest index."""
-    return v.argmax(dim=1).cpu().numpy()
+    return g.gqaoa_row_best(v, g.ROW_ARGMAX_F32, with_value=False)[0].cpu().numpy()
 
 
 def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(120, 61), p_floor: int = 1):

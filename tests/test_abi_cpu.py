@@ -337,3 +337,24 @@ def test_cost_table_noalloc_rejects_bad_arguments():
     assert lib.gqaoa_cost_table_noalloc(5, 1, None, dummy, None, None) == -1
     assert lib.gqaoa_cost_table_noalloc(5, 1, g._np_ptr(ok), None, None, None) == -1
     assert lib.gqaoa_cost_table_noalloc(5, 1, g._np_ptr(_lits([[0, 1, 4]])), dummy, None, None) == -1  # var 0 twice
+
+
+def test_selection_argument_checks():
+    lib = g.load_library()
+    d = ctypes.c_void_p(16)
+    assert lib.gqaoa_row_best(4, 8, d, 3, d, None, None) == -1            # unknown mode
+    assert lib.gqaoa_row_best(4, 0, d, 0, d, None, None) == -2
+    assert lib.gqaoa_row_best(0, 8, d, 0, d, None, None) == -2
+    assert lib.gqaoa_row_best(4, 8, None, 0, d, None, None) == -1
+    cnt = np.zeros(1, dtype=np.int64)
+    ws = lib.gqaoa_level_probs_workspace_bytes(20)
+    assert ws == 8 * ((1 << 20) // 16384 + 1) and lib.gqaoa_level_probs_workspace_bytes(2) == 0
+    assert lib.gqaoa_level_probs(2, d, d, 0, 0, 4, d, d, g._np_ptr(cnt), d, ws, None) == -2
+    assert lib.gqaoa_level_probs(20, d, d, 0, 256, 4, d, d, g._np_ptr(cnt), d, ws, None) == -2
+    assert lib.gqaoa_level_probs(20, d, d, 0, 0, -1, d, d, g._np_ptr(cnt), d, ws, None) == -2
+    assert lib.gqaoa_level_probs(20, d, d, 2, 0, 4, d, d, g._np_ptr(cnt), d, ws, None) == -1
+    assert lib.gqaoa_level_probs(20, d, d, 0, 0, 4, d, d, g._np_ptr(cnt), d, ws - 1, None) == -3
+    assert lib.gqaoa_mlp_angles(0, d, d, d, None) == -2
+    assert lib.gqaoa_mlp_angles(4, d, None, d, None) == -1
+    assert lib.gqaoa_gather_rows(4, d, 10, d, 6, d, None) == -2             # not a multiple of 4
+    assert lib.gqaoa_gather_rows(4, d, 0, d, 8, d, None) == -2
