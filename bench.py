@@ -90,14 +90,52 @@ def host_info():
     return {"cpu_count": os.cpu_count(), "cpu_model": model}
 
 
-def cpu_baseline(legs: bool = True, fair=None):
-    """The oracle on bounded samples of each workload (one thread each).
+CPU_WORKERS_MAX = 16   # the host's CPU share on a one-GPU machine
 
-    Headline: its statevector evolution (complex128, numpy) of one seed-2
-    instance at n = 22, m = 92, p = 64 rounds. With ``legs``, beside it: the
-    level-space path on 64 instances of the scan workload, the adjoint at the
-    gradient workload's size, the MLP on one batch of 256, the X mixer and,
-    given the fairness leg's distribution, the fair-sampling Monte Carlo."""
+
+def _oracle_sv_worker(k, n, m, p, barrier, results):
+    """One oracle statevector evolution (complex128, numpy, one thread) in a
+    worker process, timed from a barrier shared with the other workers."""
+    from oracle.cost import cost_table
+    from oracle.evolve import evolve_sv
+    from paper_2402_02585_amd import instances as inst
+    lits = inst.random_3sat(np.random.Generator(np.random.PCG64(500 + k)), n, m)
+    cost = cost_table(n, lits)
+    beta, gamma = inst.uniform_angles(500 + k, p)
+    barrier.wait()
+    t0 = time.perf_counter()
+    evolve_sv(n, cost, beta, gamma)
+    results.put((k, time.perf_counter() - t0))
+
+
+def oracle_sv_parallel(n: int, m: int, p: int, workers: int):
+    """Aggregate amplitude-rounds/s of ``workers`` oracle evolutions running at
+    once, one per process (one instance each: the oracle as it stands, run
+    over the host's cores instance by instance). Returns (rate, seconds)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    barrier = ctx.Barrier(workers)
+    results = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_sv_worker, args=(k, n, m, p, barrier, results)) for k in range(workers)]
+    for pr in procs:
+        pr.start()
+    times = [results.get()[1] for _ in range(workers)]
+    for pr in procs:
+        pr.join()
+    wall = max(times)
+    return workers * (2 ** n) * p / wall, wall
+
+
+def cpu_baseline(legs: bool = True, fair=None):
+    """The oracle on bounded samples of each workload.
+
+    Headline: its statevector evolution (complex128, numpy) at n = 22, m = 92,
+    p = 64 rounds, one instance per process on up to 16 host cores at once
+    (the aggregate rate), and one seed-2 instance on one thread beside it.
+    With ``legs``, beside it (one thread each): the level-space path on 64
+    instances of the scan workload, the adjoint at the gradient workload's
+    size, the MLP on one batch of 256, the X mixer and, given the fairness
+    leg's distribution, the fair-sampling Monte Carlo."""
     from oracle.cost import cost_table, level_histogram
     from oracle.evolve import evolve_hist, evolve_sv
     from paper_2402_02585_amd import instances as inst
@@ -109,9 +147,13 @@ def cpu_baseline(legs: bool = True, fair=None):
     t0 = time.perf_counter()
     evolve_sv(n, cost, beta, gamma)
     dt = time.perf_counter() - t0
-    out = {"value": (2 ** n) * p / dt, "unit": "amplitude-rounds/s", "cores": 1, "kind": "oracle",
-           "sample": f"oracle statevector evolution, n={n} m={m} p={p}, complex128 numpy, one thread, "
-                     f"{dt:.1f} s"}
+    workers = max(1, min(os.cpu_count() or 1, CPU_WORKERS_MAX))
+    rate, wall = oracle_sv_parallel(n, m, p, workers)
+    out = {"value": rate, "unit": "amplitude-rounds/s", "cores": workers, "kind": "oracle",
+           "sample": f"oracle statevector evolution, n={n} m={m} p={p}, complex128 numpy: {workers} random "
+                     f"instances at once, one process (one thread) each, {wall:.1f} s wall",
+           "single_thread": {"value": (2 ** n) * p / dt, "seconds": dt,
+                             "sample": "the seed-2 instance alone on one thread"}}
     if not legs:
         return out
     out["legs"] = {}
@@ -636,6 +678,30 @@ def mlp_leg(torch, g):
     }
 
 
+def scan_replays(torch, g, inst, k: int):
+    """Only the batched scan of the batched leg, as 1 + k graph replays of its
+    scan plan (the dispatches a counter run over scan_kernel sees when the
+    autotuner's choices come from GQAOA_TUNE_CACHE). Returns its JSON."""
+    insts = inst.batched_scan_instances(3, 4096, 8, 20)
+    ns = [it.n for it in insts]
+    ms = [it.m for it in insts]
+    hists = g.gqaoa_hist_batched(ns, ms, [it.lits for it in insts], hist_stride=max(ms) + 1).cpu().numpy()
+    grid = np.linspace(0.0, math.pi, 64)
+    plist = [1, 4, 16, 64]
+    plan = g.ScanPlan(ns, ms, hists, grid, grid, plist)
+    plan.run(grid, grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        plan.run(grid, grid)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / max(k, 1)
+    plan.close()
+    levels = (hists > 0).sum(axis=1)
+    return {"profile": "scan replays", "replays": 1 + k, "timed_replays": k, "ms_per_scan": t * 1e3,
+            "mean_levels": float(levels.mean())}
+
+
 def rounds_leg(torch, g, inst):
     """Rounds-to-target search (single angle pair, S = 50%) for 512
     satisfiable instances, n in 12..20, d ~ U(2, 4.5), the pi/180 grid."""
@@ -673,6 +739,8 @@ def main():
     ap.add_argument("--skip-mlp", action="store_true", help="omit the angle-MLP leg")
     ap.add_argument("--skip-small", action="store_true", help="omit the small-n eager vs graph leg")
     ap.add_argument("--skip-fairness", action="store_true", help="omit the fair-sampling Monte Carlo leg")
+    ap.add_argument("--profile-scan", type=int, default=0, metavar="K",
+                    help="run only 1 + K graph replays of the batched scan and print their timing (counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three 2 GiB device copies (the reference dispatch for HBM counter scaling)")
     args = ap.parse_args()
@@ -689,6 +757,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+
+    if args.profile_scan:
+        print(json.dumps(scan_replays(torch, g, inst, args.profile_scan)), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.empty(2 ** 28, dtype=torch.complex64, device="cuda")

@@ -17,7 +17,7 @@ struct ScanSlot {          // one instance inside a bucket, in queue order
     int32_t inst;          // caller's instance index
     int32_t lev_off;       // into lev/w
     int32_t K;             // occupied levels
-    int32_t t_idx;         // position of the target level among them, -1 if unoccupied
+    int32_t t_idx;         // 0 when the target level is occupied (it comes first among them), else -1
     int32_t pmax;          // rounds to run for this instance
     int32_t pad[3];
 };

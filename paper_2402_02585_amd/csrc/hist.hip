@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace gqaoa {
@@ -157,104 +158,224 @@ int run_hist_evolve(int n, int m, const uint64_t *hist, int p, const double *bet
 
 // ---- batched single-angle-pair scan, float32 -------------------------------------------
 constexpr int kScanMaxWaves = 4;
-constexpr int kScanHoistMax = 24;  // largest bucket whose phase table is kept in registers
+// Tables up to kScanHoist4 levels stay in registers whole (cos, -sin, sin, w:
+// every instruction of a level-round has two VGPR operands); up to
+// kScanHoist3 levels as (cos, sin, w), with the one negated product of a
+// level-round as a three-operand fma, which gives the same value; larger
+// tables are re-read from LDS every round.
+constexpr int kScanHoist4 = 24;
+constexpr int kScanHoist3 = 28;
 
-// CROSS = false: P_sol (and E) after each p in p_list. CROSS = true: the
-// first round j <= p_list[0] with P >= threshold; a wave stops once every
-// lane has crossed.
-template <int KMAX, bool CROSS>
-__global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
-    __shared__ float4 tab_s[kScanMaxWaves][KMAX];   // e^{-i gamma k}.re/.im, w_k, k w_k
-    const int lane = threadIdx.x & 63;
-    float4 *tab = tab_s[threadIdx.x >> 6];
-    for (;;) {
-        unsigned int item = 0;
-        if (lane == 0) item = atomicAdd(a.counter, 1u);
-        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
-        if (item >= a.total_items) break;
-        const int tile = (int)(item % (unsigned)a.ntiles);
-        const unsigned rest = item / (unsigned)a.ntiles;
-        const int g = (int)(rest % (unsigned)a.ng);
-        const ScanSlot sl = a.slots[rest / (unsigned)a.ng];
-        const int pmax = sl.pmax;
-        const double gam = a.gammas[(a.per_inst ? (size_t)sl.inst * a.ng : 0) + g];
-        for (int k = lane; k < KMAX; k += 64) {
+// Per item, each wave's table in LDS: tab[k] = {cos(gamma l_k), -sin(gamma l_k),
+// sin(gamma l_k), w_k} and kw[k] = l_k w_k (read only at readouts). The target
+// level, when occupied, is level 0 of the instance's compacted order, so the
+// crossing readout reads one amplitude.
+//
+// A level-round is eight two-operand VALU instructions on VGPR operands (the
+// form gfx950 issues at twice the rate of instructions with an SGPR or a third
+// source): the phase multiply as two products and two fused accumulates, the
+// weighted sum for <s|phi> as two fused accumulates, the mixer as two adds.
+// Dual issue needs two waves with VALU work on a SIMD, so an item's loads
+// (its descriptor, levels and weights) are issued one item ahead, while the
+// previous item's rounds run, instead of stalling the wave between items.
+
+// The work item's coordinates: beta tile, gamma index and slot.
+struct ScanItem {
+    int tile, g;
+    unsigned slot;
+};
+__device__ __forceinline__ ScanItem scan_decode(const ScanArgs &a, unsigned item) {
+    const unsigned rest = item / (unsigned)a.ntiles;
+    return ScanItem{(int)(item % (unsigned)a.ntiles), (int)(rest % (unsigned)a.ng), rest / (unsigned)a.ng};
+}
+
+// The lane's share of an instance's levels: level k = lane + 64 i.
+template <int NL>
+__device__ __forceinline__ void scan_load_levels(const ScanArgs &a, const ScanSlot &sl, int lane, int (&lv)[NL],
+                                                 float (&wk)[NL]) {
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int k = lane + 64 * i;
+        lv[i] = k < sl.K ? a.lev[sl.lev_off + k] : 0;
+        wk[i] = k < sl.K ? a.w[sl.lev_off + k] : 0.f;
+    }
+}
+
+// Writes the item's table (phases in float64, rounded once) to LDS.
+template <int KMAX, int NL>
+__device__ __forceinline__ void scan_table(const ScanArgs &a, const ScanSlot &sl, int g, int lane, const int (&lv)[NL],
+                                           const float (&wk)[NL], float4 *tab, float *kw) {
+    const double gam = a.gammas[(a.per_inst ? (size_t)sl.inst * a.ng : 0) + g];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int k = lane + 64 * i;
+        if (k < KMAX) {
             float4 e = {1.f, 0.f, 0.f, 0.f};
+            float ew = 0.f;
             if (k < sl.K) {
-                const int lv = a.lev[sl.lev_off + k];
-                const float wk = a.w[sl.lev_off + k];
-                double s, c;
-                sincos(fmod(gam * (double)lv, 2.0 * M_PI), &s, &c);
-                e = {(float)c, (float)-s, wk, wk * (float)lv};
+                double sn, cs;
+                sincos(gam * (double)lv[i], &sn, &cs);
+                e = {(float)cs, (float)-sn, (float)sn, wk[i]};
+                ew = wk[i] * (float)lv[i];
             }
             tab[k] = e;
+            kw[k] = ew;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-        const int b = tile * 64 + lane;
-        const bool active = b < a.nb;
-        double sb, cb;
-        sincos(a.betas[(a.per_inst ? (size_t)sl.inst * a.nb : 0) + (active ? b : 0)], &sb, &cb);
-        const float mr = (float)(cb - 1.0), mi = (float)(-sb);
-        float br[KMAX], bi[KMAX];
+// The rounds of one item for this lane's beta (mixer e^{-i beta} - 1 = mr + i mi).
+template <int KMAX, bool CROSS>
+__device__ __forceinline__ void scan_rounds(const ScanArgs &a, const ScanSlot &sl, const ScanItem &it, int lane,
+                                            float mr, float mi, const float4 *tab, const float *kw) {
+    const int b = it.tile * 64 + lane;
+    const bool active = b < a.nb;
+    const float w0 = sl.t_idx == 0 ? tab[0].w : 0.f;   // weight of the target level (index 0)
+    float br[KMAX], bi[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        br[k] = 1.f;
+        bi[k] = 0.f;
+    }
+    int q = 0;
+    int found = 0;
+    const int pmax = sl.pmax;
+    int next_p = CROSS ? 0 : a.p_list[0];   // next readout round, kept in a register
+    for (int j = 1; j <= pmax; ++j) {
+        // Small tables stay in registers across rounds; larger ones are
+        // re-read from LDS (broadcast) each round to bound register use.
+        if constexpr (KMAX > kScanHoist3) asm volatile("" ::: "memory");
+        float sr = 0.f, si = 0.f;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
-            br[k] = 1.f;
-            bi[k] = 0.f;
+            const float4 e = tab[k];
+            const float nr = __builtin_fmaf(e.x, br[k], e.z * bi[k]);   // cos br + sin bi
+            float ni;                                                    // cos bi - sin br
+            if constexpr (KMAX <= kScanHoist4)
+                ni = __builtin_fmaf(e.x, bi[k], e.y * br[k]);
+            else
+                ni = __builtin_fmaf(e.x, bi[k], -(e.z * br[k]));
+            br[k] = nr;
+            bi[k] = ni;
+            sr = __builtin_fmaf(e.w, nr, sr);
+            si = __builtin_fmaf(e.w, ni, si);
         }
-        int q = 0;
-        int found = 0;
-        for (int j = 1; j <= pmax; ++j) {
-            // Small tables stay in registers across rounds; larger ones are
-            // re-read from LDS (broadcast) each round to bound register use.
-            if constexpr (KMAX > kScanHoistMax) asm volatile("" ::: "memory");
-            float sr = 0.f, si = 0.f;
+        const float cr = mr * sr - mi * si, ci = mr * si + mi * sr;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                const float4 e = tab[k];
-                const float nr = e.x * br[k] - e.y * bi[k];
-                const float ni = e.x * bi[k] + e.y * br[k];
-                br[k] = nr;
-                bi[k] = ni;
-                sr += e.z * nr;
-                si += e.z * ni;
-            }
-            const float cr = mr * sr - mi * si, ci = mr * si + mi * sr;
-#pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                br[k] += cr;
-                bi[k] += ci;
-            }
-            if constexpr (CROSS) {
-                float P = 0.f;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    P += k == sl.t_idx ? tab[k].z * (br[k] * br[k] + bi[k] * bi[k]) : 0.f;
-                if (found == 0 && P >= a.threshold) found = j;
-                if (__ballot(active && found == 0) == 0) break;  // wave-uniform
-            } else if (j == a.p_list[q]) {
-                float P = 0.f, E = 0.f;
-#pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    const float4 e = tab[k];
-                    const float pb = br[k] * br[k] + bi[k] * bi[k];
-                    E += e.w * pb;
-                    P += k == sl.t_idx ? e.z * pb : 0.f;
-                }
-                if (active) {
-                    const size_t o = (((size_t)sl.inst * a.num_p + q) * a.ng + g) * a.nb + b;
-                    a.psol[o] = P;
-                    if (a.energy) a.energy[o] = E;
-                }
-                ++q;
-            }
+        for (int k = 0; k < KMAX; ++k) {
+            br[k] += cr;
+            bi[k] += ci;
         }
-        if constexpr (CROSS)
-            if (active) a.first_p[((size_t)sl.inst * a.ng + g) * a.nb + b] = found;
+        if constexpr (CROSS) {
+            const float P = w0 * (br[0] * br[0] + bi[0] * bi[0]);
+            if (found == 0 && P >= a.threshold) found = j;
+            if (__ballot(active && found == 0) == 0) break;  // wave-uniform
+        } else if (j == next_p) {
+            float E = 0.f;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) E = __builtin_fmaf(kw[k], br[k] * br[k] + bi[k] * bi[k], E);
+            const float P = w0 * (br[0] * br[0] + bi[0] * bi[0]);
+            if (active) {
+                const size_t o = (((size_t)sl.inst * a.num_p + q) * a.ng + it.g) * a.nb + b;
+                a.psol[o] = P;
+                if (a.energy) a.energy[o] = E;
+            }
+            ++q;
+            next_p = q < a.num_p ? a.p_list[q] : 0;
+        }
+    }
+    if constexpr (CROSS)
+        if (active) a.first_p[((size_t)sl.inst * a.ng + it.g) * a.nb + b] = found;
+}
+
+// Mixer factor of this lane's beta, recomputed only when the beta row changes
+// (the grid is shared, or the instance's own).
+__device__ __forceinline__ void scan_mixer(const ScanArgs &a, const ScanSlot &sl, int tile, int lane, long long &key,
+                                           float &mr, float &mi) {
+    const long long k = (long long)(a.per_inst ? sl.inst : 0) * a.ntiles + tile;
+    if (k == key) return;
+    key = k;
+    const int b = tile * 64 + lane;
+    double sb, cb;
+    sincos(a.betas[(a.per_inst ? (size_t)sl.inst * a.nb : 0) + (b < a.nb ? b : 0)], &sb, &cb);
+    mr = (float)(cb - 1.0);
+    mi = (float)(-sb);
+}
+
+// CROSS = false: P_sol (and E) after each p in p_list. Every item of a bucket
+// costs the same (same padded level count, same rounds), so wave w of the
+// grid takes items w, w + W, w + 2W, ... (W waves), and the next item's
+// descriptor and levels are loaded while the current one runs.
+// CROSS = true: the first round j <= p_i with P >= threshold; a wave stops
+// once every lane has crossed, so items differ in length and come from a
+// global queue (the next index is fetched while the current item runs).
+template <int KMAX, bool CROSS>
+__global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
+    constexpr int NL = (KMAX + 63) / 64;
+    __shared__ float4 tab_s[kScanMaxWaves][KMAX];
+    __shared__ float kw_s[kScanMaxWaves][KMAX];
+    const int lane = threadIdx.x & 63;
+    float4 *tab = tab_s[threadIdx.x >> 6];
+    float *kw = kw_s[threadIdx.x >> 6];
+    long long mix_key = -1;
+    float mr = 0.f, mi = 0.f;
+    unsigned item;
+    if constexpr (CROSS) {
+        unsigned v = 0;
+        if (lane == 0) v = atomicAdd(a.counter, 1u);
+        item = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+    } else {
+        item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    }
+    if (item >= a.total_items) return;  // whole waves
+    const unsigned W = gridDim.x * (blockDim.x >> 6);
+    ScanItem it = scan_decode(a, item);
+    ScanSlot sl = a.slots[it.slot];
+    int lv[NL];
+    float wk[NL];
+    scan_load_levels<NL>(a, sl, lane, lv, wk);
+    unsigned nxt = CROSS ? 0u : item + W;
+    ScanSlot sl_n = sl;
+    if constexpr (!CROSS)
+        if (nxt < a.total_items) sl_n = a.slots[scan_decode(a, nxt).slot];
+    for (;;) {
+        scan_table<KMAX, NL>(a, sl, it.g, lane, lv, wk, tab, kw);
+        // loads for the next item, consumed after this item's rounds
+        int lv_n[NL];
+        float wk_n[NL];
+        unsigned nn = 0;
+        ScanSlot sl_nn = sl_n;
+        if constexpr (CROSS) {
+            unsigned v = 0;
+            if (lane == 0) v = atomicAdd(a.counter, 1u);
+            nxt = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+        } else {
+            if (nxt < a.total_items) scan_load_levels<NL>(a, sl_n, lane, lv_n, wk_n);
+            nn = nxt + W;
+            if (nn < a.total_items) sl_nn = a.slots[scan_decode(a, nn).slot];
+        }
+        scan_mixer(a, sl, it.tile, lane, mix_key, mr, mi);
+        scan_rounds<KMAX, CROSS>(a, sl, it, lane, mr, mi, tab, kw);
         // the next item rewrites tab: keep every lane's reads of this one first
         __builtin_amdgcn_wave_barrier();
+        if (nxt >= a.total_items) break;
+        it = scan_decode(a, nxt);
+        if constexpr (CROSS) {
+            sl = a.slots[it.slot];
+            scan_load_levels<NL>(a, sl, lane, lv, wk);
+        } else {
+            sl = sl_n;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                lv[i] = lv_n[i];
+                wk[i] = wk_n[i];
+            }
+            sl_n = sl_nn;
+            nxt = nn;
+        }
     }
 }
 
@@ -263,28 +384,24 @@ __global__ void zero_counters_kernel(unsigned int *c, int n) {
     if (i < n) c[i] = 0u;
 }
 
-// Register-array sizes of the scan kernel instantiations.
-static const int kBuckets[] = {8, 16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128};
+// Register-array sizes of the scan kernel instantiations: every multiple of
+// 4 up to 64 (an instance pays for at most 3 padding levels, which carry
+// weight 0), then steps of 16.
+static const int kBuckets[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52, 56, 60, 64, 80, 96, 112, 128};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
 constexpr int kScanMaxK = 128;
 
 typedef void (*ScanFn)(ScanArgs);
+template <bool CROSS, int... KS>
+static ScanFn scan_fn_pick(int kmax, std::integer_sequence<int, KS...>) {
+    ScanFn f = nullptr;
+    ((f = (KS == kmax ? scan_kernel<KS, CROSS> : f)), ...);
+    return f;
+}
 template <bool CROSS>
 static ScanFn scan_fn_t(int bucket) {
-    switch (kBuckets[bucket]) {
-        case 8: return scan_kernel<8, CROSS>;
-        case 16: return scan_kernel<16, CROSS>;
-        case 24: return scan_kernel<24, CROSS>;
-        case 32: return scan_kernel<32, CROSS>;
-        case 40: return scan_kernel<40, CROSS>;
-        case 48: return scan_kernel<48, CROSS>;
-        case 56: return scan_kernel<56, CROSS>;
-        case 64: return scan_kernel<64, CROSS>;
-        case 80: return scan_kernel<80, CROSS>;
-        case 96: return scan_kernel<96, CROSS>;
-        case 112: return scan_kernel<112, CROSS>;
-        default: return scan_kernel<128, CROSS>;
-    }
+    return scan_fn_pick<CROSS>(kBuckets[bucket], std::integer_sequence<int, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48,
+                                                                       52, 56, 60, 64, 80, 96, 112, 128>{});
 }
 static ScanFn scan_fn(int bucket, bool cross) { return cross ? scan_fn_t<true>(bucket) : scan_fn_t<false>(bucket); }
 
@@ -429,9 +546,14 @@ int scan_host_tables(int num_inst, const int32_t *n_host, const int32_t *m_host,
         off[i] = (int32_t)out->lev.size();
         tidx[i] = -1;
         const double invN = std::ldexp(1.0, -n_host[i]);
+        // the target level (when occupied) first, then the others in level order
+        if (t <= m_host[i] && h[t]) {
+            tidx[i] = 0;
+            out->lev.push_back(t);
+            out->w.push_back((float)((double)h[t] * invN));
+        }
         for (int k = 0; k <= m_host[i]; ++k)
-            if (h[k]) {
-                if (k == t) tidx[i] = (int32_t)(out->lev.size() - off[i]);
+            if (h[k] && k != t) {
                 out->lev.push_back(k);
                 out->w.push_back((float)((double)h[k] * invN));
             }
