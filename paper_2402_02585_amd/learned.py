@@ -12,6 +12,14 @@ Reference points for judging the network:
   * ``cluster_median``: one fixed pair per p (the median of the training
     labels), i.e. what parameter clustering alone gives;
   * the plain and batched optimizers of ``optim``.
+
+``solve`` is the learned form end to end for one round count: the network's
+pair, local window scans around it, and the plain per-instance optimizer for
+every instance whose result stays below 0.99 of the cluster-median pair.
+The labels come from the batched optimizer, which runs the plain optimizer's
+grid and refines by zoomed grid windows instead of L-BFGS-B: labelling the
+20,000 x 4 training instance-p pairs with the plain optimizer (one device
+call per evaluation, seconds per pair) would take days.
 """
 from __future__ import annotations
 
@@ -139,6 +147,31 @@ def evaluate_pairs(ns, ms, hists, betas, gammas, p: int):
     gm = np.asarray(gammas, dtype=np.float64).reshape(I, 1)
     ps, _ = g.gqaoa_scan_batched(ns, ms, hists, b, gm, [p], with_energy=False)
     return ps.reshape(I).cpu().numpy().astype(np.float64)
+
+
+def solve(model, hists_dev, ns, ms, hists, p: int, median_pair, plain_grid=None, fallback_ratio: float = 0.99):
+    """The learned form for round count p on every instance: the network's
+    pair, refined by ``refine_local``; where the result stays below
+    ``fallback_ratio`` times the P_sol of the fixed cluster-median pair, the
+    plain optimizer (``optim.plain_single_pair`` over ``plain_grid``, default
+    the paper's pi/180 grid) replaces it.
+    Returns dict(beta, gamma, psol, fallback (bool mask), psol_learned (the
+    network's pair alone), psol_median)."""
+    I = len(ns)
+    x = features_for(hists_dev, ns, ms, p)
+    bl, gl = model.angles(x)
+    p_learn = evaluate_pairs(ns, ms, hists, bl, gl, p)
+    b, gm, ps = refine_local(ns, ms, hists, bl, gl, p, start_psol=p_learn)
+    p_med = evaluate_pairs(ns, ms, hists, np.full(I, median_pair[0]), np.full(I, median_pair[1]), p)
+    fb = ps < fallback_ratio * p_med
+    if fb.any():
+        gb, gg = optim.fundamental_grid(*(plain_grid or optim.paper_grid()))
+        for i in np.nonzero(fb)[0]:
+            hdev = hists_dev[i, :ms[i] + 1].contiguous()
+            r = optim.plain_single_pair(int(ns[i]), int(ms[i]), hdev, p, gb, gg)
+            b[i], gm[i], ps[i] = r["beta"], r["gamma"], r["psol"]
+    return {"beta": np.mod(b, 2 * math.pi), "gamma": gm, "psol": ps, "fallback": fb, "psol_learned": p_learn,
+            "psol_median": p_med}
 
 
 def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 0.015), zoom: int = 16,

@@ -1,12 +1,14 @@
 """GPU: the learned angle predictor against the methods without it.
 
 Trains the device MLP on batched-optimizer labels of small seeded instances
-and checks on held-out instances that
+at p in {1, 4, 16, 64} and checks on held-out instances that
   * training reduces the loss,
   * the predicted pairs beat the single fixed cluster-median pair per p (the
     clustering-only baseline) in mean P_sol,
-  * with one local window scan, the learned form reaches >= 0.99 of the
-    batched optimizer's mean P_sol,
+  * the learned form (network pair, local window scans, plain-optimizer
+    fallback: learned.solve) reaches >= 0.99 of the batched optimizer's mean
+    P_sol, and >= 0.99 of the plain per-instance optimizer's on a seeded
+    subsample, at every p including 64,
   * the batched optimizer agrees with the plain per-call optimizer,
   * a checkpoint restores the network and its optimizer exactly, and
     training resumed from it continues bit for bit.
@@ -24,16 +26,16 @@ from paper_2402_02585_amd import instances as inst
 from paper_2402_02585_amd import learned, optim
 
 pytestmark = pytest.mark.gpu
-P_LIST = [1, 4, 16]
+P_LIST = [1, 4, 16, 64]
 
 
 @pytest.fixture(scope="module")
 def trained():
     torch = need_gpu()
-    train = inst.batched_scan_instances(5, 800, 10, 16)
+    train = inst.batched_scan_instances(5, 1600, 10, 16)
     X, Y, lab = learned.training_set(train, P_LIST, grid=(64, 32))
     model = learned.AngleMLP(seed=0)
-    losses = model.train(X, Y, steps=1500, batch=256, lr=2e-3, log_every=500)
+    losses = model.train(X, Y, steps=2000, batch=256, lr=2e-3, log_every=500)
     log(f"losses {losses}")
     test = inst.batched_scan_instances(6, 200, 10, 16)
     ns = [it.n for it in test]
@@ -69,11 +71,35 @@ def test_learned_beats_cluster_median_and_tracks_optimizer(trained):
         bl, gl = model.angles(x)
         p_learn = learned.evaluate_pairs(ns, ms, H, bl, gl, p)
         p_med = learned.evaluate_pairs(ns, ms, H, np.full(len(ns), med[p][0]), np.full(len(ns), med[p][1]), p)
-        _, _, p_ref = learned.refine_local(ns, ms, H, bl, gl, p)
+        sol = learned.solve(model, hd, ns, ms, H, p, med[p], plain_grid=(96, 48))
+        p_ref = sol["psol"]
         log(f"p={p}: learned {p_learn.mean():.4f}  cluster-median {p_med.mean():.4f}  "
-            f"learned+window {p_ref.mean():.4f}  optimizer {opt_p[:, q].mean():.4f}")
+            f"learned form {p_ref.mean():.4f} ({int(sol['fallback'].sum())} fallbacks)  "
+            f"optimizer {opt_p[:, q].mean():.4f}")
         assert p_learn.mean() > p_med.mean()
         assert p_ref.mean() >= 0.99 * opt_p[:, q].mean()
+        # every instance's result is the P_sol of its returned pair
+        for i in (0, 7, 50):
+            ref = psol_single_pair_hist(H[i, :ms[i] + 1], sol["beta"][i], sol["gamma"][i], p)
+            assert abs(ref - p_ref[i]) < 1e-5
+
+
+def test_learned_form_within_one_percent_of_plain_optimizer(trained):
+    """The judge named for the learned form: the plain per-instance optimizer
+    (a grid, one device call per evaluation, then L-BFGS-B), on a seeded
+    subsample, at every p including 64."""
+    torch = trained["torch"]
+    model, lab = trained["model"], trained["lab"]
+    ns, ms, H, hd = trained["ns"], trained["ms"], trained["hists"], trained["hists_dev"]
+    med = learned.cluster_median(lab, P_LIST)
+    sub = np.random.Generator(np.random.PCG64(11)).choice(len(ns), 5, replace=False)
+    gb, gg = optim.fundamental_grid(96, 48)
+    for p in P_LIST:
+        sol = learned.solve(model, hd, ns, ms, H, p, med[p], plain_grid=(96, 48))
+        plain = [optim.plain_single_pair(ns[i], ms[i], hd[i, :ms[i] + 1].contiguous(), p, gb, gg)["psol"]
+                 for i in sub]
+        log(f"p={p}: learned form {sol['psol'][sub].mean():.4f}  plain {np.mean(plain):.4f}")
+        assert sol["psol"][sub].mean() >= 0.99 * np.mean(plain), (p, sol["psol"][sub], plain)
 
 
 def test_plain_optimizer_agrees_with_batched():
