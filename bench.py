@@ -58,49 +58,44 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_sha() -> str:
+def source_sha(*files) -> str:
+    """Hash of kernel sources (csrc file names), stored beside counter summaries."""
     h = hashlib.sha256()
-    for f in ("sv.hip", "internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2402_02585_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch of the round kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "sv_round_c64_n28_counters.md")
-    if not os.path.exists(path):
-        return None
-    text = open(path).read()
-    m = re.search(r"```json\n(.*?)\n```", text, re.S)
-    if not m:
-        return None
-    d = json.loads(m.group(1))
-    if d.get("source_sha") != kernel_source_sha():
-        return None
-    return d.get("hbm_bytes_per_launch")
-
-
-def scan_source_sha() -> str:
-    h = hashlib.sha256()
-    for f in ("hist.hip", "batch.h", "internal.h"):
-        with open(os.path.join(ROOT, "paper_2402_02585_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def read_scan_counters():
-    """Issued VALU lane-operations per scan replay from the committed counter
-    summary, or None when the scan kernel's source changed since."""
-    path = os.path.join(ROOT, "profiles", "scan_c3_counters_and_trace.md")
+def profile_json(name: str, *files):
+    """The JSON block of a committed counter summary under profiles/, or None
+    when it is missing or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     d = json.loads(m.group(1))
-    return d.get("valu_lane_ops_per_replay") if d.get("source_sha") == scan_source_sha() else None
+    return d if d.get("source_sha") == source_sha(*files) else None
+
+
+def read_traffic():
+    """HBM bytes per launch of the round kernel (counters), or None."""
+    d = profile_json("sv_round_c64_n28_counters.md", "sv.hip", "internal.h")
+    return None if d is None else d.get("hbm_bytes_per_launch")
+
+
+def read_scan_counters():
+    """Issued VALU lane-operations per scan replay (counters), or None."""
+    d = profile_json("scan_c3_counters_and_trace.md", "hist.hip", "batch.h", "internal.h")
+    return None if d is None else d.get("valu_lane_ops_per_replay")
+
+
+def read_cost_table_counters():
+    """Issued VALU lane-operations per cost-table launch (counters), or None."""
+    d = profile_json("cost_table_n28_counters.md", "cost_table.hip", "cost_bits.h", "internal.h")
+    return None if d is None else d.get("valu_lane_ops_per_launch")
 
 
 def host_info():
@@ -940,8 +935,13 @@ def main():
                 "kernel": "sv_forward_kernel<float, true, true, 2, 4, 1, false>", "avg_launch_ms": avg_round_ms,
                 "launches": args.steps * P_ROUNDS, "launches_timed": round_cnt,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
-    cost_table = {"avg_launch_ms": ct_ms / max(ct_cnt, 1),
-                  "clause_evals_per_s": M_CLAUSES * N / (ct_ms / max(ct_cnt, 1) * 1e-3)}
+    ct_avg = ct_ms / max(ct_cnt, 1)
+    ct_ops = read_cost_table_counters()
+    cost_table = {"avg_launch_ms": ct_avg, "clause_evals_per_s": M_CLAUSES * N / (ct_avg * 1e-3),
+                  "valu_lane_ops_per_launch": ct_ops,
+                  "issued_frac_of_valu_peak": None if ct_ops is None else ct_ops / (ct_avg * 1e-3) / VALU_LANE_OPS_PEAK,
+                  "note": "issued lane-operations from the committed counter summary "
+                          "(profiles/cost_table_n28_counters.md; null once the kernel changes)"}
 
     out = {
         "metric": "amplitude-rounds/s (n=28,p=64) + batched instance-angle evals/s vs plain, same GPU",
