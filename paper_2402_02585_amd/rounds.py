@@ -113,7 +113,8 @@ def _argbest(v):
     return g.gqaoa_row_best(v, g.ROW_ARGMAX_F32, with_value=False)[0].cpu().numpy()
 
 
-def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(120, 61), p_floor: int = 1):
+def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(120, 61), p_floor: int = 1,
+                        progress=None):
     """Least full-G-QAOA rounds reaching S for every instance.
 
     For a candidate p the seed is the best single pair of a (beta, gamma) grid
@@ -125,7 +126,8 @@ def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(1
     end. Instances with p_single = 0 (not reached) are skipped.
     Returns (p_full[I] (0 where skipped), betas [I, p_max], gammas [I, p_max],
     psol[I], optimized[I]) at p_full; optimized[i] is False where no p below
-    p_single reached S (then the angles are zero and psol NaN)."""
+    p_single reached S (then the angles are zero and psol NaN).
+    progress(step, candidates, reached) is called after every bisection step."""
     hists = np.asarray(hists)
     ns = np.asarray(ns, dtype=np.int32)
     ms = np.asarray(ms, dtype=np.int32)
@@ -139,10 +141,12 @@ def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(1
     psol = np.full(I, np.nan)
     opt = np.zeros(I, dtype=bool)
     gb, gg = optim.fundamental_grid(*grid)
+    step = 0
     while True:
         act = np.nonzero((hi > 0) & (lo < hi))[0]
         if act.size == 0:
             break
+        step += 1
         mid = (lo[act] + hi[act]) // 2
         b0, g0 = _best_pairs_at(ns[act], ms[act], hists[act], tg[act], mid, gb, gg)
         bs, gs, P = optim.full_gqaoa_batched(ns[act], ms[act], hists[act], mid, b0, g0, tg[act])
@@ -158,6 +162,8 @@ def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(1
                 opt[i] = True
             else:
                 lo[i] = mid[k] + 1
+        if progress is not None:
+            progress(step, int(act.size), int(ok.sum()))
     return hi, betas, gammas, psol, opt
 
 

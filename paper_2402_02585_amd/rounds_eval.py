@@ -169,8 +169,9 @@ def main(argv=None):
         if pool.size:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            pf, _, _, Pf, okf = rounds.full_rounds_batched(ns[pool], ms[pool], H[pool], 0.5, p_half[pool],
-                                                           targets=targets[pool], grid=tuple(a.full_grid))
+            pf, _, _, Pf, okf = rounds.full_rounds_batched(
+                ns[pool], ms[pool], H[pool], 0.5, p_half[pool], targets=targets[pool], grid=tuple(a.full_grid),
+                progress=lambda st, c, r: log(f"{kind} full G-QAOA bisection step {st}: {c} candidates, {r} reach S"))
             t_full = time.perf_counter() - t0
             full = [{"n": int(ns[i]), "m": int(ms[i]), "P": float(P[i]), "p_single": int(p_half[i]),
                      "p_full": int(pf[k])} for k, i in enumerate(pool)]
