@@ -191,6 +191,9 @@ def main(argv=None):
             log(f"{kind} full G-QAOA: {len(full)} instances, slope {rec.get('fit_slope', float('nan')):.3f}, "
                 f"mean p_full/p_single {rec['mean_ratio_full_to_single']:.3f}, {t_full:.1f} s")
         res[kind] = entry
+        if a.out:   # keep what is done so far
+            with open(a.out, "w") as f:
+                f.write(json.dumps(res, default=float) + "\n")
     out = json.dumps(res, default=float)
     print(out, flush=True)
     if a.out:
