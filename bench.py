@@ -586,10 +586,12 @@ def xqaoa_leg(torch, g, inst, it, reps: int = 3):
     g.gqaoa_profile_enable(False)
     pass_ms, pass_cnt = g.gqaoa_profile_read("x_pass_c64")
     passes = pass_cnt // reps
-    # groups at n = 28: qubits 0-11, 12-19, 20-27; a round is two passes. The
-    # first pass starts from |s> (writes 8 B, reads 1 B of cost), every other
-    # pass reads and writes 16 B, and the p later readout passes (p - 1 fused
-    # round boundaries and the last pass) read 1 B of cost
+    # groups at n = 28: qubits 0-11, 12-19, 20-27, taken in the order 1 0 2,
+    # then 2 0 1; a round is two passes (group 0 mixing only, and a fused
+    # boundary pass). The first pass starts from |s> (writes 8 B, reads 1 B of
+    # cost), every other pass reads and writes 16 B, and the p later readout
+    # passes (p - 1 fused round boundaries and the last pass) read 1 B of cost;
+    # the two cost copies of a call (2 B per amplitude each) are not passes
     pass_bytes = N * (9 + (passes - 1) * 16 + p * 1)
     del psi, ws, cost
     torch.cuda.empty_cache()

@@ -16,14 +16,24 @@
 //   * each thread holds E = 2^(T-8) amplitudes of a tile in registers and
 //     applies the butterflies of the register-resident bits there; the tile
 //     is re-distributed through LDS to bring the next bits into registers
-//     (two to four exchanges per pass, never a butterfly in LDS);
-//   * the group order alternates between rounds (0..g-1, then g-1..0, ...),
+//     (one to four exchanges per pass, never a butterfly in LDS). For group 0
+//     and the full groups the chunk plan is a template parameter, so the
+//     exchanges use fixed LDS offsets and the stages run without branches;
+//   * the group order alternates between rounds (o_0..o_{g-1}, then back),
 //     so the last pass of a round and the first of the next touch the same
 //     group and are fused: mixers of round j, readout of the state after
 //     round j, phase of round j+1, mixers of round j+1. A round then costs
-//     g - 1 passes (two at n = 28, complex64) instead of g.
+//     g - 1 passes (two at n = 28, complex64) instead of g. With three or
+//     more groups, group 0 (the most qubits, contiguous tiles) goes second,
+//     so it takes a mixing-only pass and the fused passes, which apply two
+//     mixers, fall on smaller groups.
 // The phase and readouts need C(z) in tile order: group 0 reads the cost
-// table itself, the last group a tile-ordered copy built once per call.
+// table itself, the other two groups that take the fused passes read
+// tile-ordered copies built once per call. After a group's forward mixers
+// each thread's costs are consecutive in either, so the streaming passes
+// read them with one vector load per tile, issued with the next tile's state
+// loads. The first pass of a call starts in that layout (|s> is the same in
+// every layout) and runs its mixers backward.
 // Up to T qubits the whole state is one tile, evolved by a simple LDS kernel.
 #include "internal.h"
 
@@ -180,6 +190,62 @@ struct XPlan {
     int mask[kXMaxChunks];
 };
 
+// The chunks for the group on tile bits [mlo, TB): from the top register
+// position down by R at a time, never below mlo, each taking the group's bits
+// it covers that no earlier chunk took.
+constexpr XPlan x_plan(int TB, int R, int mlo) {
+    XPlan pl{};
+    uint32_t done = 0;
+    const uint32_t want = ((1u << TB) - 1u) & ~((1u << mlo) - 1u);
+    int rb = TB - R;
+    for (;;) {
+        int m = 0;
+        for (int r = 0; r < R; ++r) {
+            const int bit = rb + r;
+            if (bit >= mlo && bit < TB && !((done >> bit) & 1u)) {
+                m |= 1 << r;
+                done |= 1u << bit;
+            }
+        }
+        pl.rb[pl.nchunks] = rb;
+        pl.mask[pl.nchunks] = m;
+        ++pl.nchunks;
+        if (done == want) break;
+        rb = rb - R > mlo ? rb - R : mlo;
+    }
+    return pl;
+}
+
+// Group 0 in a pass that only mixes: the loaded layout's chunk first, then
+// from tile bit 0 upwards, so that the last chunk is the highest one below it
+// and the tile can be stored from there (lanes over runs of >= 128 bytes)
+// without an exchange back.
+constexpr XPlan x_plan_mix0(int TB, int R) {
+    XPlan pl{};
+    const int rb0 = TB - R;
+    pl.rb[0] = rb0;
+    pl.mask[0] = (1 << R) - 1;
+    pl.nchunks = 1;
+    uint32_t done = ((1u << R) - 1u) << rb0;
+    for (int lo = 0; done != (1u << TB) - 1u; lo += R) {
+        const int rb = lo + R <= rb0 ? lo : rb0 - R;
+        int m = 0;
+        for (int r = 0; r < R; ++r)
+            if (!((done >> (rb + r)) & 1u)) {
+                m |= 1 << r;
+                done |= 1u << (rb + r);
+            }
+        pl.rb[pl.nchunks] = rb;
+        pl.mask[pl.nchunks] = m;
+        ++pl.nchunks;
+    }
+    return pl;
+}
+// The compile-time plans: MLO >= 0 a group on tile bits [MLO, TB); kXPlanMix0
+// group 0's plan for a mixing-only pass.
+constexpr int kXPlanMix0 = 64;
+constexpr XPlan x_plan_id(int TB, int R, int id) { return id == kXPlanMix0 ? x_plan_mix0(TB, R) : x_plan(TB, R, id); }
+
 enum : int {
     XOP_PRE = 1,     // readout, then phase lut_a, before mixer A (first pass)
     XOP_MIX_A = 2,   // mixer A (c_a, s_a)
@@ -189,7 +255,8 @@ enum : int {
 
 struct XPassArgs {
     void *psi;
-    const uint8_t *cost;   // C in tile order: tile t, element e at (t << T) + e
+    const uint8_t *cost;   // C of tile t at (t << T), in the order after the group's forward mixers
+    const uint8_t *cost_z; // the cost table (z order), for the readout-only pass
     int n, mlo, q0;        // tile bits [0, mlo) = z bits [0, mlo); [mlo, T) = z bits [q0, ...)
     int contig;            // tile bits that are consecutive in z (T for group 0, else mlo)
     uint64_t ntiles;
@@ -215,25 +282,100 @@ __device__ __forceinline__ void x_store(XC<T> a, XC<T> *p) {
     __builtin_nontemporal_store(v2{a.re, a.im}, reinterpret_cast<v2 *>(p));
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void x_exchange(XC<T> (&v)[1 << R], XC<T> *lds, int from, int to) {
-    const int t = threadIdx.x;
+// The LDS slot of register element i of thread t in layout rb splits into a
+// per-thread part and a per-element part: the bits of the element index that
+// come from t and from i are disjoint, so the pad term e >> 4 splits too.
+// With rb fixed at compile time the element part is an instruction's
+// immediate offset.
+template <int R>
+__device__ __forceinline__ int x_slot_t(int t, int rb) {
+    const int tp = (t & ((1 << rb) - 1)) | ((t >> rb) << (rb + R));
+    return tp + (tp >> 4);
+}
+constexpr int x_slot_i(int i, int rb) { return (i << rb) + ((i << rb) >> 4); }
+
+template <typename T>
+struct XV2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+
+// Write (PUT) or read the register elements in layout RB.
+template <typename T, int R, bool PUT, int RB>
+__device__ __forceinline__ void x_lds_at(XC<T> (&v)[1 << R], XC<T> *lds) {
+    typedef typename XV2<T>::type v2;
+    v2 *p = reinterpret_cast<v2 *>(lds) + x_slot_t<R>(threadIdx.x, RB);
 #pragma unroll
-    for (int i = 0; i < (1 << R); ++i) lds[x_phys(x_elem(t, i, from, R))] = v[i];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < (1 << R); ++i) v[i] = lds[x_phys(x_elem(t, i, to, R))];
-    __syncthreads();
+    for (int i = 0; i < (1 << R); ++i) {
+        if constexpr (PUT) {
+            p[x_slot_i(i, RB)] = v2{v[i].re, v[i].im};
+        } else {
+            const v2 w = p[x_slot_i(i, RB)];
+            v[i] = XC<T>{w.x, w.y};
+        }
+    }
+}
+// The same for the runtime rb of a plan (uniform across the block, 0 <= rb <= T - R).
+template <typename T, int R, bool PUT, int RB = 0>
+__device__ __forceinline__ void x_lds_move(XC<T> (&v)[1 << R], XC<T> *lds, int rb) {
+    if constexpr (RB <= kXThreadBits) {
+        if (rb == RB) x_lds_at<T, R, PUT, RB>(v, lds);
+        else x_lds_move<T, R, PUT, RB + 1>(v, lds, rb);
+    }
 }
 
 template <typename T, int R>
-__device__ __forceinline__ void x_stages(XC<T> (&v)[1 << R], int mask, T c, T s) {
+__device__ __forceinline__ void x_exchange(XC<T> (&v)[1 << R], XC<T> *lds, int from, int to) {
+    x_lds_move<T, R, true>(v, lds, from);
+    __syncthreads();
+    x_lds_move<T, R, false>(v, lds, to);
+    __syncthreads();
+}
+template <typename T, int R, int FROM, int TO>
+__device__ __forceinline__ void x_exchange_c(XC<T> (&v)[1 << R], XC<T> *lds) {
+    x_lds_at<T, R, true, FROM>(v, lds);
+    __syncthreads();
+    x_lds_at<T, R, false, TO>(v, lds);
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T x_fma(T a, T b, T c);
+template <>
+__device__ __forceinline__ float x_fma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double x_fma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// xrot as one multiply and one accumulate per output, with -s in a register
+// of its own, so that every instruction is a two-operand form on vector
+// registers (these issue at twice the rate of forms with a scalar operand).
+template <typename T>
+__device__ __forceinline__ void xrot2(XC<T> &a, XC<T> &b, T c, T s, T ns) {
+    const XC<T> na{x_fma(s, b.im, c * a.re), x_fma(ns, b.re, c * a.im)};
+    const XC<T> nb{x_fma(s, a.im, c * b.re), x_fma(ns, a.re, c * b.im)};
+    a = na;
+    b = nb;
+}
+
+// cos and sin of a mixer angle and -sin, in vector registers.
+template <typename T>
+struct XF {
+    T c, s, ns;
+};
+template <typename T>
+__device__ __forceinline__ XF<T> x_factors(T c, T s) {
+    T cv = c, sv = s, nsv = -s;
+    asm volatile("" : "+v"(cv), "+v"(sv), "+v"(nsv));
+    return XF<T>{cv, sv, nsv};
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void x_stages(XC<T> (&v)[1 << R], int mask, const XF<T> &f) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!((mask >> r) & 1)) continue;  // uniform across the block
 #pragma unroll
         for (int i = 0; i < (1 << R); ++i)
-            if (!((i >> r) & 1)) xrot(v[i], v[i | (1 << r)], c, s);
+            if (!((i >> r) & 1)) xrot2(v[i], v[i | (1 << r)], f.c, f.s, f.ns);
     }
 }
 
@@ -241,14 +383,40 @@ __device__ __forceinline__ void x_stages(XC<T> (&v)[1 << R], int mask, T c, T s)
 // the last chunk); rb is the register layout on entry and on exit.
 template <typename T, int R>
 __device__ __forceinline__ void x_mix(XC<T> (&v)[1 << R], XC<T> *lds, const XPlan &pl, bool forward, int &rb,
-                                      T c, T s) {
+                                      const XF<T> &f) {
     for (int k = 0; k < pl.nchunks; ++k) {
         const int kk = forward ? k : pl.nchunks - 1 - k;
         if (pl.rb[kk] != rb) {
             x_exchange<T, R>(v, lds, rb, pl.rb[kk]);
             rb = pl.rb[kk];
         }
-        x_stages<T, R>(v, pl.mask[kk], c, s);
+        x_stages<T, R>(v, pl.mask[kk], f);
+    }
+}
+
+// The same with the group's plan fixed at compile time (group on tile bits
+// [MLO, TB)): exchanges at fixed layouts, no branches between stages.
+template <typename T, int R, int MASK>
+__device__ __forceinline__ void x_stages_c(XC<T> (&v)[1 << R], const XF<T> &f) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if ((MASK >> r) & 1) {
+#pragma unroll
+            for (int i = 0; i < (1 << R); ++i)
+                if (!((i >> r) & 1)) xrot2(v[i], v[i | (1 << r)], f.c, f.s, f.ns);
+        }
+    }
+}
+template <typename T, int R, int TB, int PLAN, bool FWD, int K = 0>
+__device__ __forceinline__ void x_mix_c(XC<T> (&v)[1 << R], XC<T> *lds, const XF<T> &f) {
+    constexpr XPlan P = x_plan_id(TB, R, PLAN);
+    if constexpr (K < P.nchunks) {
+        constexpr int kk = FWD ? K : P.nchunks - 1 - K;
+        constexpr int from = K == 0 ? (FWD ? P.rb[0] : P.rb[P.nchunks - 1])
+                                    : (FWD ? P.rb[K - 1] : P.rb[P.nchunks - K]);
+        if constexpr (P.rb[kk] != from) x_exchange_c<T, R, from, P.rb[kk]>(v, lds);
+        x_stages_c<T, R, P.mask[kk]>(v, f);
+        x_mix_c<T, R, TB, PLAN, FWD, K + 1>(v, lds, f);
     }
 }
 
@@ -270,13 +438,42 @@ __device__ __forceinline__ void x_readout(const XC<T> (&v)[1 << R], const uint32
     aN += (double)sN;
 }
 
+// The 2^R cost bytes of one thread's elements in the layout after a group's
+// forward mixers (register bits at the plan's last chunk): consecutive in
+// the cost array for group 0 (z order, last chunk at bit 0) and in the last
+// group's tile-ordered copy, which is written in that order.
+template <int R>
+struct XCostVec {
+    typedef uint32_t type __attribute__((ext_vector_type((1 << R) / 4)));
+};
+template <int R>
+__device__ __forceinline__ typename XCostVec<R>::type x_load_costs(const uint8_t *ct) {
+    return *reinterpret_cast<const typename XCostVec<R>::type *>(ct + ((size_t)threadIdx.x << R));
+}
+template <int R>
+__device__ __forceinline__ void x_unpack_costs(const typename XCostVec<R>::type &w, uint32_t (&cz)[1 << R]) {
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) cz[i] = (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+}
+
 // OPS: the XOP_* flags of the pass, fixed at compile time so that a pass
-// that only mixes carries no readout, cost or phase state.
-template <typename T, int OPS>
+// that only mixes carries no readout, cost or phase state. MLO >= 0: the
+// group is on tile bits [MLO, T) and its plan is fixed at compile time
+// (group 0 and the full groups of 8 qubits); MLO = -1: any group, from the
+// plan in the arguments.
+template <typename T, int OPS, int MLO>
 __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     constexpr int TB = XCfg<T>::TB, R = XCfg<T>::R, E = 1 << R;
     static_assert(TB - R == kXThreadBits, "one tile per block of 256 threads");
-    extern __shared__ unsigned char smem[];
+    static_assert(E >= 8, "costs are read as whole 32-bit words");
+    // Passes that start with the mixers always read the state and keep the
+    // next tile's loads (and its costs, when the pass reads them) in flight
+    // while this tile is mixed and stored.
+    constexpr bool kStream = (OPS & XOP_MIX_A) != 0 && (OPS & XOP_PRE) == 0;
+    constexpr bool kReadout = (OPS & (XOP_PRE | XOP_MID | XOP_POST)) != 0;
+    constexpr int kPlan = OPS == XOP_MIX_A && MLO == 0 ? kXPlanMix0 : MLO >= 0 ? MLO : 0;
+    constexpr XPlan kP = x_plan_id(TB, R, kPlan);
+    extern __shared__ __align__(16) unsigned char smem[];
     XC<T> *lds = reinterpret_cast<XC<T> *>(smem);
     __shared__ XC<T> lut_s[2][256];
     __shared__ double red_s[3 * kXThreads / kWave];
@@ -286,97 +483,127 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     }
     __syncthreads();
     const int t = threadIdx.x;
-    const int rb0 = TB - R;
-    const T ca = (T)a.ca, sa = (T)a.sa, cb = (T)a.cb, sb = (T)a.sb;
+    constexpr int rb0 = TB - R;
     constexpr bool store = (OPS & (XOP_MIX_A | XOP_MID)) != 0;
     XC<T> *psi = reinterpret_cast<XC<T> *>(a.psi);
-    const int lowbits = a.q0 - a.mlo;         // z bits mlo..q0-1 come from the tile index
-    const int hishift = a.q0 + TB - a.mlo;    // z bits above the group
-    const uint32_t cmask = (1u << a.mlo) - 1u;
+    const int mlo = MLO >= 0 ? MLO : a.mlo;
+    const int contig = MLO == 0 ? TB : MLO > 0 ? MLO : a.contig;
+    const int lowbits = a.q0 - mlo;         // z bits mlo..q0-1 come from the tile index
+    const int hishift = a.q0 + TB - mlo;    // z bits above the group
+    const uint32_t cmask = (1u << mlo) - 1u;
     double aP = 0.0, aE = 0.0, aN = 0.0;
     // z of tile element e is base | zmap(e); zmap is a bit placement, so for
     // e = (thread part) | (register part) it splits into a per-thread offset
     // and a per-register offset that is uniform across the block.
-    auto zmap = [&](uint32_t e) -> uint64_t { return (uint64_t)(e & cmask) | ((uint64_t)(e >> a.mlo) << a.q0); };
+    auto zmap = [&](uint32_t e) -> uint64_t { return (uint64_t)(e & cmask) | ((uint64_t)(e >> mlo) << a.q0); };
     const uint64_t zt0 = zmap((uint32_t)x_elem(t, 0, rb0, R));
     auto tile_base = [&](uint64_t tile) -> uint64_t {
-        return ((tile & ((1ull << lowbits) - 1)) << a.mlo) | ((tile >> lowbits) << hishift);
+        return ((tile & ((1ull << lowbits) - 1)) << mlo) | ((tile >> lowbits) << hishift);
     };
     auto load_tile = [&](uint64_t tile, XC<T>(&w)[E]) {
         const XC<T> *src = psi + tile_base(tile) + zt0;
 #pragma unroll
         for (int i = 0; i < E; ++i) w[i] = x_load(src + zmap((uint32_t)i << rb0));
     };
+    auto store_tile = [&](uint64_t tile, XC<T>(&w)[E], int rb) {
+        // store from a layout whose lanes cover runs of >= 128 bytes
+        if ((int)sizeof(XC<T>) << (rb < contig ? rb : contig) < 128) {
+            x_exchange<T, R>(w, lds, rb, rb0);
+            rb = rb0;
+        }
+        XC<T> *dst = psi + tile_base(tile) + zmap((uint32_t)x_elem(t, 0, rb, R));
+#pragma unroll
+        for (int i = 0; i < E; ++i) x_store(w[i], dst + zmap((uint32_t)i << rb));
+    };
+    // mixers forward from rb0 or backward to it; rb: the layout on exit
+    auto mix = [&](XC<T>(&w)[E], bool forward, int &rb, const XF<T> &f) {
+        if constexpr (MLO >= 0) {
+            if (forward) {
+                x_mix_c<T, R, TB, kPlan, true>(w, lds, f);
+                rb = kP.rb[kP.nchunks - 1];
+            } else {
+                x_mix_c<T, R, TB, kPlan, false>(w, lds, f);
+                rb = rb0;
+            }
+        } else {
+            x_mix<T, R>(w, lds, a.plan, forward, rb, f);
+        }
+    };
     XC<T> v[E];
-    if constexpr (OPS == XOP_MIX_A) {
-        // Mixing only: light enough in registers to keep the next tile's
-        // loads in flight while this tile is mixed and stored.
+    uint32_t cz[E];
+    if constexpr (kStream) {
+        constexpr bool kCosts = (OPS & (XOP_MID | XOP_POST)) != 0;
+        typedef typename XCostVec<R>::type CV;
         XC<T> nxt[E];
+        CV cn{};
         uint64_t tile = blockIdx.x;
-        if (tile < a.ntiles) load_tile(tile, nxt);
+        if (tile < a.ntiles) {
+            load_tile(tile, nxt);
+            if constexpr (kCosts) cn = x_load_costs<R>(a.cost + (tile << TB));
+        }
         for (; tile < a.ntiles; tile += gridDim.x) {
 #pragma unroll
             for (int i = 0; i < E; ++i) v[i] = nxt[i];
-            if (tile + gridDim.x < a.ntiles) load_tile(tile + gridDim.x, nxt);
+            const CV cw = cn;
+            if (tile + gridDim.x < a.ntiles) {
+                load_tile(tile + gridDim.x, nxt);
+                if constexpr (kCosts) cn = x_load_costs<R>(a.cost + ((tile + gridDim.x) << TB));
+            }
             int rb = rb0;
-            x_mix<T, R>(v, lds, a.plan, true, rb, ca, sa);
-            if ((int)sizeof(XC<T>) << (rb < a.contig ? rb : a.contig) < 128) {
-                x_exchange<T, R>(v, lds, rb, rb0);
-                rb = rb0;
+            mix(v, true, rb, x_factors((T)a.ca, (T)a.sa));
+            if constexpr (kCosts) {
+                x_unpack_costs<R>(cw, cz);
+                x_readout<T, R>(v, cz, aP, aE, aN, a.target);
             }
-            XC<T> *dst = psi + tile_base(tile) + zmap((uint32_t)x_elem(t, 0, rb, R));
+            if constexpr ((OPS & XOP_MID) != 0) {
 #pragma unroll
-            for (int i = 0; i < E; ++i) x_store(v[i], dst + zmap((uint32_t)i << rb));
-        }
-        return;
-    }
-    for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        XC<T> *tp = psi + tile_base(tile);
-        const uint8_t *ct = a.cost + (tile << TB);
-        uint32_t cz[E];
-        // C of this tile's elements in register layout rb (read where used)
-        auto load_cost = [&](int rb) {
-            const uint8_t *cc = ct + x_elem(t, 0, rb, R);
-#pragma unroll
-            for (int i = 0; i < E; ++i) cz[i] = cc[i << rb];
-        };
-        if (a.init_uniform) {
-#pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = XC<T>{(T)a.init_amp, (T)0};
-        } else {
-            load_tile(tile, v);
-        }
-        int rb = rb0;
-        if constexpr ((OPS & XOP_PRE) != 0) {
-            load_cost(rb);
-            x_readout<T, R>(v, cz, aP, aE, aN, a.target);
-#pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = xmul(lut_s[0][cz[i]], v[i]);
-        }
-        if constexpr ((OPS & XOP_MIX_A) != 0) x_mix<T, R>(v, lds, a.plan, true, rb, ca, sa);
-        if constexpr ((OPS & XOP_MID) != 0) {
-            load_cost(rb);
-            x_readout<T, R>(v, cz, aP, aE, aN, a.target);
-#pragma unroll
-            for (int i = 0; i < E; ++i) v[i] = xmul(lut_s[1][cz[i]], v[i]);
-            x_mix<T, R>(v, lds, a.plan, false, rb, cb, sb);
-        }
-        if constexpr ((OPS & XOP_POST) != 0) {
-            load_cost(rb);
-            x_readout<T, R>(v, cz, aP, aE, aN, a.target);
-        }
-        if constexpr (store) {
-            // store from a layout whose lanes cover runs of >= 128 bytes
-            if ((int)sizeof(XC<T>) << (rb < a.contig ? rb : a.contig) < 128) {
-                x_exchange<T, R>(v, lds, rb, rb0);
-                rb = rb0;
+                for (int i = 0; i < E; ++i) v[i] = xmul(lut_s[1][cz[i]], v[i]);
+                mix(v, false, rb, x_factors((T)a.cb, (T)a.sb));
             }
-            XC<T> *dst = tp + zmap((uint32_t)x_elem(t, 0, rb, R));
+            store_tile(tile, v, rb);
+        }
+    } else {
+        // The first pass of a call: the tile is taken in the layout its
+        // group's costs are stored in (after the forward mixers; |s> needs no
+        // load, a given state one exchange), read out and phased there, and
+        // mixed backward into the load layout. The readout-only pass (p = 0)
+        // gathers its costs from the cost table.
+        static_assert((OPS & XOP_PRE) == 0 || (OPS & XOP_MID) == 0, "the first pass is no boundary pass");
+        const int rb_end = MLO >= 0 ? kP.rb[kP.nchunks - 1] : a.plan.rb[a.plan.nchunks - 1];
+        for (uint64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+            auto load_cost = [&](int rb) {
+                const uint8_t *cc = a.cost_z + tile_base(tile) + zmap((uint32_t)x_elem(t, 0, rb, R));
 #pragma unroll
-            for (int i = 0; i < E; ++i) x_store(v[i], dst + zmap((uint32_t)i << rb));
+                for (int i = 0; i < E; ++i) cz[i] = cc[zmap((uint32_t)i << rb)];
+            };
+            int rb = rb0;
+            if constexpr ((OPS & XOP_PRE) != 0) {
+                const typename XCostVec<R>::type cw = x_load_costs<R>(a.cost + (tile << TB));
+                if (a.init_uniform) {
+#pragma unroll
+                    for (int i = 0; i < E; ++i) v[i] = XC<T>{(T)a.init_amp, (T)0};
+                } else {
+                    load_tile(tile, v);
+                    if (rb_end != rb0) x_exchange<T, R>(v, lds, rb0, rb_end);
+                }
+                rb = rb_end;
+                x_unpack_costs<R>(cw, cz);
+                x_readout<T, R>(v, cz, aP, aE, aN, a.target);
+#pragma unroll
+                for (int i = 0; i < E; ++i) v[i] = xmul(lut_s[0][cz[i]], v[i]);
+                if constexpr ((OPS & XOP_MIX_A) != 0) mix(v, false, rb, x_factors((T)a.ca, (T)a.sa));
+            } else {
+                load_tile(tile, v);
+                if constexpr ((OPS & XOP_MIX_A) != 0) mix(v, true, rb, x_factors((T)a.ca, (T)a.sa));
+            }
+            if constexpr ((OPS & XOP_POST) != 0) {
+                load_cost(rb);
+                x_readout<T, R>(v, cz, aP, aE, aN, a.target);
+            }
+            if constexpr (store) store_tile(tile, v, rb);
         }
     }
-    if constexpr ((OPS & (XOP_PRE | XOP_MID | XOP_POST)) != 0) {
+    if constexpr (kReadout) {
         double r[3] = {aP, aE, aN};
         block_sum<3, kXThreads>(r, red_s);
         if (threadIdx.x == 0)
@@ -385,17 +612,44 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     }
 }
 
-// Tile-ordered copy of the cost table for one group: out[(t << T) + e] = C(z(t, e)).
+// Tile-ordered copy of the cost table for one high group (tile bits [0, mlo)
+// = z bits [0, mlo), mlo >= 3), each tile in the order its streaming passes
+// read it after the forward mixers: thread t's 2^R costs are consecutive,
+// out[(tile << tb) + (t << R) + i] = C(z(tile, e)) with e = x_elem(t, i, rb, R).
+// A block takes kXCopyTiles consecutive tiles: their rows are runs of 2^mlo
+// bytes of the table, adjacent for adjacent tiles while the tile index's low
+// bits are z bits, so lanes read consecutive 8-byte pieces; the tiles are
+// staged in LDS in element order and each thread then gathers its 2^R bytes
+// and writes them with one vector store.
+constexpr int kXCopyTilesLog2 = 3;
 __global__ void __launch_bounds__(256) x_cost_tiles_kernel(const uint8_t *__restrict__ cost, uint8_t *__restrict__ out,
-                                                          int tb, int mlo, int q0, uint64_t total) {
+                                                          int tb, int mlo, int q0, int rb, int R, uint64_t ntiles) {
+    __shared__ __align__(16) uint8_t st[(1 << kXCopyTilesLog2) << 12];
     const int lowbits = q0 - mlo, hishift = q0 + tb - mlo;
-    const uint32_t cmask = (1u << mlo) - 1u;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t tile = k >> tb;
-        const uint32_t e = (uint32_t)(k & ((1ull << tb) - 1));
-        const uint64_t base = ((tile & ((1ull << lowbits) - 1)) << mlo) | ((tile >> lowbits) << hishift);
-        out[k] = cost[base | (e & cmask) | ((uint64_t)(e >> mlo) << q0)];
+    const int ntl = ntiles < (1ull << kXCopyTilesLog2) ? __builtin_ctzll(ntiles) : kXCopyTilesLog2;
+    const int runl = mlo - 3;  // 8-byte pieces per row run, log2
+    const int E = 1 << R;
+    for (uint64_t tile0 = (uint64_t)blockIdx.x << ntl; tile0 < ntiles; tile0 += (uint64_t)gridDim.x << ntl) {
+        for (int k = threadIdx.x; k < (1 << (ntl + tb - 3)); k += blockDim.x) {
+            const int pb = k & ((1 << runl) - 1);
+            const int j = (k >> runl) & ((1 << ntl) - 1);
+            const int row = k >> (runl + ntl);
+            const uint64_t tile = tile0 + j;
+            const uint64_t base = ((tile & ((1ull << lowbits) - 1)) << mlo) | ((tile >> lowbits) << hishift);
+            const uint2 v = *reinterpret_cast<const uint2 *>(cost + (base | ((uint64_t)pb << 3) | ((uint64_t)row << q0)));
+            *reinterpret_cast<uint2 *>(st + (j << tb) + (row << mlo) + (pb << 3)) = v;
+        }
+        __syncthreads();
+        for (int w0 = threadIdx.x * E; w0 < (1 << (ntl + tb)); w0 += blockDim.x * E) {
+            const int j = w0 >> tb, t = (w0 & ((1 << tb) - 1)) >> R;
+            const uint8_t *src = st + (j << tb);
+            uint32_t wd[4] = {0u, 0u, 0u, 0u};
+            for (int i = 0; i < E; ++i) wd[i >> 2] |= (uint32_t)src[x_elem(t, i, rb, R)] << (8 * (i & 3));
+            uint8_t *dst = out + (tile0 << tb) + w0;
+            if (E == 16) *reinterpret_cast<uint4 *>(dst) = uint4{wd[0], wd[1], wd[2], wd[3]};
+            else *reinterpret_cast<uint2 *>(dst) = uint2{wd[0], wd[1]};
+        }
+        __syncthreads();
     }
 }
 
@@ -418,13 +672,29 @@ __global__ void __launch_bounds__(1024) x_finalize_kernel(XPartialFin f) {
 
 // Workspace: phase LUTs [max(p,1)][256] complex, readouts [p+1][3] doubles,
 // block partials [kXMaxBlocks][kXR] doubles, and for n > T the tile-ordered
-// cost table of the last group (2^n bytes); each region 256-byte aligned.
+// cost copies of the groups that take the fused boundary passes, other than
+// group 0 (x_copies of 2^n bytes); each region 256-byte aligned.
 struct XLayout {
     char *lut;
     double *ro, *part;
     uint8_t *cost_t;
     size_t bytes;
 };
+
+// Qubit groups for n > T: group 0 = qubits [0, T), then groups of up to
+// kXGroupBits qubits. Group 0, the largest and the only one with contiguous
+// tiles, goes second in the order when there are three or more groups, so
+// that it takes the mixing-only pass and the fused boundary passes (two
+// mixers each) fall on the smaller groups.
+static int x_ngroups(int n, int dtype) {
+    const int tb = x_tile_bits(dtype);
+    return n <= tb ? 1 : 1 + (n - tb + kXGroupBits - 1) / kXGroupBits;
+}
+static int x_order(int G, int k) { return G >= 3 ? (k == 0 ? 1 : k == 1 ? 0 : k) : k; }
+static int x_copies(int n, int dtype) {
+    const int G = x_ngroups(n, dtype);
+    return G <= 1 ? 0 : (x_order(G, 0) != 0) + (x_order(G, G - 1) != 0);
+}
 
 static XLayout x_layout(void *ws, int n, int p, int dtype) {
     const size_t cs = dtype == GQAOA_C64 ? 8 : 16;
@@ -439,34 +709,34 @@ static XLayout x_layout(void *ws, int n, int p, int dtype) {
     L.part = reinterpret_cast<double *>(w + off);
     off += al(sizeof(double) * kXR * (size_t)kXMaxBlocks);
     L.cost_t = reinterpret_cast<uint8_t *>(w + off);
-    if (n > x_tile_bits(dtype)) off += al(size_t(1) << n);
+    off += (size_t)x_copies(n, dtype) * al(size_t(1) << n);
     L.bytes = off;
     return L;
 }
 
 size_t x_workspace_bytes(int n, int p, int dtype) { return x_layout(nullptr, n, p, dtype).bytes; }
 
+template <typename T, int OPS>
+static void launch_group(int mlo, int blocks, size_t smem, hipStream_t st, const XPassArgs &a) {
+    constexpr int kFull = XCfg<T>::TB - kXGroupBits;  // tile bits below a full group
+    if (mlo == 0)
+        hipLaunchKernelGGL((x_pass_kernel<T, OPS, 0>), dim3(blocks), dim3(kXThreads), smem, st, a);
+    else if (mlo == kFull)
+        hipLaunchKernelGGL((x_pass_kernel<T, OPS, kFull>), dim3(blocks), dim3(kXThreads), smem, st, a);
+    else
+        hipLaunchKernelGGL((x_pass_kernel<T, OPS, -1>), dim3(blocks), dim3(kXThreads), smem, st, a);
+}
+
 template <typename T>
 static int launch_pass(int ops, int blocks, size_t smem, hipStream_t st, const XPassArgs &a) {
     switch (ops) {
-        case XOP_MIX_A:
-            hipLaunchKernelGGL((x_pass_kernel<T, XOP_MIX_A>), dim3(blocks), dim3(kXThreads), smem, st, a);
-            break;
-        case XOP_PRE | XOP_MIX_A:
-            hipLaunchKernelGGL((x_pass_kernel<T, XOP_PRE | XOP_MIX_A>), dim3(blocks), dim3(kXThreads), smem, st, a);
-            break;
-        case XOP_MIX_A | XOP_MID:
-            hipLaunchKernelGGL((x_pass_kernel<T, XOP_MIX_A | XOP_MID>), dim3(blocks), dim3(kXThreads), smem, st, a);
-            break;
-        case XOP_MIX_A | XOP_POST:
-            hipLaunchKernelGGL((x_pass_kernel<T, XOP_MIX_A | XOP_POST>), dim3(blocks), dim3(kXThreads), smem, st, a);
-            break;
-        case XOP_POST:
-            hipLaunchKernelGGL((x_pass_kernel<T, XOP_POST>), dim3(blocks), dim3(kXThreads), smem, st, a);
-            break;
+        case XOP_MIX_A: launch_group<T, XOP_MIX_A>(a.mlo, blocks, smem, st, a); break;
+        case XOP_PRE | XOP_MIX_A: launch_group<T, XOP_PRE | XOP_MIX_A>(a.mlo, blocks, smem, st, a); break;
+        case XOP_MIX_A | XOP_MID: launch_group<T, XOP_MIX_A | XOP_MID>(a.mlo, blocks, smem, st, a); break;
+        case XOP_MIX_A | XOP_POST: launch_group<T, XOP_MIX_A | XOP_POST>(a.mlo, blocks, smem, st, a); break;
+        case XOP_POST: launch_group<T, XOP_POST>(a.mlo, blocks, smem, st, a); break;
         case XOP_PRE | XOP_MIX_A | XOP_POST:
-            hipLaunchKernelGGL((x_pass_kernel<T, XOP_PRE | XOP_MIX_A | XOP_POST>), dim3(blocks), dim3(kXThreads), smem,
-                               st, a);
+            launch_group<T, XOP_PRE | XOP_MIX_A | XOP_POST>(a.mlo, blocks, smem, st, a);
             break;
         default:
             return fail(GQAOA_EINVAL, "internal: X pass operations %d", ops);
@@ -485,24 +755,7 @@ static XGroup x_group(int mlo, int q0, int TB, int R) {
     XGroup g{};
     g.mlo = mlo;
     g.q0 = q0;
-    uint32_t done = 0;
-    const uint32_t want = ((1u << TB) - 1u) & ~((1u << mlo) - 1u);
-    int rb = TB - R;
-    for (;;) {
-        int m = 0;
-        for (int r = 0; r < R; ++r) {
-            const int bit = rb + r;
-            if (bit >= mlo && bit < TB && !((done >> bit) & 1u)) {
-                m |= 1 << r;
-                done |= 1u << bit;
-            }
-        }
-        g.plan.rb[g.plan.nchunks] = rb;
-        g.plan.mask[g.plan.nchunks] = m;
-        ++g.plan.nchunks;
-        if (done == want) break;
-        rb = std::max(mlo, rb - R);
-    }
+    g.plan = x_plan(TB, R, mlo);
     return g;
 }
 
@@ -585,29 +838,51 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
         // groups: qubits [0, T), then runs of kXGroupBits, the last one shorter
         std::vector<XGroup> groups;
         groups.push_back(x_group(0, 0, TB, R));
+        // the streaming passes read group 0's costs straight from the table:
+        // its forward mixers end with the register bits at tile bit 0
+        if (groups[0].plan.rb[groups[0].plan.nchunks - 1] != 0)
+            return fail(GQAOA_EINVAL, "internal: X group 0 plan ends at tile bit %d",
+                        groups[0].plan.rb[groups[0].plan.nchunks - 1]);
         for (int q0 = TB; q0 < n; q0 += kXGroupBits) {
             const int kb = std::min(kXGroupBits, n - q0);
             groups.push_back(x_group(TB - kb, q0, TB, R));
         }
         const int G = (int)groups.size();
-        const XGroup &last = groups[G - 1];
+        if (G != x_ngroups(n, dtype)) return fail(GQAOA_EINVAL, "internal: %d X groups for n=%d", G, n);
         const uint64_t total = 1ull << n;
         const uint64_t ntiles = total >> TB;
-        // 32 blocks per CU (about 4 resident at once by LDS): at n = 28 the passes
-        // ran 3% faster per round than with 8 per CU, and no faster with more
+        // 32 blocks per CU (about 4 resident at once by LDS): at n = 28 a round
+        // ran 1-5% faster than with 4, 8 or 16 per CU, and no faster with up
+        // to one tile per block
         const int blocks = (int)std::min<uint64_t>(ntiles, std::min<uint64_t>((uint64_t)dev.num_cus * 32, kXMaxBlocks));
+        // cost copies of the boundary groups other than group 0, each in the
+        // order its streaming passes read (after the forward mixers)
+        std::vector<const uint8_t *> cost_of(G, nullptr);
+        cost_of[0] = cost;
         {
-            const int cb = (int)std::min<uint64_t>((total + 255) / 256, (uint64_t)dev.num_cus * 16);
-            hipLaunchKernelGGL(x_cost_tiles_kernel, dim3(cb), dim3(256), 0, st, cost, L.cost_t, TB, last.mlo, last.q0,
-                               total);
-            GQ_LAUNCH_CHECK();
+            const int cb = (int)std::max<uint64_t>(
+                1, std::min<uint64_t>(ntiles >> kXCopyTilesLog2, (uint64_t)dev.num_cus * 16));
+            int slot = 0;
+            for (int b : {x_order(G, 0), x_order(G, G - 1)}) {
+                if (cost_of[b]) continue;
+                const XGroup &gr = groups[b];
+                if (gr.mlo < 3 || (R != 3 && R != 4))
+                    return fail(GQAOA_EINVAL, "internal: X cost copy for mlo=%d, R=%d", gr.mlo, R);
+                uint8_t *dst = L.cost_t + (size_t)slot++ * ((total + 255) & ~uint64_t(255));
+                hipLaunchKernelGGL(x_cost_tiles_kernel, dim3(cb), dim3(256), 0, st, cost, dst, TB, gr.mlo, gr.q0,
+                                   gr.plan.rb[gr.plan.nchunks - 1], R, ntiles);
+                GQ_LAUNCH_CHECK();
+                cost_of[b] = dst;
+            }
+            if (slot != x_copies(n, dtype)) return fail(GQAOA_EINVAL, "internal: %d X cost copies", slot);
         }
         const size_t smem = (cs << TB) + (cs << TB) / 16;
         auto pass = [&](int gi, int ops, bool uniform, int ja, int jb, int readout_j) -> int {
             const XGroup &gr = groups[gi];
             XPassArgs a{};
             a.psi = psi;
-            a.cost = gi == 0 ? cost : L.cost_t;
+            a.cost = cost_of[gi];
+            a.cost_z = cost;
             a.n = n;
             a.mlo = gr.mlo;
             a.q0 = gr.q0;
@@ -651,7 +926,7 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
             const bool fwd = (j % 2) == 0;
             for (int k = 0; k < G; ++k) {
                 if (k == 0 && j > 0) continue;  // fused into the previous round's last pass
-                const int gi = fwd ? k : G - 1 - k;
+                const int gi = x_order(G, fwd ? k : G - 1 - k);
                 int ops = XOP_MIX_A, readout = -1, jb = 0;
                 if (j == 0 && k == 0) {
                     ops |= XOP_PRE;

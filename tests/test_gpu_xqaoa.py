@@ -77,6 +77,30 @@ def test_zero_rounds_writes_uniform_state():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("n,dt", [(12, g.C64), (20, g.C64), (22, g.C128)])
+def test_zero_rounds_reads_out_given_state(n, dt):
+    """p = 0 from a given state: the state is left as it is and the readout is
+    the oracle's readout of it (the readout-only pass on the streaming tiles)."""
+    torch = need_gpu()
+    m = int(round(4.2 * n))
+    lits = rand_lits(n, m, 500 + n)
+    cost, _ = g.gqaoa_cost_table(n, lits)
+    ref_cost = cost_table(n, lits)
+    psi0 = rand_state(n, 600 + n)
+    psi_d = torch.tensor(psi0, dtype=_torch_dtype(torch, dt), device="cuda")
+    t = int(np.nonzero(level_histogram(ref_cost, m))[0][0])
+    psi, psol, energy, norm = g.gqaoa_evolve_x(n, m, cost, [], [], dtype=dt, psi=psi_d, init_uniform=False,
+                                               target_level=t)
+    _, rpsol, renergy, rnorm = evolve_x(n, ref_cost, [], [], psi0=psi0, target=t)
+    got = psi.cpu().numpy().astype(np.complex128)
+    ref0 = psi0.astype(np.complex64).astype(np.complex128) if dt == g.C64 else psi0
+    assert np.array_equal(got, ref0)
+    assert abs(psol[0] - rpsol[0]) < TOL[dt]
+    assert abs(energy[0] - renergy[0]) / m < TOL[dt]
+    assert abs(norm[0] - rnorm[0]) < TOL[dt]
+    torch.cuda.synchronize()
+
+
 def test_full_size_n28_bit_flip_closed_form():
     """n = 28, m = 118, complex64, at the X-QAOA launch shape. With beta = pi/2
     every factor exp(-i pi/2 X_q) = -i X_q, so a round maps psi_z to
