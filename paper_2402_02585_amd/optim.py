@@ -145,7 +145,7 @@ def batched_single_pair(ns, ms, hists, p_list, grid=None, zoom_levels: int = 2, 
     return np.mod(beta, 2 * math.pi), gamma, out_p, out_e
 
 
-def lockstep_lbfgsb(evaluate, x0s, ftol: float = 1e-6, max_workers: int = 512):
+def lockstep_lbfgsb(evaluate, x0s, ftol: float = 1e-6, max_workers: int = 512, on_batch=None):
     """scipy L-BFGS-B from every start point of ``x0s``, run in lockstep.
 
     Each optimization runs in its own host thread and asks for its objective
@@ -154,8 +154,9 @@ def lockstep_lbfgsb(evaluate, x0s, ftol: float = 1e-6, max_workers: int = 512):
     their points; F[k] the value and G[k] the gradient at xs[k]). Every
     optimization takes the same steps as a scipy call of its own, as long as
     evaluate's result for one point does not depend on the others in the
-    batch. At most ``max_workers`` optimizations run at a time. Returns the
-    scipy results in the order of x0s."""
+    batch. At most ``max_workers`` optimizations run at a time; on_batch(k,
+    waiting), when given, is called after the k-th batched evaluation. Returns
+    the scipy results in the order of x0s."""
     import threading
 
     x0s = [np.asarray(x, dtype=np.float64) for x in x0s]
@@ -192,6 +193,7 @@ def lockstep_lbfgsb(evaluate, x0s, ftol: float = 1e-6, max_workers: int = 512):
         threads = [threading.Thread(target=worker, args=(w,), daemon=True) for w in range(W)]
         for t in threads:
             t.start()
+        nbatch = 0
         while True:
             with cv:
                 cv.wait_for(lambda: state["posted"] + state["done"] >= W)
@@ -214,12 +216,15 @@ def lockstep_lbfgsb(evaluate, x0s, ftol: float = 1e-6, max_workers: int = 512):
             for k, w in enumerate(waiting):
                 ans[w] = (float(F[k]), np.asarray(G[k], dtype=np.float64))
                 ready[w].set()
+            nbatch += 1
+            if on_batch is not None:
+                on_batch(nbatch, len(waiting))
         for t in threads:
             t.join()
     return results
 
 
-def full_gqaoa_batched(ns, ms, hists, p, beta0, gamma0, targets=None):
+def full_gqaoa_batched(ns, ms, hists, p, beta0, gamma0, targets=None, on_batch=None):
     """Full G-QAOA (App. C, "Optimization"): all 2 p_i angles of every instance
     by L-BFGS-B (maximizing P_sol, ftol 1e-6) from its single pair (beta0_i,
     gamma0_i) broadcast to every round, with the level-space adjoint gradient
@@ -249,7 +254,7 @@ def full_gqaoa_batched(ns, ms, hists, p, beta0, gamma0, targets=None):
         grads = [-np.concatenate([db[k, :p[i]], dg[k, :p[i]]]) for k, i in enumerate(idx)]
         return -P, grads
 
-    res = lockstep_lbfgsb(evaluate, x0s)
+    res = lockstep_lbfgsb(evaluate, x0s, on_batch=on_batch)
     betas = np.zeros((I, pmax))
     gammas = np.zeros((I, pmax))
     psol = np.zeros(I)

@@ -114,7 +114,7 @@ def _argbest(v):
 
 
 def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(120, 61), p_floor: int = 1,
-                        progress=None):
+                        progress=None, on_batch=None):
     """Least full-G-QAOA rounds reaching S for every instance.
 
     For a candidate p the seed is the best single pair of a (beta, gamma) grid
@@ -127,7 +127,8 @@ def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(1
     Returns (p_full[I] (0 where skipped), betas [I, p_max], gammas [I, p_max],
     psol[I], optimized[I]) at p_full; optimized[i] is False where no p below
     p_single reached S (then the angles are zero and psol NaN).
-    progress(step, candidates, reached) is called after every bisection step."""
+    progress(step, candidates, reached) is called after every bisection step,
+    on_batch(k, waiting) after every batched gradient of the optimizations."""
     hists = np.asarray(hists)
     ns = np.asarray(ns, dtype=np.int32)
     ms = np.asarray(ms, dtype=np.int32)
@@ -149,7 +150,7 @@ def full_rounds_batched(ns, ms, hists, S: float, p_single, targets=None, grid=(1
         step += 1
         mid = (lo[act] + hi[act]) // 2
         b0, g0 = _best_pairs_at(ns[act], ms[act], hists[act], tg[act], mid, gb, gg)
-        bs, gs, P = optim.full_gqaoa_batched(ns[act], ms[act], hists[act], mid, b0, g0, tg[act])
+        bs, gs, P = optim.full_gqaoa_batched(ns[act], ms[act], hists[act], mid, b0, g0, tg[act], on_batch=on_batch)
         ok = P >= S
         for k, i in enumerate(act):
             if ok[k]:

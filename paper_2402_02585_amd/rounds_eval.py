@@ -18,8 +18,9 @@ Reported:
   * S = 25% and 75% for the n = ``conv_n`` instances (the convergence study);
   * full G-QAOA rounds (all 2p angles optimized by L-BFGS-B with the
     level-space adjoint gradient, bisection below the single-pair count) for
-    every instance with n <= ``full_n_max`` (default 20: Sec. V compares the
-    single-pair results at 26 qubits with full G-QAOA results at 20);
+    every instance with ``full_n_min`` <= n <= ``full_n_max`` (default n <= 20:
+    Sec. V compares the single-pair results at 26 qubits with full G-QAOA
+    results at 20);
   * rounds against density (slope of a linear fit) for both sets;
   * the spread of the single-pair angles (median and interquartile range),
     which is the parameter clustering of Sec. III.B and its Max-SAT appendix.
@@ -73,7 +74,11 @@ def main(argv=None):
     ap.add_argument("--conv-n", type=int, default=16)
     ap.add_argument("--full", type=int, default=0,
                     help="full G-QAOA on a seeded subsample of this many instances per set (0: all with n <= full-n-max)")
+    ap.add_argument("--full-n-min", type=int, default=0)
     ap.add_argument("--full-n-max", type=int, default=20)
+    ap.add_argument("--kinds", default="sat,unsat", help="instance sets to run (sat, unsat or both)")
+    ap.add_argument("--full-slice", type=int, nargs=2, default=[0, 1], metavar=("OFFSET", "STRIDE"),
+                    help="full G-QAOA on every STRIDE-th eligible instance from OFFSET (to split a long run)")
     ap.add_argument("--full-grid", type=int, nargs=2, default=[120, 61],
                     help="grid of the single-pair seed at each candidate p of the full G-QAOA search")
     ap.add_argument("--grid", type=int, nargs=2, default=[360, 181], help="grid for n <= 20")
@@ -88,7 +93,7 @@ def main(argv=None):
     res = {"workload": {"n": [a.n_lo, a.n_hi], "per_n": a.per_n, "per_n_large": a.per_n_large,
                         "sat_density": [2.0, 4.5], "unsat_density": [4.6, 8.0], "grid": a.grid,
                         "grid_large": a.grid_large, "cap": f"ceil({a.cap_c}/sqrt(P))"}}
-    for kind in ("sat", "unsat"):
+    for kind in [k for k in ("sat", "unsat") if k in a.kinds.split(",")]:
         t0 = time.perf_counter()
         its = _set(kind, a.n_lo, a.n_hi, a.per_n, a.per_n_large, a.workers)
         t_gen = time.perf_counter() - t0
@@ -162,16 +167,18 @@ def main(argv=None):
         # full G-QAOA (all 2p angles, level-space adjoint) on every instance with
         # n <= full_n_max that the single pair reached in more than one round
         # (or a seeded subsample of --full of them)
-        pool = np.nonzero((ns <= a.full_n_max) & (p_half > 1))[0]
+        pool = np.nonzero((ns >= a.full_n_min) & (ns <= a.full_n_max) & (p_half > 1))[0]
         if a.full and pool.size > a.full:
             rng = np.random.Generator(np.random.PCG64(77 if kind == "sat" else 78))
             pool = np.sort(rng.choice(pool, a.full, replace=False))
+        pool = pool[a.full_slice[0]::a.full_slice[1]]
         if pool.size:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             pf, _, _, Pf, okf = rounds.full_rounds_batched(
                 ns[pool], ms[pool], H[pool], 0.5, p_half[pool], targets=targets[pool], grid=tuple(a.full_grid),
-                progress=lambda st, c, r: log(f"{kind} full G-QAOA bisection step {st}: {c} candidates, {r} reach S"))
+                progress=lambda st, c, r: log(f"{kind} full G-QAOA bisection step {st}: {c} candidates, {r} reach S"),
+                on_batch=lambda k, w: k % 200 == 0 and log(f"{kind} full G-QAOA: {k} batched gradients, {w} in the last"))
             t_full = time.perf_counter() - t0
             full = [{"n": int(ns[i]), "m": int(ms[i]), "P": float(P[i]), "p_single": int(p_half[i]),
                      "p_full": int(pf[k])} for k, i in enumerate(pool)]
