@@ -153,8 +153,10 @@ def solve(model, hists_dev, ns, ms, hists, p: int, median_pair, plain_grid=None,
     """The learned form for round count p on every instance: the network's
     pair, refined by ``refine_local``; where the result stays below
     ``fallback_ratio`` times the P_sol of the fixed cluster-median pair, the
-    plain optimizer (``optim.plain_single_pair`` over ``plain_grid``, default
-    the paper's pi/180 grid) replaces it.
+    plain optimizer's steps (``optim.plain_batched_grid`` over ``plain_grid``,
+    default the paper's pi/180 grid: the grid, then L-BFGS-B from its best
+    point) replace it, with the grid stage of all such instances in one
+    batched scan.
     Returns dict(beta, gamma, psol, fallback (bool mask), psol_learned (the
     network's pair alone), psol_median)."""
     I = len(ns)
@@ -166,21 +168,23 @@ def solve(model, hists_dev, ns, ms, hists, p: int, median_pair, plain_grid=None,
     fb = ps < fallback_ratio * p_med
     if fb.any():
         gb, gg = optim.fundamental_grid(*(plain_grid or optim.paper_grid()))
-        for i in np.nonzero(fb)[0]:
-            hdev = hists_dev[i, :ms[i] + 1].contiguous()
-            r = optim.plain_single_pair(int(ns[i]), int(ms[i]), hdev, p, gb, gg)
-            b[i], gm[i], ps[i] = r["beta"], r["gamma"], r["psol"]
+        ix = np.nonzero(fb)[0]
+        b[ix], gm[ix], ps[ix] = optim.plain_batched_grid(np.asarray(ns)[ix], np.asarray(ms)[ix],
+                                                         np.asarray(hists)[ix], hists_dev[ix], p, gb, gg)
     return {"beta": np.mod(b, 2 * math.pi), "gamma": gm, "psol": ps, "fallback": fb, "psol_learned": p_learn,
             "psol_median": p_med}
 
 
-def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 0.015), zoom: int = 16,
+def refine_local(ns, ms, hists, betas, gammas, p: int, widths=(0.5, 0.25, 0.06, 0.015), zoom: int = 24,
                  start_psol=None):
     """Best pair after one zoom x zoom window scan per width, each centred on the
     previous best (one replay of a graph-captured scan per width, all
     instances). The peak narrows as p grows, hence shrinking windows; at
     p = 64 the network's pair can sit a few tenths of a radian in beta from
-    the optimum, hence the first window's half-width of 0.5."""
+    the optimum, hence the first window's half-width of 0.5, and the peak is
+    then narrow in both angles, hence 24 points a side: with 16 the first
+    window's spacing steps over it on 18% of the instances (below 0.99 of
+    the batched optimizer's P_sol), with 24 on 4%."""
     I = len(ns)
     b = np.asarray(betas, dtype=np.float64).copy()
     gm = np.asarray(gammas, dtype=np.float64).copy()

@@ -8,6 +8,8 @@ seed. Here every evaluation runs on the GPU:
 * ``plain_single_pair``: the plain per-instance optimizer - one device call
   per angle pair (``gqaoa_hist_evolve``), grid then L-BFGS-B. This is the
   comparator for the batched and learned forms.
+* ``plain_batched_grid``: the plain optimizer's steps for several instances
+  with the grid stage as one batched scan (the learned form's fallback).
 * ``batched_single_pair``: all instances at once - the fundamental-domain grid
   through one ``gqaoa_scan_batched`` call, then two rounds of per-instance
   zoomed grids around each best point (per p, one graph-captured scan plan
@@ -69,6 +71,52 @@ def plain_single_pair(n: int, m: int, hist_dev, p: int, betas_grid, gammas_grid,
     ps, en, _ = g.gqaoa_hist_evolve(n, m, hist_dev, np.full(p, x[0]), np.full(p, x[1]), target)
     return {"beta": float(x[0]), "gamma": float(x[1]), "psol": float(ps[-1]), "energy": float(en[-1]),
             "evals": evals}
+
+
+def plain_batched_grid(ns, ms, hists, hists_dev, p: int, betas_grid, gammas_grid, objective: str = "psol",
+                       targets=None, max_out_bytes: float = 2e9):
+    """The plain optimizer's steps (``plain_single_pair``: the grid, then
+    L-BFGS-B from its best point) for several instances, with the grid stage
+    evaluated for all of them at once: one batched scan (the best cell per
+    instance, ties to the lowest (gamma, beta) index), then per instance the
+    grid point's value and L-BFGS-B with one float64 device call per
+    evaluation, as in ``plain_single_pair``. ``hists_dev[i, :ms[i] + 1]`` is
+    instance i's histogram on the device. Returns beta[I], gamma[I], psol[I]."""
+    hists = np.asarray(hists)
+    ns = np.asarray(ns)
+    ms = np.asarray(ms)
+    I = hists.shape[0]
+    gb, gg = np.asarray(betas_grid, dtype=np.float64), np.asarray(gammas_grid, dtype=np.float64)
+    tg = np.zeros(I, dtype=np.int32) if targets is None else np.asarray(targets, dtype=np.int32)
+    want_e = objective != "psol"
+    mode = g.ROW_ARGMIN_F32 if want_e else g.ROW_ARGMAX_F32
+    chunk = max(1, int(max_out_bytes // (gb.size * gg.size * 4 * (2 if want_e else 1))))
+    x0 = np.empty((I, 2))
+    for c0 in range(0, I, chunk):
+        sl = slice(c0, min(I, c0 + chunk))
+        psol, energy = g.gqaoa_scan_batched(ns[sl], ms[sl], hists[sl], gb, gg, [p], targets=tg[sl],
+                                            with_energy=want_e)
+        jd, _ = g.gqaoa_row_best((energy if want_e else psol).reshape(sl.stop - sl.start, -1), mode)
+        j = jd.cpu().numpy()
+        x0[sl, 0] = gb[j % gb.size]
+        x0[sl, 1] = gg[j // gb.size]
+        del psol, energy
+    beta, gamma, ps_out = np.empty(I), np.empty(I), np.empty(I)
+    for i in range(I):
+        hdev = hists_dev[i, :int(ms[i]) + 1].contiguous()
+        n, m, t = int(ns[i]), int(ms[i]), int(tg[i])
+
+        def f(x):
+            ps, en, _ = g.gqaoa_hist_evolve(n, m, hdev, np.full(p, x[0]), np.full(p, x[1]), t)
+            return _value(ps[-1], en[-1], objective)
+
+        x, best = x0[i], f(x0[i])
+        res = minimize(f, x0[i], method="L-BFGS-B", options={"ftol": 1e-6})
+        if res.fun < best:
+            x = res.x
+        ps, _, _ = g.gqaoa_hist_evolve(n, m, hdev, np.full(p, x[0]), np.full(p, x[1]), t)
+        beta[i], gamma[i], ps_out[i] = x[0], x[1], ps[-1]
+    return beta, gamma, ps_out
 
 
 def paper_grid():

@@ -9,6 +9,8 @@ at p in {1, 4, 16, 64} and checks on held-out instances that
     fallback: learned.solve) reaches >= 0.99 of the batched optimizer's mean
     P_sol, and >= 0.99 of the plain per-instance optimizer's on a seeded
     subsample, at every p including 64,
+  * the fallback runs the plain optimizer's steps (grid, then L-BFGS-B) and
+    matches optim.plain_single_pair,
   * the batched optimizer agrees with the plain per-call optimizer,
   * a checkpoint restores the network and its optimizer exactly, and
     training resumed from it continues bit for bit.
@@ -100,6 +102,29 @@ def test_learned_form_within_one_percent_of_plain_optimizer(trained):
                  for i in sub]
         log(f"p={p}: learned form {sol['psol'][sub].mean():.4f}  plain {np.mean(plain):.4f}")
         assert sol["psol"][sub].mean() >= 0.99 * np.mean(plain), (p, sol["psol"][sub], plain)
+
+
+def test_fallback_runs_the_plain_optimizer_steps(trained):
+    """Every instance forced to the fallback (ratio far above 1): its pair is
+    the plain optimizer's (grid, then L-BFGS-B) with the grid evaluated in one
+    batched scan, so its P_sol matches optim.plain_single_pair's over the same
+    grid, and equals the oracle's at the returned pair."""
+    torch = trained["torch"]
+    model, lab = trained["model"], trained["lab"]
+    ns, ms, H, hd = trained["ns"], trained["ms"], trained["hists"], trained["hists_dev"]
+    med = learned.cluster_median(lab, P_LIST)
+    sub = np.random.Generator(np.random.PCG64(12)).choice(len(ns), 6, replace=False)
+    ns6, ms6 = [ns[i] for i in sub], [ms[i] for i in sub]
+    gb, gg = optim.fundamental_grid(96, 48)
+    for p in (4, 16):
+        sol = learned.solve(model, hd[sub], ns6, ms6, H[sub], p, med[p], plain_grid=(96, 48), fallback_ratio=1e9)
+        assert sol["fallback"].all()
+        for k, i in enumerate(sub):
+            r = optim.plain_single_pair(ns[i], ms[i], hd[i, :ms[i] + 1].contiguous(), p, gb, gg)
+            log(f"p={p} instance {i}: fallback {sol['psol'][k]:.6f}  plain {r['psol']:.6f}")
+            assert sol["psol"][k] == pytest.approx(r["psol"], rel=1e-5, abs=1e-7)
+            ref = psol_single_pair_hist(H[i, :ms[i] + 1], sol["beta"][k], sol["gamma"][k], p)
+            assert sol["psol"][k] == pytest.approx(ref, abs=1e-12)
 
 
 def test_plain_optimizer_agrees_with_batched():
