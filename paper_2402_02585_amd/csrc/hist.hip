@@ -204,7 +204,7 @@ __device__ __forceinline__ void scan_load_levels(const ScanArgs &a, const ScanSl
 // Writes the item's table (phases in float64, rounded once) to LDS.
 template <int KMAX, int NL>
 __device__ __forceinline__ void scan_table(const ScanArgs &a, const ScanSlot &sl, int g, int lane, const int (&lv)[NL],
-                                           const float (&wk)[NL], float4 *tab, float *kw) {
+                                           const float (&wk)[NL], float4 *tab, float (&kwl)[NL]) {
     const double gam = a.gammas[(a.per_inst ? (size_t)sl.inst * a.ng : 0) + g];
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
@@ -219,7 +219,7 @@ __device__ __forceinline__ void scan_table(const ScanArgs &a, const ScanSlot &sl
                 ew = wk[i] * (float)lv[i];
             }
             tab[k] = e;
-            kw[k] = ew;
+            kwl[i] = ew;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -230,16 +230,31 @@ __device__ __forceinline__ void scan_table(const ScanArgs &a, const ScanSlot &sl
 // The rounds of one item for this lane's beta (mixer e^{-i beta} - 1 = mr + i mi).
 template <int KMAX, bool CROSS>
 __device__ __forceinline__ void scan_rounds(const ScanArgs &a, const ScanSlot &sl, const ScanItem &it, int lane,
-                                            float mr, float mi, const float4 *tab, const float *kw) {
+                                            float mr, float mi, const float4 *tab,
+                                            const float (&kwl)[(KMAX + 63) / 64]) {
+    // l_k w_k of every level, for the energy readout: the same in every lane,
+    // so held in scalar registers (read out of the lane that computed it)
+    float kw[CROSS ? 1 : KMAX];
+    if constexpr (!CROSS) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            kw[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kwl[k / 64]), k % 64));
+    }
     const int b = it.tile * 64 + lane;
     const bool active = b < a.nb;
     const float w0 = sl.t_idx == 0 ? tab[0].w : 0.f;   // weight of the target level (index 0)
-    float br[KMAX], bi[KMAX];
+    // The lane keeps the phased amplitudes phi_k of the current round and the
+    // mixer's correction c of the round before, and forms b_k = phi_k + c at
+    // the start of the next round: the same adds on the same operands as
+    // applying the mixer at the end of each round, with one level's
+    // temporaries live at a time instead of all of them.
+    float pr[KMAX], pi[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
-        br[k] = 1.f;
-        bi[k] = 0.f;
+        pr[k] = 1.f;
+        pi[k] = 0.f;
     }
+    float cr = 0.f, ci = 0.f;
     int q = 0;
     int found = 0;
     const int pmax = sl.pmax;
@@ -252,32 +267,34 @@ __device__ __forceinline__ void scan_rounds(const ScanArgs &a, const ScanSlot &s
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             const float4 e = tab[k];
-            const float nr = __builtin_fmaf(e.x, br[k], e.z * bi[k]);   // cos br + sin bi
+            const float xr = pr[k] + cr, xi = pi[k] + ci;               // b_k after the last mixer
+            const float nr = __builtin_fmaf(e.x, xr, e.z * xi);         // cos br + sin bi
             float ni;                                                    // cos bi - sin br
             if constexpr (KMAX <= kScanHoist4)
-                ni = __builtin_fmaf(e.x, bi[k], e.y * br[k]);
+                ni = __builtin_fmaf(e.x, xi, e.y * xr);
             else
-                ni = __builtin_fmaf(e.x, bi[k], -(e.z * br[k]));
-            br[k] = nr;
-            bi[k] = ni;
+                ni = __builtin_fmaf(e.x, xi, -(e.z * xr));
+            pr[k] = nr;
+            pi[k] = ni;
             sr = __builtin_fmaf(e.w, nr, sr);
             si = __builtin_fmaf(e.w, ni, si);
         }
-        const float cr = mr * sr - mi * si, ci = mr * si + mi * sr;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-            br[k] += cr;
-            bi[k] += ci;
-        }
+        cr = mr * sr - mi * si;
+        ci = mr * si + mi * sr;
         if constexpr (CROSS) {
-            const float P = w0 * (br[0] * br[0] + bi[0] * bi[0]);
+            const float b0r = pr[0] + cr, b0i = pi[0] + ci;
+            const float P = w0 * (b0r * b0r + b0i * b0i);
             if (found == 0 && P >= a.threshold) found = j;
             if (__ballot(active && found == 0) == 0) break;  // wave-uniform
         } else if (j == next_p) {
             float E = 0.f;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) E = __builtin_fmaf(kw[k], br[k] * br[k] + bi[k] * bi[k], E);
-            const float P = w0 * (br[0] * br[0] + bi[0] * bi[0]);
+            for (int k = 0; k < KMAX; ++k) {
+                const float br = pr[k] + cr, bi = pi[k] + ci;
+                E = __builtin_fmaf(kw[k], br * br + bi * bi, E);
+            }
+            const float b0r = pr[0] + cr, b0i = pi[0] + ci;
+            const float P = w0 * (b0r * b0r + b0i * b0i);
             if (active) {
                 const size_t o = (((size_t)sl.inst * a.num_p + q) * a.ng + it.g) * a.nb + b;
                 a.psol[o] = P;
@@ -316,10 +333,9 @@ template <int KMAX, bool CROSS>
 __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
     constexpr int NL = (KMAX + 63) / 64;
     __shared__ float4 tab_s[kScanMaxWaves][KMAX];
-    __shared__ float kw_s[kScanMaxWaves][KMAX];
     const int lane = threadIdx.x & 63;
     float4 *tab = tab_s[threadIdx.x >> 6];
-    float *kw = kw_s[threadIdx.x >> 6];
+    float kwl[NL];
     long long mix_key = -1;
     float mr = 0.f, mi = 0.f;
     unsigned item;
@@ -342,7 +358,7 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
     if constexpr (!CROSS)
         if (nxt < a.total_items) sl_n = a.slots[scan_decode(a, nxt).slot];
     for (;;) {
-        scan_table<KMAX, NL>(a, sl, it.g, lane, lv, wk, tab, kw);
+        scan_table<KMAX, NL>(a, sl, it.g, lane, lv, wk, tab, kwl);
         // loads for the next item, consumed after this item's rounds
         int lv_n[NL];
         float wk_n[NL];
@@ -358,7 +374,7 @@ __global__ void __launch_bounds__(kScanMaxWaves * 64) scan_kernel(ScanArgs a) {
             if (nn < a.total_items) sl_nn = a.slots[scan_decode(a, nn).slot];
         }
         scan_mixer(a, sl, it.tile, lane, mix_key, mr, mi);
-        scan_rounds<KMAX, CROSS>(a, sl, it, lane, mr, mi, tab, kw);
+        scan_rounds<KMAX, CROSS>(a, sl, it, lane, mr, mi, tab, kwl);
         // the next item rewrites tab: keep every lane's reads of this one first
         __builtin_amdgcn_wave_barrier();
         if (nxt >= a.total_items) break;
