@@ -24,6 +24,15 @@
  *    index j the state after round j's mixer.
  *  - The library is not thread-safe for concurrent calls sharing a
  *    workspace; independent workspaces/streams may be used concurrently.
+ *  - Device memory: calls with a ws_dev argument use only it and the
+ *    caller's buffers. The calls without one that stage per-call tables on
+ *    the device (gqaoa_cost_table, gqaoa_hist_batched, gqaoa_cost_batched,
+ *    gqaoa_hist_evolve, gqaoa_sv_items, gqaoa_shots_to_all,
+ *    gqaoa_draws_to_reject) take them stream-ordered (hipMallocAsync on
+ *    `stream`, freed on it after their last launch; clause records, round
+ *    tables and block rows, a few MiB at most); gqaoa_cost_table_noalloc is
+ *    the form of gqaoa_cost_table that allocates nothing. Plans allocate
+ *    their device tables at create and free them at destroy.
  */
 #ifndef GQAOA_H
 #define GQAOA_H
