@@ -178,10 +178,6 @@ __global__ void __launch_bounds__(kXThreads) x_low_kernel(XLowArgs a) {
 __device__ __forceinline__ int x_elem(int t, int i, int rb, int R) {
     return (t & ((1 << rb) - 1)) | (i << rb) | ((t >> rb) << (rb + R));
 }
-// LDS slot of tile element e: one pad slot per 16 elements spreads the
-// strided layouts over the banks.
-__device__ __forceinline__ int x_phys(int e) { return e + (e >> 4); }
-
 // The register chunks of one group's mixers: chunk k holds tile bits
 // [rb[k], rb[k] + R) in registers and applies the qubits of mask[k].
 struct XPlan {
@@ -282,9 +278,11 @@ __device__ __forceinline__ void x_store(XC<T> a, XC<T> *p) {
     __builtin_nontemporal_store(v2{a.re, a.im}, reinterpret_cast<v2 *>(p));
 }
 
-// The LDS slot of register element i of thread t in layout rb splits into a
-// per-thread part and a per-element part: the bits of the element index that
-// come from t and from i are disjoint, so the pad term e >> 4 splits too.
+// Tile element e sits in LDS slot e + (e >> 4): one pad slot per 16
+// elements spreads the strided layouts over the banks. The slot of register
+// element i of thread t in layout rb splits into a per-thread part and a
+// per-element part: the bits of the element index that come from t and from
+// i are disjoint, so the pad term e >> 4 splits too.
 // With rb fixed at compile time the element part is an instruction's
 // immediate offset.
 template <int R>
