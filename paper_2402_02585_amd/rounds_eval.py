@@ -15,7 +15,8 @@ Reported:
     the fundamental domain, two zoom refinements), with a round cap of
     ceil(cap_c / sqrt(P)); the fit log p = a + b log(1/P) (b = 1/2 is the
     quadratic speed-up) and the median of p sqrt(P);
-  * S = 25% and 75% for the n = ``conv_n`` instances (the convergence study);
+  * S = 25% and 75% for the n = ``conv_n`` instances (the convergence study),
+    with ``--full-conv`` also full G-QAOA there;
   * full G-QAOA rounds (all 2p angles optimized by L-BFGS-B with the
     level-space adjoint gradient, bisection below the single-pair count) for
     every instance with ``full_n_min`` <= n <= ``full_n_max`` (default n <= 20:
@@ -77,6 +78,8 @@ def main(argv=None):
     ap.add_argument("--full-n-min", type=int, default=0)
     ap.add_argument("--full-n-max", type=int, default=20)
     ap.add_argument("--kinds", default="sat,unsat", help="instance sets to run (sat, unsat or both)")
+    ap.add_argument("--full-conv", action="store_true",
+                    help="also full G-QAOA at S = 25%% and 75%% on the conv-n instances")
     ap.add_argument("--full-slice", type=int, nargs=2, default=[0, 1], metavar=("OFFSET", "STRIDE"),
                     help="full G-QAOA on every STRIDE-th eligible instance from OFFSET (to split a long run)")
     ap.add_argument("--full-grid", type=int, nargs=2, default=[120, 61],
@@ -158,6 +161,19 @@ def main(argv=None):
                 # per instance: n, m, d, P (or D), rounds (0: not reached within the cap), cap
                 rec["records"] = [[int(ns[i]), int(ms[i]), round(float(ds[i]), 4), float(P[i]), int(p_star[k]),
                                    int(cap_s[k])] for k, i in enumerate(sel)]
+            if S != 0.5 and a.full_conv and ok.sum() >= 3:
+                # full G-QAOA at this target on the same n = conv_n instances
+                ix = sel[ok]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pf, _, _, _, okf = rounds.full_rounds_batched(
+                    ns[ix], ms[ix], H[ix], S, p_star[ok], targets=targets[ix], grid=tuple(a.full_grid))
+                rec["full_gqaoa"] = {"instances": int(ix.size), "seconds": time.perf_counter() - t0,
+                                     "mean_ratio_full_to_single": float(np.mean(pf / p_star[ok])),
+                                     "instances_below_single": int(okf.sum()),
+                                     "median_p_full": float(np.median(pf)), "median_p_single": float(np.median(p_star[ok])),
+                                     "median_p_sqrtP": float(np.median(pf * np.sqrt(P[ix])))}
+                log(f"{kind} S={S} full G-QAOA: mean p_full/p_single {rec['full_gqaoa']['mean_ratio_full_to_single']:.3f}")
             entry["per_S"][str(S)] = rec
             log(f"{kind} S={S}: {rec.get('reached')}/{rec['instances']} reached, slope "
                 f"{rec.get('fit_slope_log_p_vs_log_inv_P', float('nan')):.3f}, c {rec.get('median_p_sqrtP', float('nan')):.3f}, "
