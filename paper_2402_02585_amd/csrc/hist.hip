@@ -164,7 +164,7 @@ constexpr int kScanMaxWaves = 4;
 // level-round as a three-operand fma, which gives the same value; larger
 // tables are re-read from LDS every round.
 constexpr int kScanHoist4 = 24;
-constexpr int kScanHoist3 = 28;
+constexpr int kScanHoist3 = 36;
 
 // Per item, each wave's table in LDS: tab[k] = {cos(gamma l_k), -sin(gamma l_k),
 // sin(gamma l_k), w_k} and kw[k] = l_k w_k (read only at readouts). The target
