@@ -27,6 +27,32 @@ def test_rounds_eval_small(tmp_path, capsys):
             assert 0.0 < e["fit_slope_log_p_vs_log_inv_P"] < 1.5
 
 
+def test_rounds_eval_set_range_slice_and_convergence_options(tmp_path):
+    """One set, an n range for the full-angle search, every second eligible
+    instance of it, and full G-QAOA at S = 25% and 75% on the conv-n
+    instances: full-angle rounds never exceed the single-pair ones."""
+    need_gpu()
+    from paper_2402_02585_amd import rounds_eval
+    out = tmp_path / "rounds_opts.json"
+    rounds_eval.main(["--kinds", "sat", "--n-lo", "9", "--n-hi", "11", "--per-n", "6", "--per-n-large", "2",
+                      "--conv-n", "10", "--full-n-min", "10", "--full-n-max", "11", "--full-slice", "1", "2",
+                      "--full-conv", "--full-grid", "40", "21", "--grid", "60", "31", "--workers", "1",
+                      "--out", str(out)])
+    r = json.loads(out.read_text())
+    assert set(r) == {"workload", "sat"}
+    e = r["sat"]
+    rec = e["per_S"]["0.5"]["records"]          # [n, m, d, P, p_single, cap]
+    eligible = [x for x in rec if 10 <= x[0] <= 11 and x[4] > 1]
+    full = e["full_gqaoa"]
+    assert full["instances"] == len(eligible[1::2])
+    assert all(f["n"] in (10, 11) and 1 <= f["p_full"] <= f["p_single"] for f in full["records"])
+    for S in ("0.25", "0.75"):
+        fc = e["per_S"][S].get("full_gqaoa")
+        if fc is not None:
+            assert 0 < fc["mean_ratio_full_to_single"] <= 1.0
+            assert fc["median_p_full"] <= fc["median_p_single"]
+
+
 def test_fairness_eval_small(tmp_path):
     need_gpu()
     from paper_2402_02585_amd import fairness_eval
