@@ -167,8 +167,9 @@ constexpr int kScanHoist4 = 24;
 constexpr int kScanHoist3 = 36;
 
 // Per item, each wave's table in LDS: tab[k] = {cos(gamma l_k), -sin(gamma l_k),
-// sin(gamma l_k), w_k} and kw[k] = l_k w_k (read only at readouts). The target
-// level, when occupied, is level 0 of the instance's compacted order, so the
+// sin(gamma l_k), w_k}; the energy weights l_k w_k (read only at readouts) go
+// from the lanes that compute them to scalar registers. The target level,
+// when occupied, is level 0 of the instance's compacted order, so the
 // crossing readout reads one amplitude.
 //
 // A level-round is eight two-operand VALU instructions on VGPR operands (the
