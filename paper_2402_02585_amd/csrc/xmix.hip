@@ -9,16 +9,21 @@
 //
 // Above T qubits (T = 12 for complex64, 11 for complex128: a 32 KiB tile)
 // the qubits form groups: group 0 = qubits 0..T-1 (a tile is 2^T consecutive
-// amplitudes), then groups of K = 8 qubits (a tile is 2^(T-K) consecutive
-// amplitudes, one 128-byte run, times the 2^K values of the group's qubits),
-// the last one possibly smaller (its runs are longer). One pass streams the
-// state once and applies one group's factors:
-//   * each thread holds E = 2^(T-8) amplitudes of a tile in registers and
-//     applies the butterflies of the register-resident bits there; the tile
-//     is re-distributed through LDS to bring the next bits into registers
-//     (one to four exchanges per pass, never a butterfly in LDS). For group 0
-//     and the full groups the chunk plan is a template parameter, so the
-//     exchanges use fixed LDS offsets and the stages run without branches;
+// amplitudes), then groups of K = 8 qubits, the last one possibly smaller.
+// A high group's tile is twice as large, 2^(T+1) amplitudes (64 KiB): runs of
+// 2^(T+1-K) consecutive amplitudes (256 bytes) times the 2^K values of the
+// group's qubits: a high group's passes on them ran 15% faster than on the
+// 128-byte runs of 32 KiB tiles (n = 28, complex64), and the GPU holds two
+// such tiles per CU in LDS. One
+// pass streams the state once and applies one group's factors:
+//   * each thread holds E = 2^R amplitudes of a tile in registers (R = 4
+//     for complex64, 3 for complex128; 256 threads per group-0 tile, 512 per
+//     high-group tile) and applies the butterflies of the register-resident
+//     bits there; the tile is re-distributed through LDS to bring the next
+//     bits into registers (one to four exchanges per pass, never a butterfly
+//     in LDS). For group 0 and the full groups the chunk plan is a template
+//     parameter, so the exchanges use fixed LDS offsets and the stages run
+//     without branches;
 //   * the group order alternates between rounds (o_0..o_{g-1}, then back),
 //     so the last pass of a round and the first of the next touch the same
 //     group and are fused: mixers of round j, readout of the state after
@@ -26,14 +31,16 @@
 //     g - 1 passes (two at n = 28, complex64) instead of g. With three or
 //     more groups, group 0 (the most qubits, contiguous tiles) goes second,
 //     so it takes a mixing-only pass and the fused passes, which apply two
-//     mixers, fall on smaller groups.
+//     mixers, fall on the high groups.
 // The phase and readouts need C(z) in tile order: group 0 reads the cost
 // table itself, the other two groups that take the fused passes read
 // tile-ordered copies built once per call. After a group's forward mixers
 // each thread's costs are consecutive in either, so the streaming passes
-// read them with one vector load per tile, issued with the next tile's state
-// loads. The first pass of a call starts in that layout (|s> is the same in
-// every layout) and runs its mixers backward.
+// read them with one vector load per tile. Group 0's passes run on a grid of
+// 32 blocks per CU, each block keeping its next tile's loads in flight while
+// it mixes the current one; the high groups' passes give each block one
+// tile. The first pass of a call starts in the cost-copy layout (|s> is the
+// same in every layout) and runs its mixers backward.
 // Up to T qubits the whole state is one tile, evolved by a simple LDS kernel.
 #include "internal.h"
 
@@ -43,11 +50,11 @@
 
 namespace gqaoa {
 
-constexpr int kXThreads = 256;
-constexpr int kXThreadBits = 8;
-constexpr int kXTileBytesLog2 = 15;  // 32 KiB of LDS per tile
+constexpr int kXThreads = 256;       // blocks of the group-0 and small-state kernels
+constexpr int kXMaxRb = 9;           // largest register layout of a pass (TB - R of the high-group tiles)
+constexpr int kXTileBytesLog2 = 15;  // 32 KiB group-0 tiles; the high groups' tiles are twice that
 constexpr int kXGroupBits = 8;       // qubits of a full high group
-constexpr int kXMaxBlocks = 8192;
+constexpr int kXMaxBlocks = 65536;
 constexpr int kXR = 7;  // partial sums per block of the small-n kernel
 constexpr int kXMaxChunks = 6;
 
@@ -55,13 +62,15 @@ inline int x_tile_bits(int dtype) { return kXTileBytesLog2 - (dtype == GQAOA_C64
 
 template <typename T>
 struct XCfg;
+// TB: tile bits of group 0 (256 threads of 2^R registers); TBW = TB + 1: tile
+// bits of the high groups (512 threads), whose rows are then 256 bytes long.
 template <>
 struct XCfg<float> {
-    static constexpr int TB = 12, R = 4;
+    static constexpr int TB = 12, TBW = 13, R = 4;
 };
 template <>
 struct XCfg<double> {
-    static constexpr int TB = 11, R = 3;
+    static constexpr int TB = 11, TBW = 12, R = 3;
 };
 
 template <typename T>
@@ -315,7 +324,7 @@ __device__ __forceinline__ void x_lds_at(XC<T> (&v)[1 << R], XC<T> *lds) {
 // The same for the runtime rb of a plan (uniform across the block, 0 <= rb <= T - R).
 template <typename T, int R, bool PUT, int RB = 0>
 __device__ __forceinline__ void x_lds_move(XC<T> (&v)[1 << R], XC<T> *lds, int rb) {
-    if constexpr (RB <= kXThreadBits) {
+    if constexpr (RB <= kXMaxRb) {
         if (rb == RB) x_lds_at<T, R, PUT, RB>(v, lds);
         else x_lds_move<T, R, PUT, RB + 1>(v, lds, rb);
     }
@@ -455,14 +464,15 @@ __device__ __forceinline__ void x_unpack_costs(const typename XCostVec<R>::type 
 }
 
 // OPS: the XOP_* flags of the pass, fixed at compile time so that a pass
-// that only mixes carries no readout, cost or phase state. MLO >= 0: the
-// group is on tile bits [MLO, T) and its plan is fixed at compile time
-// (group 0 and the full groups of 8 qubits); MLO = -1: any group, from the
-// plan in the arguments.
-template <typename T, int OPS, int MLO>
-__global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
-    constexpr int TB = XCfg<T>::TB, R = XCfg<T>::R, E = 1 << R;
-    static_assert(TB - R == kXThreadBits, "one tile per block of 256 threads");
+// that only mixes carries no readout, cost or phase state. TB: the tile bits
+// (group 0's tiles or the high groups' twice larger ones), one tile per
+// 2^(TB - R) threads. MLO >= 0: the group is on tile bits [MLO, TB) and its
+// plan is fixed at compile time (group 0 and the full groups of 8 qubits);
+// MLO = -1: any group, from the plan in the arguments.
+template <typename T, int OPS, int MLO, int TB>
+__global__ void __launch_bounds__(1 << (TB - XCfg<T>::R)) x_pass_kernel(XPassArgs a) {
+    constexpr int R = XCfg<T>::R, E = 1 << R, kThreads = 1 << (TB - R);
+    static_assert(TB - R <= kXMaxRb, "register layouts up to kXMaxRb");
     static_assert(E >= 8, "costs are read as whole 32-bit words");
     // Passes that start with the mixers always read the state and keep the
     // next tile's loads (and its costs, when the pass reads them) in flight
@@ -474,8 +484,8 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     XC<T> *lds = reinterpret_cast<XC<T> *>(smem);
     __shared__ XC<T> lut_s[2][256];
-    __shared__ double red_s[3 * kXThreads / kWave];
-    for (int i = threadIdx.x; i < 256; i += kXThreads) {
+    __shared__ double red_s[3 * kThreads / kWave];
+    for (int i = threadIdx.x; i < 256; i += kThreads) {
         if constexpr ((OPS & XOP_PRE) != 0) lut_s[0][i] = reinterpret_cast<const XC<T> *>(a.lut_a)[i];
         if constexpr ((OPS & XOP_MID) != 0) lut_s[1][i] = reinterpret_cast<const XC<T> *>(a.lut_b)[i];
     }
@@ -603,7 +613,7 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
     }
     if constexpr (kReadout) {
         double r[3] = {aP, aE, aN};
-        block_sum<3, kXThreads>(r, red_s);
+        block_sum<3, kThreads>(r, red_s);
         if (threadIdx.x == 0)
 #pragma unroll
             for (int k = 0; k < 3; ++k) a.partials[(size_t)blockIdx.x * 3 + k] = r[k];
@@ -620,11 +630,19 @@ __global__ void __launch_bounds__(kXThreads) x_pass_kernel(XPassArgs a) {
 // staged in LDS in element order and each thread then gathers its 2^R bytes
 // and writes them with one vector store.
 constexpr int kXCopyTilesLog2 = 3;
+constexpr int kXCopyBytesLog2 = 15;  // LDS of the copy kernel
+// Tiles per block of the copy kernel, log2: kXCopyTilesLog2, fewer when the
+// tiles are larger than 4 KiB or there are fewer tiles (ntiles is a power of 2).
+__host__ __device__ inline int x_copy_ntl(int tb, uint64_t ntiles) {
+    int ntl = kXCopyTilesLog2 < kXCopyBytesLog2 - tb ? kXCopyTilesLog2 : kXCopyBytesLog2 - tb;
+    while (ntl > 0 && (1ull << ntl) > ntiles) --ntl;
+    return ntl;
+}
 __global__ void __launch_bounds__(256) x_cost_tiles_kernel(const uint8_t *__restrict__ cost, uint8_t *__restrict__ out,
                                                           int tb, int mlo, int q0, int rb, int R, uint64_t ntiles) {
-    __shared__ __align__(16) uint8_t st[(1 << kXCopyTilesLog2) << 12];
+    __shared__ __align__(16) uint8_t st[1 << kXCopyBytesLog2];
     const int lowbits = q0 - mlo, hishift = q0 + tb - mlo;
-    const int ntl = ntiles < (1ull << kXCopyTilesLog2) ? __builtin_ctzll(ntiles) : kXCopyTilesLog2;
+    const int ntl = x_copy_ntl(tb, ntiles);
     const int runl = mlo - 3;  // 8-byte pieces per row run, log2
     const int E = 1 << R;
     for (uint64_t tile0 = (uint64_t)blockIdx.x << ntl; tile0 < ntiles; tile0 += (uint64_t)gridDim.x << ntl) {
@@ -661,6 +679,9 @@ struct XPartialFin {
 __global__ void __launch_bounds__(1024) x_finalize_kernel(XPartialFin f) {
     __shared__ double lds[3 * 1024 / kWave];
     double r[3] = {0, 0, 0};
+    // up to one row per pass block (32768 for the high groups at n = 28):
+    // unrolled so that several rows' loads are in flight per thread
+#pragma unroll 8
     for (int b = threadIdx.x; b < f.nblocks; b += 1024)
         for (int k = 0; k < 3; ++k) r[k] += f.partials[(size_t)b * f.stride + f.off + k];
     block_sum<3, 1024>(r, lds);
@@ -705,7 +726,8 @@ static XLayout x_layout(void *ws, int n, int p, int dtype) {
     L.ro = reinterpret_cast<double *>(w + off);
     off += al(sizeof(double) * 3 * ((size_t)p + 1));
     L.part = reinterpret_cast<double *>(w + off);
-    off += al(sizeof(double) * kXR * (size_t)kXMaxBlocks);
+    static_assert(kXR <= 3 * kXMaxBlocks, "the small-state kernel's partials fit");
+    off += al(sizeof(double) * 3 * (size_t)kXMaxBlocks);
     L.cost_t = reinterpret_cast<uint8_t *>(w + off);
     off += (size_t)x_copies(n, dtype) * al(size_t(1) << n);
     L.bytes = off;
@@ -714,15 +736,18 @@ static XLayout x_layout(void *ws, int n, int p, int dtype) {
 
 size_t x_workspace_bytes(int n, int p, int dtype) { return x_layout(nullptr, n, p, dtype).bytes; }
 
+// Group 0 (mlo = 0) on its own tiles; the high groups on the larger ones,
+// a full group of 8 qubits with its compile-time plan.
 template <typename T, int OPS>
 static void launch_group(int mlo, int blocks, size_t smem, hipStream_t st, const XPassArgs &a) {
-    constexpr int kFull = XCfg<T>::TB - kXGroupBits;  // tile bits below a full group
+    constexpr int TB = XCfg<T>::TB, TBW = XCfg<T>::TBW, R = XCfg<T>::R;
+    constexpr int kFull = TBW - kXGroupBits;  // high-group tile bits below a full group
     if (mlo == 0)
-        hipLaunchKernelGGL((x_pass_kernel<T, OPS, 0>), dim3(blocks), dim3(kXThreads), smem, st, a);
+        hipLaunchKernelGGL((x_pass_kernel<T, OPS, 0, TB>), dim3(blocks), dim3(1 << (TB - R)), smem, st, a);
     else if (mlo == kFull)
-        hipLaunchKernelGGL((x_pass_kernel<T, OPS, kFull>), dim3(blocks), dim3(kXThreads), smem, st, a);
+        hipLaunchKernelGGL((x_pass_kernel<T, OPS, kFull, TBW>), dim3(blocks), dim3(1 << (TBW - R)), smem, st, a);
     else
-        hipLaunchKernelGGL((x_pass_kernel<T, OPS, -1>), dim3(blocks), dim3(kXThreads), smem, st, a);
+        hipLaunchKernelGGL((x_pass_kernel<T, OPS, -1, TBW>), dim3(blocks), dim3(1 << (TBW - R)), smem, st, a);
 }
 
 template <typename T>
@@ -745,12 +770,14 @@ static int launch_pass(int ops, int blocks, size_t smem, hipStream_t st, const X
 
 // One group of qubits for the streaming passes (n > T).
 struct XGroup {
-    int mlo, q0;  // tile bits [mlo, T) are qubits q0 .. q0 + T - mlo - 1
+    int tb;       // tile bits of the group's passes
+    int mlo, q0;  // tile bits [mlo, tb) are qubits q0 .. q0 + tb - mlo - 1
     XPlan plan;
 };
 
 static XGroup x_group(int mlo, int q0, int TB, int R) {
     XGroup g{};
+    g.tb = TB;
     g.mlo = mlo;
     g.q0 = q0;
     g.plan = x_plan(TB, R, mlo);
@@ -766,6 +793,7 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
     const size_t cs = dtype == GQAOA_C64 ? 8 : 16;
     const XLayout L = x_layout(ws, n, p, dtype);
     const int TB = x_tile_bits(dtype);
+    const int TBW = dtype == GQAOA_C64 ? XCfg<float>::TBW : XCfg<double>::TBW;
     const int R = dtype == GQAOA_C64 ? XCfg<float>::R : XCfg<double>::R;
     const char *prof = dtype == GQAOA_C64 ? "x_pass_c64" : "x_pass_c128";
     std::vector<char> tab((size_t)std::max(p, 1) * 256 * cs, 0);
@@ -843,40 +871,51 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
                         groups[0].plan.rb[groups[0].plan.nchunks - 1]);
         for (int q0 = TB; q0 < n; q0 += kXGroupBits) {
             const int kb = std::min(kXGroupBits, n - q0);
-            groups.push_back(x_group(TB - kb, q0, TB, R));
+            groups.push_back(x_group(TBW - kb, q0, TBW, R));
         }
         const int G = (int)groups.size();
         if (G != x_ngroups(n, dtype)) return fail(GQAOA_EINVAL, "internal: %d X groups for n=%d", G, n);
         const uint64_t total = 1ull << n;
-        const uint64_t ntiles = total >> TB;
-        // 32 blocks per CU (about 4 resident at once by LDS): at n = 28 a round
-        // ran 1-5% faster than with 4, 8 or 16 per CU, and no faster with up
-        // to one tile per block
-        const int blocks = (int)std::min<uint64_t>(ntiles, std::min<uint64_t>((uint64_t)dev.num_cus * 32, kXMaxBlocks));
+        // Group 0: 32 blocks per CU looping over tiles with the next one in
+        // flight (about 4 resident at once by LDS): at n = 28 its pass ran
+        // 1-5% faster than with 4, 8 or 16 per CU, and no faster with up to
+        // one tile per block. High groups: one tile per block up to
+        // kXMaxBlocks (2 resident per CU by LDS).
+        auto ntiles_of = [&](const XGroup &gr) -> uint64_t { return total >> gr.tb; };
+        auto blocks_of = [&](const XGroup &gr) -> int {
+            const uint64_t want = gr.tb == TB ? (uint64_t)dev.num_cus * 32 : ntiles_of(gr);
+            return (int)std::min<uint64_t>(ntiles_of(gr), std::min<uint64_t>(want, kXMaxBlocks));
+        };
+        auto smem_of = [&](const XGroup &gr) -> size_t { return (cs << gr.tb) + (cs << gr.tb) / 16; };
+        for (const XGroup &gr : groups)
+            if (gr.tb > TBW || gr.tb - R > kXMaxRb || gr.mlo < 0 || gr.mlo >= gr.tb || gr.q0 + gr.tb - gr.mlo > n ||
+                smem_of(gr) + 2 * 256 * cs + 3 * sizeof(double) * (1 << (gr.tb - R)) / kWave > dev.lds_per_block)
+                return fail(GQAOA_EINVAL, "internal: X group tb=%d mlo=%d q0=%d for n=%d", gr.tb, gr.mlo, gr.q0, n);
         // cost copies of the boundary groups other than group 0, each in the
         // order its streaming passes read (after the forward mixers)
         std::vector<const uint8_t *> cost_of(G, nullptr);
         cost_of[0] = cost;
         {
-            const int cb = (int)std::max<uint64_t>(
-                1, std::min<uint64_t>(ntiles >> kXCopyTilesLog2, (uint64_t)dev.num_cus * 16));
             int slot = 0;
             for (int b : {x_order(G, 0), x_order(G, G - 1)}) {
                 if (cost_of[b]) continue;
                 const XGroup &gr = groups[b];
-                if (gr.mlo < 3 || (R != 3 && R != 4))
-                    return fail(GQAOA_EINVAL, "internal: X cost copy for mlo=%d, R=%d", gr.mlo, R);
+                if (gr.mlo < 3 || (R != 3 && R != 4) || (1 << (x_copy_ntl(gr.tb, ntiles_of(gr)) + gr.tb)) > (1 << kXCopyBytesLog2))
+                    return fail(GQAOA_EINVAL, "internal: X cost copy for tb=%d, mlo=%d, R=%d", gr.tb, gr.mlo, R);
+                const int cb = (int)std::max<uint64_t>(
+                    1, std::min<uint64_t>(ntiles_of(gr) >> kXCopyTilesLog2, (uint64_t)dev.num_cus * 16));
                 uint8_t *dst = L.cost_t + (size_t)slot++ * ((total + 255) & ~uint64_t(255));
-                hipLaunchKernelGGL(x_cost_tiles_kernel, dim3(cb), dim3(256), 0, st, cost, dst, TB, gr.mlo, gr.q0,
-                                   gr.plan.rb[gr.plan.nchunks - 1], R, ntiles);
+                hipLaunchKernelGGL(x_cost_tiles_kernel, dim3(cb), dim3(256), 0, st, cost, dst, gr.tb, gr.mlo, gr.q0,
+                                   gr.plan.rb[gr.plan.nchunks - 1], R, ntiles_of(gr));
                 GQ_LAUNCH_CHECK();
                 cost_of[b] = dst;
             }
             if (slot != x_copies(n, dtype)) return fail(GQAOA_EINVAL, "internal: %d X cost copies", slot);
         }
-        const size_t smem = (cs << TB) + (cs << TB) / 16;
         auto pass = [&](int gi, int ops, bool uniform, int ja, int jb, int readout_j) -> int {
             const XGroup &gr = groups[gi];
+            const int blocks = blocks_of(gr);
+            const size_t smem = smem_of(gr);
             XPassArgs a{};
             a.psi = psi;
             a.cost = cost_of[gi];
@@ -885,7 +924,7 @@ int run_evolve_x(int n, const uint8_t *cost, int p, const double *beta, const do
             a.mlo = gr.mlo;
             a.q0 = gr.q0;
             a.contig = gi == 0 ? TB : gr.mlo;
-            a.ntiles = ntiles;
+            a.ntiles = ntiles_of(gr);
             a.plan = gr.plan;
             a.ops = ops;
             a.init_uniform = uniform ? 1 : 0;

@@ -21,8 +21,11 @@ def _torch_dtype(torch, dt):
     return torch.complex64 if dt == g.C64 else torch.complex128
 
 
-# n = 3..11: a single low tile; 12/13: c64 one tile or low + 1 qubit; 17, 20:
-# one high pass; 22: two high passes, the last ragged
+# n = 3..11: a single low tile; 12: complex64 one low tile, complex128 low
+# + a 1-qubit high group; 13: complex64 low + 1 qubit (its high tile is the
+# whole state); 17: one ragged high group; 20: complex64 one full high group
+# (compile-time plan), complex128 a full and a 1-qubit one; 22: two high
+# groups, the last ragged
 @pytest.mark.parametrize("n", [3, 7, 11, 12, 13, 17, 20, 22])
 @pytest.mark.parametrize("dt", [g.C64, g.C128])
 def test_states_match_oracle(n, dt):
