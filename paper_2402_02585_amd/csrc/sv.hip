@@ -713,22 +713,25 @@ struct PassShape {
     int amp, unroll, blocks_x, nt;
 };
 
-constexpr int kMaxPassBlocks = 65536;  // partial-sum rows per launch (all instances)
+constexpr int kMaxPassBlocks = 262144;  // partial-sum rows per launch (all instances)
 
 // Launch shape of the streaming passes. A lane moves exactly one 16-byte
 // chunk of the state per group (2 complex64 or 1 complex128 amplitudes), so
 // each wave-wide load or store instruction covers 1 KiB of contiguous memory;
 // UNROLL groups per loop trip keep that many loads in flight per lane. By
-// default the grid gives every block one tile (4 groups per lane, 256 blocks
-// per CU allowed, up to kMaxPassBlocks rows): at n = 28 that streams about 5%
-// faster than a persistent grid of 16 blocks per CU looping over 8-group
-// tiles, and the extra partial rows are folded before the finalize. The
-// fused finalize (the last block sums every row) keeps the persistent grid.
+// default the grid gives every block one tile (4 groups per lane, up to 1024
+// blocks per CU and kMaxPassBlocks rows): at n = 28 (131,072 blocks) that
+// streams about 5% faster than a persistent grid of 16 blocks per CU looping
+// over 8-group tiles and 1.2% faster than 65,536 blocks of two tiles each,
+// and the 256 instances of a batched adjoint of n = 20 get 1024 blocks each
+// (3% faster per batch than 256); the extra partial rows are folded before
+// the finalize. The fused finalize (the last block sums every row) keeps the
+// persistent grid.
 // GQAOA_SV_SHAPE="amp,unroll,blocks_per_cu,nt" overrides the round pass (a
 // tuning hook; shapes outside the compiled set fall back to the default).
 static PassShape pass_shape(uint64_t N, int num_inst, int dtype, const DeviceInfo &dev, bool fused = false) {
     PassShape s;
-    int bpc = fused ? 16 : 256;
+    int bpc = fused ? 16 : 1024;
     s.nt = 1;
     s.amp = dtype == GQAOA_C64 ? 2 : 1;
     s.unroll = fused ? 8 : 4;

@@ -3,10 +3,11 @@ takes, whose partial rows are folded first, in launches of several
 instances.
 
 - Three statevector items at n = 26 (complex64) stream as one batch of three
-  instances: the 65,536 partial rows of a pass are shared out as 21,845 per
-  instance, so every instance folds 21 full runs of 1024 rows and a ragged run
-  of 341. P_sol and E against the oracle's float64 level-space evolution of
-  the brute-force histogram (1e-5, 1e-5 m).
+  instances on a grid of 256 blocks per CU (GQAOA_SV_SHAPE): the 65,536
+  partial rows of a pass are shared out as 21,845 per instance, so every
+  instance folds 21 full runs of 1024 rows and a ragged run of 341. P_sol and
+  E against the oracle's float64 level-space evolution of the brute-force
+  histogram (1e-5, 1e-5 m).
 - A two-instance adjoint batch at n = 22 (complex128): 4096 blocks per
   instance, 4 folded rows each, in the forward and the reverse passes; P_sol
   and the gradient against the oracle's level-space sweep (1e-12, 1e-10).
@@ -26,8 +27,9 @@ pytestmark = pytest.mark.gpu
 P_LIST = [1, 5, 12]
 
 
-def test_three_streamed_items_ragged_fold():
+def test_three_streamed_items_ragged_fold(monkeypatch):
     torch = need_gpu()
+    monkeypatch.setenv("GQAOA_SV_SHAPE", "2,4,256,1")
     n = 26
     m = inst.m_from_density(n, 4.2)
     lits = [rand_lits(n, m, 300 + k) for k in range(3)]
@@ -36,6 +38,7 @@ def test_three_streamed_items_ragged_fold():
     beta = np.array([0.7, 2.9, 4.4])
     gamma = np.array([0.35, 0.2, 1.1])
     ps, en = g.gqaoa_sv_items([n] * 3, [m] * 3, costs, [0, 1, 2], beta, gamma, P_LIST, with_energy=True)
+    monkeypatch.delenv("GQAOA_SV_SHAPE")
     ps, en = ps.cpu().numpy(), en.cpu().numpy()
     del costs
     torch.cuda.empty_cache()
