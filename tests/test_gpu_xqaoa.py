@@ -136,3 +136,28 @@ def test_full_size_n28_bit_flip_closed_form():
     assert np.abs(p64 - p128).max() < 1e-5
     assert np.abs(e64 - e128).max() / m < 1e-5
     torch.cuda.empty_cache()
+
+
+def test_bit_flip_closed_form_complex128_n30():
+    """complex128 at n = 30: the high groups' 64 KiB tiles outnumber the
+    passes' largest grid (2^18 tiles, 65,536 blocks), so every block loops
+    over four tiles with the next one in flight. The beta = pi/2 closed form
+    (see the n = 28 test) at 4096 sampled z, to 1e-12 after scaling by
+    2^(n/2), and the norm to 1e-12."""
+    torch = need_gpu()
+    n = 30
+    m = inst.m_from_density(n, 4.2)
+    lits = rand_lits(n, m, 30)
+    cost, _ = g.gqaoa_cost_table(n, lits, with_hist=False)
+    gamma = np.array([0.83, 1.57])
+    log(f"x-qaoa n={n} complex128 closed form")
+    psi, _, _, norm = g.gqaoa_evolve_x(n, m, cost, [np.pi / 2] * 2, gamma, dtype=g.C128)
+    rng = np.random.Generator(np.random.PCG64(30))
+    z = rng.integers(0, 2 ** n, size=4096, dtype=np.int64)
+    zbar = (2 ** n - 1) ^ z
+    ref = (-1) ** n * np.exp(-1j * (gamma[0] * cost_of(z, lits) + gamma[1] * cost_of(zbar, lits)))
+    got = psi[torch.tensor(z, device="cuda")].cpu().numpy() * 2 ** (n / 2)
+    assert np.abs(got - ref).max() < 1e-12
+    assert np.abs(norm - 1).max() < 1e-12
+    del psi, cost
+    torch.cuda.empty_cache()
