@@ -995,7 +995,11 @@ static int fold_for_finalize(const FwdPlan &P, const double *rows, const double 
 static int launch_finalize(const FwdPlan &P, FinArgs f, hipStream_t st) {
     int s = fold_for_finalize<kFwdR>(P, f.partials, &f.partials, &f.nblocks, st);
     if (s) return s;
+    // the smallest block that holds one row per thread (the rows past
+    // nblocks add zeros in a larger one, so the sums are the same bits)
     if (f.nblocks <= kFinWave) hipLaunchKernelGGL(sv_finalize_kernel<kFinWave>, dim3(P.num_inst), dim3(kFinWave), 0, st, f);
+    else if (f.nblocks <= 2 * kFinWave)
+        hipLaunchKernelGGL(sv_finalize_kernel<2 * kFinWave>, dim3(P.num_inst), dim3(2 * kFinWave), 0, st, f);
     else hipLaunchKernelGGL(sv_finalize_kernel<kFinThreads>, dim3(P.num_inst), dim3(kFinThreads), 0, st, f);
     GQ_LAUNCH_CHECK();
     return GQAOA_OK;
