@@ -1,12 +1,13 @@
-"""GPU parity of the batched scan on instances with 41..128 occupied levels,
-the register-array sizes above 40 (buckets 48, 56, 64, 80, 96, 112, 128) that
-random 3-SAT instances of the scan workload (n <= 20) do not reach but
-unsatisfiable paper-scale sets (m up to 208) do. Histograms are synthetic (K
-occupied levels out of 0..m, counts summing to 2^n; the level-space method
-does not care which formula produced them), fed straight into
-gqaoa_scan_batched and gqaoa_scan_crossing and compared with the oracle's
-level-space evolution (float64) at the single-precision bar: 1e-5 on P_sol and
-1e-5 * m on E."""
+"""GPU parity of the batched scan on every register-array size of the scan
+kernel: "narrow", 1..40 occupied levels, every even size from 4 to 36 and 40,
+with K at a size and just below it; "wide", 41..128 levels, the sizes above
+40 (48, 56, 64, 80, 96, 112, 128) that random 3-SAT instances of the scan
+workload (n <= 20) do not reach but unsatisfiable paper-scale sets (m up to
+208) do. Histograms are synthetic (K occupied levels out of 0..m, counts
+summing to 2^n; the level-space method does not care which formula produced
+them), fed straight into gqaoa_scan_batched and gqaoa_scan_crossing and
+compared with the oracle's level-space evolution (float64) at the
+single-precision bar: 1e-5 on P_sol and 1e-5 * m on E."""
 import numpy as np
 import pytest
 
@@ -18,24 +19,30 @@ from paper_2402_02585_amd import optim
 
 pytestmark = pytest.mark.gpu
 
-KS = [41, 47, 48, 49, 56, 63, 64, 65, 79, 80, 81, 96, 100, 112, 127, 128]
-M, N = 200, 30
+# (levels per instance, m, n) of each set
+SETS = {
+    "narrow": ([1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 13, 15, 17, 19, 20, 21, 23, 25, 27, 29, 31, 33, 35, 36, 37, 39, 40],
+               60, 20),
+    "wide": ([41, 47, 48, 49, 56, 63, 64, 65, 79, 80, 81, 96, 100, 112, 127, 128], 200, 30),
+}
 P_LIST = [1, 4, 16, 64]
 
 
-def _inputs(seed):
+def _inputs(name, seed):
+    KS, M, N = SETS[name]
     H = np.stack([synthetic_hist(K, M, N, seed + K) for K in KS])
     rng = np.random.Generator(np.random.PCG64(seed))
     targets = np.zeros(len(KS), dtype=np.int32)
     for i in range(1, len(KS), 3):        # every third instance targets another occupied level
         targets[i] = int(rng.choice(np.nonzero(H[i])[0]))
-    return H, targets
+    return KS, M, N, H, targets
 
 
+@pytest.mark.parametrize("name", list(SETS))
 @pytest.mark.parametrize("tile", [None, [1, 4], [4, 2]])
-def test_scan_wide_buckets_match_oracle(tile):
+def test_scan_buckets_match_oracle(tile, name):
     need_gpu()
-    H, targets = _inputs(900)
+    KS, M, N, H, targets = _inputs(name, 900)
     ns, ms = [N] * len(KS), [M] * len(KS)
     gb, gg = optim.fundamental_grid(64, 5)
     log(f"scan K={KS[0]}..{KS[-1]} tile={tile}")
@@ -55,9 +62,10 @@ def test_scan_wide_buckets_match_oracle(tile):
     log(f"worst |dP| {worst:.2e}")
 
 
-def test_crossing_wide_buckets_match_oracle():
+@pytest.mark.parametrize("name", list(SETS))
+def test_crossing_buckets_match_oracle(name):
     need_gpu()
-    H, targets = _inputs(910)
+    KS, M, N, H, targets = _inputs(name, 910)
     ns, ms = [N] * len(KS), [M] * len(KS)
     gb, gg = optim.fundamental_grid(16, 6)
     S, p_max, margin = 0.05, 64, 1e-4
