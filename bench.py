@@ -86,15 +86,6 @@ def read_traffic():
     return None if d is None else d.get("hbm_bytes_per_launch")
 
 
-def scan_padded_levels(levels):
-    """The register-array size the scan library runs an instance with K
-    occupied levels at: the next even size from 4 to 36, multiple of 4 up to
-    64, multiple of 16 up to 128 (its kernel instantiations)."""
-    k = np.maximum(levels, 1)
-    return np.where(k <= 36, np.maximum(4, np.ceil(k / 2) * 2),
-                    np.where(k <= 64, np.ceil(k / 4) * 4, np.ceil(k / 16) * 16))
-
-
 def read_scan_counters():
     """Issued VALU lane-operations per scan replay (counters), or None."""
     d = profile_json("scan_c3_counters_and_trace.md", "hist.hip", "batch.h", "internal.h")
@@ -409,7 +400,7 @@ def batched_leg(torch, g, inst, steps: int):
     # phase multiply (6 flops), the weighted sum for the mixer (4) and the
     # mixer update (2), issued as 8 two-operand VALU instructions
     levels = (hists > 0).sum(axis=1).astype(np.float64)
-    padded = scan_padded_levels(levels)
+    padded = np.ceil(levels / 4) * 4
     scan_flops = float(levels.sum()) * 64 * 64 * plist[-1] * 12
     ops_alg = float(levels.sum()) * 64 * 64 * plist[-1] * 8
     ops_pad = float(padded.sum()) * 64 * 64 * plist[-1] * 8

@@ -401,12 +401,10 @@ __global__ void zero_counters_kernel(unsigned int *c, int n) {
     if (i < n) c[i] = 0u;
 }
 
-// Register-array sizes of the scan kernel instantiations: every even size
-// from 4 to 36 (the register-held tables; an instance pays for at most one
-// padding level, which carries weight 0), every multiple of 4 up to 64, then
-// steps of 16.
-static const int kBuckets[] = {4,  6,  8,  10, 12, 14, 16, 18, 20, 22, 24, 26, 28, 30,
-                               32, 34, 36, 40, 44, 48, 52, 56, 60, 64, 80, 96, 112, 128};
+// Register-array sizes of the scan kernel instantiations: every multiple of
+// 4 up to 64 (an instance pays for at most 3 padding levels, which carry
+// weight 0), then steps of 16.
+static const int kBuckets[] = {4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 52, 56, 60, 64, 80, 96, 112, 128};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
 constexpr int kScanMaxK = 128;
 
@@ -419,9 +417,8 @@ static ScanFn scan_fn_pick(int kmax, std::integer_sequence<int, KS...>) {
 }
 template <bool CROSS>
 static ScanFn scan_fn_t(int bucket) {
-    return scan_fn_pick<CROSS>(kBuckets[bucket], std::integer_sequence<int, 4, 6, 8, 10, 12, 14, 16, 18, 20, 22, 24, 26, 28, 30,
-                                                                       32, 34, 36, 40, 44, 48, 52, 56, 60, 64, 80, 96, 112,
-                                                                       128>{});
+    return scan_fn_pick<CROSS>(kBuckets[bucket], std::integer_sequence<int, 4, 8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48,
+                                                                       52, 56, 60, 64, 80, 96, 112, 128>{});
 }
 static ScanFn scan_fn(int bucket, bool cross) { return cross ? scan_fn_t<true>(bucket) : scan_fn_t<false>(bucket); }
 

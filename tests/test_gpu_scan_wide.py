@@ -1,9 +1,9 @@
 """GPU parity of the batched scan on every register-array size of the scan
-kernel: "narrow", 1..40 occupied levels, every even size from 4 to 36 and 40,
-with K at a size and just below it; "wide", 41..128 levels, the sizes above
-40 (48, 56, 64, 80, 96, 112, 128) that random 3-SAT instances of the scan
-workload (n <= 20) do not reach but unsatisfiable paper-scale sets (m up to
-208) do. Histograms are synthetic (K occupied levels out of 0..m, counts
+kernel: "narrow", 1..40 occupied levels, every size from 4 to 40 (multiples
+of 4) with K at a size and next to it; "wide", 41..128 levels, the sizes
+above 40 (48, 56, 64, 80, 96, 112, 128) that random 3-SAT instances of the
+scan workload (n <= 20) do not reach but unsatisfiable paper-scale sets (m
+up to 208) do. Histograms are synthetic (K occupied levels out of 0..m, counts
 summing to 2^n; the level-space method does not care which formula produced
 them), fed straight into gqaoa_scan_batched and gqaoa_scan_crossing and
 compared with the oracle's level-space evolution (float64) at the
