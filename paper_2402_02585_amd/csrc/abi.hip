@@ -8,6 +8,7 @@
 
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 namespace gqaoa {
@@ -190,6 +191,37 @@ int device_info(DeviceInfo *out) {
     g_devs.push_back(d);
     *out = d;
     return GQAOA_OK;
+}
+
+// ---- streams lent to graph captures ---------------------------------------------------------
+static std::mutex g_pool_mu;
+static std::vector<std::pair<int, hipStream_t>> g_pool;  // (device, stream), free for the taking
+
+int stream_pool_take(size_t n, std::vector<hipStream_t> *out) {
+    int dev = -1;
+    GQ_HIP(hipGetDevice(&dev));
+    size_t got = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (size_t i = g_pool.size(); i-- > 0 && got < n;)
+            if (g_pool[i].first == dev) {
+                out->push_back(g_pool[i].second);
+                g_pool.erase(g_pool.begin() + (ptrdiff_t)i);
+                ++got;
+            }
+    }
+    for (; got < n; ++got) {
+        hipStream_t s = nullptr;
+        GQ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        out->push_back(s);
+    }
+    return GQAOA_OK;
+}
+
+void stream_pool_give(int device, const std::vector<hipStream_t> &streams) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (hipStream_t s : streams)
+        if (s) g_pool.emplace_back(device, s);
 }
 
 // ---- validation helpers ------------------------------------------------------------------

@@ -58,14 +58,22 @@ static void fill_items(ScanPlan *P) {
 static void release(ScanPlan *P) {
     if (!P) return;
     if (P->done) (void)hipEventSynchronize(P->done);
-    if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->fork) (void)hipEventDestroy(P->fork);
     for (hipEvent_t e : P->join) (void)hipEventDestroy(e);
     if (P->staged) (void)hipEventDestroy(P->staged);
     if (P->done) (void)hipEventDestroy(P->done);
-    if (P->cap) (void)hipStreamDestroy(P->cap);
-    for (hipStream_t b : P->branch) (void)hipStreamDestroy(b);
+    // the capture and branch streams go back to the pool once the plan was
+    // instantiated (every capture on them has ended); a plan that failed
+    // half-way destroys them
+    std::vector<hipStream_t> ss(P->branch);
+    if (P->cap) ss.push_back(P->cap);
+    if (P->exec) {
+        stream_pool_give(P->device, ss);
+    } else {
+        for (hipStream_t x : ss) (void)hipStreamDestroy(x);
+    }
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->dev) (void)hipFree(P->dev);
     if (P->stage) (void)hipHostFree(P->stage);
     delete P;
@@ -168,7 +176,12 @@ int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host,
     GQ_HIP(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
     GQ_HIP(hipEventCreateWithFlags(&P->staged, hipEventDisableTiming));
     GQ_HIP(hipEventCreateWithFlags(&P->done, hipEventDisableTiming));
-    GQ_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    {
+        std::vector<hipStream_t> c;
+        const int sc = stream_pool_take(1, &c);
+        if (!c.empty()) P->cap = c[0];
+        if (sc) return sc;
+    }
 
     // static tables and the first grid
     std::memcpy(P->stage + P->off_b, betas, 8 * P->n_b);
@@ -236,11 +249,9 @@ int scan_plan_create(int num_inst, const int32_t *n_host, const int32_t *m_host,
     }
     GQ_HIP(hipStreamSynchronize(st));  // uploads and tuning done; host tables end here
     const size_t nbranch = bucket_args.size() + item_args.size();
+    if ((s = stream_pool_take(nbranch, &P->branch))) return s;
     for (size_t q = 0; q < nbranch; ++q) {
-        hipStream_t b = nullptr;
         hipEvent_t e = nullptr;
-        GQ_HIP(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
-        P->branch.push_back(b);
         GQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         P->join.push_back(e);
     }

@@ -1324,7 +1324,12 @@ void evolve_plan_destroy(EvolvePlan *E) {
     if (!E) return;
     if (E->exec) (void)hipGraphExecDestroy(E->exec);
     if (E->graph) (void)hipGraphDestroy(E->graph);
-    if (E->cap) (void)hipStreamDestroy(E->cap);
+    if (E->cap) {
+        // back to the pool once the graph was instantiated (its capture has
+        // ended); destroyed after a failed creation
+        if (E->exec) stream_pool_give(E->device, {E->cap});
+        else (void)hipStreamDestroy(E->cap);
+    }
     if (E->stage) (void)hipHostFree(E->stage);
     delete E;
 }
@@ -1388,7 +1393,12 @@ int evolve_plan_create(int n, int m, const uint8_t *cost, int p, int dtype, int 
     P.shape = pass_shape(P.N, 1, dtype, dev);
     GQ_HIP(hipHostMalloc(reinterpret_cast<void **>(&E->stage), sizeof(double) * (2 * (size_t)p + 3 * ((size_t)p + 1)),
                          hipHostMallocDefault));
-    GQ_HIP(hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking));
+    {
+        std::vector<hipStream_t> c;
+        s = stream_pool_take(1, &c);
+        if (!c.empty()) E->cap = c[0];
+        if (s) return s;
+    }
     const int32_t tg = target;
     GQ_HIP(hipMemcpyAsync(P.ws + P.L.target, &tg, 4, hipMemcpyHostToDevice, st));
     GQ_HIP(hipStreamSynchronize(st));  // tg ends here; the captured work reads the target from the workspace
