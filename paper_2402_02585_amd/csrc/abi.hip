@@ -2,6 +2,7 @@
 // and dispatch to the kernel launchers. Every check runs before the first HIP
 // call, so an invalid call returns without touching the device.
 #include "internal.h"
+#include "stream_pool.h"
 #include "tune_cache.h"
 
 #include <cmath>

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "stream_pool.h"
 
 namespace gqaoa {
 

@@ -21,6 +21,7 @@
 // All kernels take an instance index in blockIdx.y so that many equally
 // sized instances stream in one launch.
 #include "internal.h"
+#include "stream_pool.h"
 
 #include <algorithm>
 #include <cmath>
