@@ -162,9 +162,15 @@ def solve(model, hists_dev, ns, ms, hists, p: int, median_pair, plain_grid=None,
     I = len(ns)
     x = features_for(hists_dev, ns, ms, p)
     bl, gl = model.angles(x)
-    p_learn = evaluate_pairs(ns, ms, hists, bl, gl, p)
+    # the network's pair and the cluster-median pair in one scan: a 2 x 2 grid
+    # per instance whose diagonal holds the two pairs (every cell is computed
+    # on its own, so the values are those of two separate scans)
+    b2 = np.stack([np.asarray(bl, dtype=np.float64), np.full(I, float(median_pair[0]))], axis=1)
+    g2 = np.stack([np.asarray(gl, dtype=np.float64), np.full(I, float(median_pair[1]))], axis=1)
+    ps2, _ = g.gqaoa_scan_batched(ns, ms, hists, b2, g2, [p], with_energy=False)
+    ps2 = ps2.cpu().numpy().astype(np.float64)
+    p_learn, p_med = ps2[:, 0, 0, 0], ps2[:, 0, 1, 1]
     b, gm, ps = refine_local(ns, ms, hists, bl, gl, p, start_psol=p_learn)
-    p_med = evaluate_pairs(ns, ms, hists, np.full(I, median_pair[0]), np.full(I, median_pair[1]), p)
     fb = ps < fallback_ratio * p_med
     if fb.any():
         gb, gg = optim.fundamental_grid(*(plain_grid or optim.paper_grid()))
