@@ -32,7 +32,9 @@
  *    `stream`, freed on it after their last launch; clause records, round
  *    tables and block rows, a few MiB at most); gqaoa_cost_table_noalloc is
  *    the form of gqaoa_cost_table that allocates nothing. Plans allocate
- *    their device tables at create and free them at destroy.
+ *    their device tables at create and free them at destroy; the streams a
+ *    plan captures its graph on are borrowed from a per-device pool that the
+ *    library keeps until the process ends (no device memory).
  */
 #ifndef GQAOA_H
 #define GQAOA_H
