@@ -823,7 +823,7 @@ def rounds_leg(torch, g, inst):
     H = g.gqaoa_hist_batched(ns, ms, [x.lits for x in its], hist_stride=int(ms.max()) + 1).cpu().numpy()
     P = H[:, 0] / np.exp2(ns)
     caps = np.clip(np.ceil(3.0 / np.sqrt(P)), 8, 100000).astype(np.int32)
-    rounds.single_pair_rounds(ns[:8], ms[:8], H[:8], 0.5, caps[:8])   # warm-up (autotuning)
+    rounds.single_pair_rounds(ns, ms, H, 0.5, caps)   # warm-up: the scan autotuner sees every bucket the timed call uses
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     p_star, _, _ = rounds.single_pair_rounds(ns, ms, H, 0.5, caps)
